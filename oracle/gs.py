@@ -1,0 +1,214 @@
+"""Plain FP64 CPU oracle for the method of alternating projections
+(Gerchberg-Saxton) that computes a phase-only SLM mask.
+
+TEST INFRASTRUCTURE ONLY.  This module is the checker, not the product: only
+the test suite, the smoke check and the CPU-baseline leg of the benchmark may
+import it.  It shares no code with the device library and imports nothing
+from it.  Everything here is slow on purpose: float64/complex128 NumPy, no
+blocking, no fusion, steps in the paper's order and notation.
+
+Notation (Sec. II of the paper)
+-------------------------------
+* ``u`` in C^N is the field on the SLM, N = n_x * n_y, stored row-major as a
+  ``[n_y][n_x]`` array (rows = y, columns = x).
+* ``p`` >= 0 is the illumination amplitude on the SLM (Eq. 1).  The device
+  path is phase-only, p = 1; the functions here accept a general p.
+* ``m`` >= 0 is the target amplitude of the optical stimulation pattern
+  (Eq. 2), in natural DFT order (zero frequency at ``[0][0]``).
+* ``F`` is the 2-D discrete Fourier transform, taken unitary here (forward
+  kernel exp(-2 pi i (k_y y / n_y + k_x x / n_x)) / sqrt(N)) so that the
+  projections of Eq. 4 are nearest-point maps in the Euclidean norm
+  (Sec. II: a projection maps a point to its nearest points).
+
+Readings where the paper is silent (each also listed in the design notes):
+* Scale of m.  The iterates do not depend on any positive scale of m (P_M
+  keeps only the phase of Fu, P_S divides every modulus out), so the oracle
+  works with the energy-matched target  m~ = m * ||p|| / ||m||  (Parseval:
+  ||F u|| = ||u|| = ||p|| for u in S).  Error norms are reported relative to
+  ||p||.
+* Zero tie-break of Eq. 4a and Eq. 5.  The set-valued branch (u = 0) takes
+  theta = 0, and "zero" means |z|^2 below the smallest normal float64.
+* Gap, Eq. 7.  For u in S the printed formula ||P_S u - P_M u|| equals
+  ||u - P_M u|| = d(u, M), reported here as the Fourier-plane error E_F.
+  The sentence after Eq. 7 (accumulation points in M and their projections
+  onto S) is d(P_M u, S), reported as the gap G.  Both are relative to ||p||.
+* Iteration count.  ``n_iter`` applications of P_S P_M (Eq. 6) starting from
+  u^0 = p exp(i phi0); the returned mask is u^n.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "DBL_MIN",
+    "F",
+    "F_inv",
+    "matched_target",
+    "P_S",
+    "M_hat",
+    "P_M",
+    "fourier_error",
+    "gap",
+    "mask_errors",
+    "gs_solve",
+    "physical_error",
+    "intensity_loss",
+    "intensity_loss_grad",
+]
+
+DBL_MIN = np.finfo(np.float64).tiny
+
+
+def F(u: np.ndarray) -> np.ndarray:
+    """Unitary 2-D DFT over the last two axes (rows = y, columns = x).
+
+    Models Fraunhofer propagation from the SLM to the specimen (Sec. II,
+    the sentence before Eq. 2)."""
+    return np.fft.fft2(np.asarray(u, dtype=np.complex128), axes=(-2, -1), norm="ortho")
+
+
+def F_inv(v: np.ndarray) -> np.ndarray:
+    """Inverse of the unitary 2-D DFT (also its adjoint)."""
+    return np.fft.ifft2(np.asarray(v, dtype=np.complex128), axes=(-2, -1), norm="ortho")
+
+
+def matched_target(m: np.ndarray, p: np.ndarray | None = None) -> np.ndarray:
+    """Energy-matched target m~ = m ||p|| / ||m|| (float64)."""
+    m = np.asarray(m, dtype=np.float64)
+    n = m.shape[-2] * m.shape[-1]
+    p_norm = np.sqrt(n) if p is None else np.linalg.norm(np.asarray(p, dtype=np.float64))
+    return m * (p_norm / np.linalg.norm(m))
+
+
+def _phase_of(z: np.ndarray) -> np.ndarray:
+    """z / |z| where |z|^2 >= DBL_MIN, else exp(i 0) = 1 (tie-break theta = 0)."""
+    a2 = z.real * z.real + z.imag * z.imag
+    nz = a2 >= DBL_MIN
+    out = np.ones_like(z)
+    out[nz] = z[nz] / np.sqrt(a2[nz])
+    return out
+
+
+def P_S(u: np.ndarray, p: np.ndarray | None = None) -> np.ndarray:
+    """Projection onto S, Eq. 4a: every pixel keeps its phase and takes
+    modulus p (p = 1 if omitted); a zero pixel takes p exp(i 0)."""
+    ph = _phase_of(np.asarray(u, dtype=np.complex128))
+    return ph if p is None else np.asarray(p, dtype=np.float64) * ph
+
+
+def M_hat(Fu: np.ndarray, m: np.ndarray) -> np.ndarray:
+    """Fourier-plane amplitude adaption, Eq. 5: every coefficient keeps its
+    phase and takes modulus m; a zero coefficient takes m exp(i 0)."""
+    return np.asarray(m, dtype=np.float64) * _phase_of(np.asarray(Fu, dtype=np.complex128))
+
+
+def P_M(u: np.ndarray, m: np.ndarray) -> np.ndarray:
+    """Projection onto M, Eq. 4b: F^{-1} of M_hat(F u)."""
+    return F_inv(M_hat(F(u), m))
+
+
+def fourier_error(u: np.ndarray, m: np.ndarray) -> float:
+    """E_F = || |F u| - m~ || / ||p||  (p = 1, so ||p|| = sqrt N).
+
+    For u in S this is d(u, M) / ||p|| (Parseval), the literal Eq. 7."""
+    u = np.asarray(u, dtype=np.complex128)
+    n = u.shape[-2] * u.shape[-1]
+    mt = matched_target(m)
+    return float(np.linalg.norm(np.abs(F(u)) - mt) / np.sqrt(n))
+
+
+def gap(v: np.ndarray) -> float:
+    """G = d(v, S) / ||p|| = || |v| - 1 || / sqrt N for a point v of M
+    (the prose reading of Eq. 7, p = 1)."""
+    v = np.asarray(v, dtype=np.complex128)
+    n = v.shape[-2] * v.shape[-1]
+    return float(np.linalg.norm(np.abs(v) - 1.0) / np.sqrt(n))
+
+
+def mask_errors(m: np.ndarray, phi: np.ndarray) -> tuple[float, float]:
+    """(E_F, G) of the phase-only mask u = exp(i phi) against target m."""
+    u = np.exp(1j * np.asarray(phi, dtype=np.float64))
+    mt = matched_target(m)
+    return fourier_error(u, m), gap(P_M(u, mt))
+
+
+def gs_solve(m: np.ndarray, phi0: np.ndarray, n_iter: int) -> dict:
+    """Method of alternating projections, Eq. 6, with p = 1.
+
+    u^0 = exp(i phi0); for nu = 0 .. n_iter-1:
+        U      = F u^nu                          (Eq. 2 / Eq. 4b)
+        E_F^nu = || |U| - m~ || / sqrt N          (error before projecting)
+        V      = M_hat(U)                         (Eq. 5)
+        w      = F^{-1} V  = P_M u^nu             (Eq. 4b)
+        G^nu   = || |w| - 1 || / sqrt N           (Eq. 7, prose reading)
+        u^{nu+1} = P_S w                          (Eq. 4a)
+    and finally E_F^n of the returned mask.
+
+    Returns a dict with the field ``u`` (= u^n), the phase ``phi`` =
+    angle(u^n) in (-pi, pi], and ``history`` = [E_F^0, G^0, ..., E_F^{n-1},
+    G^{n-1}, E_F^n] (length 2 n_iter + 1).
+    """
+    if n_iter < 0:
+        raise ValueError("n_iter must be >= 0")
+    m = np.asarray(m, dtype=np.float64)
+    phi0 = np.asarray(phi0, dtype=np.float64)
+    if m.shape != phi0.shape or m.ndim != 2:
+        raise ValueError("target and phase must be 2-D arrays of one shape")
+    n = m.size
+    mt = matched_target(m)
+    u = np.exp(1j * phi0)
+    hist = []
+    for _ in range(n_iter):
+        U = F(u)
+        hist.append(float(np.linalg.norm(np.abs(U) - mt) / np.sqrt(n)))
+        w = F_inv(M_hat(U, mt))
+        hist.append(float(np.linalg.norm(np.abs(w) - 1.0) / np.sqrt(n)))
+        u = P_S(w)
+    hist.append(float(np.linalg.norm(np.abs(F(u)) - mt) / np.sqrt(n)))
+    return {"u": u, "phi": np.angle(u), "history": np.array(hist)}
+
+
+def physical_error(m: np.ndarray, u: np.ndarray, t_l: float = 0.1,
+                   t_d: float = 3e-4) -> tuple[float, float]:
+    """Physical error of Eq. 8a/8b: (E_lit, E_dark).
+
+    Reading (the paper calls both u and m intensities here, leaves their
+    scale and the lit/dark split unstated): target intensity I_t = m~^2 and
+    reconstructed intensity I_r = |F u|^2, each divided by its own maximum;
+    a pixel is lit when I_t > t_d, dark otherwise; the sums are as printed.
+    Tolerances t_l = 0.1 (relative, lit) and t_d = 3e-4 (absolute, dark)
+    are the paper's (Sec. II, last paragraph).
+    """
+    it = matched_target(m) ** 2
+    ir = np.abs(F(u)) ** 2
+    it = it / it.max()
+    ir = ir / ir.max()
+    lit = it > t_d
+    rel = np.abs(it[lit] - ir[lit]) / it[lit]
+    e_lit = float(np.sum((t_d * rel / t_l - t_d) * (rel - t_l > 0)))
+    d = ir[~lit]
+    e_dark = float(np.sum((d - t_d) * (d - t_d > 0)))
+    return e_lit, e_dark
+
+
+def intensity_loss(phi: np.ndarray, target_intensity: np.ndarray) -> float:
+    """L(phi) = sum_k ( |(F exp(i phi))_k|^2 - I_k )^2 with unitary F.
+
+    Not in the paper: the gradient-based alternative that sits beside the
+    projection method.  The caller chooses the scale of I (sum I = N matches
+    the energy of a phase-only field)."""
+    U = F(np.exp(1j * np.asarray(phi, dtype=np.float64)))
+    r = np.abs(U) ** 2 - np.asarray(target_intensity, dtype=np.float64)
+    return float(np.sum(r * r))
+
+
+def intensity_loss_grad(phi: np.ndarray, target_intensity: np.ndarray) -> np.ndarray:
+    """dL/dphi_j = 4 Im( exp(-i phi_j) (F^H (r . U))_j ),  r = |U|^2 - I.
+
+    Chain rule: d|U_k|^2/dphi_j = 2 Re( conj(U_k) F_kj i u_j ), summed with
+    the weight 2 r_k over k; F^H = F^{-1} for the unitary transform."""
+    u = np.exp(1j * np.asarray(phi, dtype=np.float64))
+    U = F(u)
+    r = np.abs(U) ** 2 - np.asarray(target_intensity, dtype=np.float64)
+    g = F_inv(r * U)
+    return 4.0 * np.imag(np.conj(u) * g)

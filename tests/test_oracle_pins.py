@@ -1,0 +1,342 @@
+"""Pins for the FP64 oracle: each test checks the oracle against something
+other than itself -- a brute-force transform, a closed form, a theorem about
+projections, an invariance of the method, or finite differences -- so that a
+dropped term, a wrong sign or index, or a transposed operand fails one of
+them.  CPU only."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import gs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# The transform F (Eq. 2, Eq. 4b): brute force and closed forms
+# --------------------------------------------------------------------------
+
+def _brute_dft2(u, sign):
+    """Textbook O(N^2) 2-D DFT from its defining double sum, unitary scale."""
+    h, w = u.shape
+    out = np.zeros((h, w), dtype=np.complex128)
+    ys = np.arange(h)[:, None]
+    xs = np.arange(w)[None, :]
+    for ky in range(h):
+        for kx in range(w):
+            ph = sign * 2.0 * math.pi * (ky * ys / h + kx * xs / w)
+            out[ky, kx] = np.sum(u * (np.cos(ph) + 1j * np.sin(ph)))
+    return out / math.sqrt(h * w)
+
+
+@pytest.mark.parametrize("shape", [(16, 16), (8, 16), (16, 8)])
+def test_dft_matches_brute_force(shape):
+    rng = np.random.default_rng(7)
+    u = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    tol = 1e-12 * np.linalg.norm(u)
+    assert np.max(np.abs(gs.F(u) - _brute_dft2(u, -1.0))) <= tol
+    assert np.max(np.abs(gs.F_inv(u) - _brute_dft2(u, +1.0))) <= tol
+
+
+@pytest.mark.parametrize("shape", [(8, 16), (16, 8), (32, 32)])
+def test_dft_closed_forms(shape):
+    h, w = shape
+    n = h * w
+    # delta at the origin -> constant 1/sqrt(N)
+    d = np.zeros(shape, complex)
+    d[0, 0] = 1.0
+    assert np.allclose(gs.F(d), np.full(shape, 1 / math.sqrt(n)), atol=1e-15, rtol=0)
+    # constant -> sqrt(N) delta
+    c = np.ones(shape, complex)
+    e = np.zeros(shape, complex)
+    e[0, 0] = math.sqrt(n)
+    assert np.max(np.abs(gs.F(c) - e)) <= 1e-13
+    # plane wave exp(+2 pi i (a y/h + b x/w)) -> sqrt(N) delta at (a, b):
+    # pins the forward sign and which axis is rows
+    a, b = 3, 5
+    ys = np.arange(h)[:, None]
+    xs = np.arange(w)[None, :]
+    pw = np.exp(2j * math.pi * (a * ys / h + b * xs / w))
+    e = np.zeros(shape, complex)
+    e[a, b] = math.sqrt(n)
+    assert np.max(np.abs(gs.F(pw) - e)) <= 1e-12
+
+
+def test_parseval_and_inverse():
+    rng = np.random.default_rng(8)
+    u = rng.standard_normal((32, 64)) + 1j * rng.standard_normal((32, 64))
+    U = gs.F(u)
+    assert abs(np.linalg.norm(U) - np.linalg.norm(u)) <= 1e-13 * np.linalg.norm(u)
+    assert np.max(np.abs(gs.F_inv(U) - u)) <= 1e-13 * np.linalg.norm(u)
+
+
+# --------------------------------------------------------------------------
+# Projections P_S (Eq. 4a) and P_M (Eq. 4b, Eq. 5)
+# --------------------------------------------------------------------------
+
+def test_PS_modulus_phase_idempotent():
+    rng = np.random.default_rng(9)
+    u = rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))
+    v = gs.P_S(u)
+    assert np.max(np.abs(np.abs(v) - 1.0)) <= 1e-15
+    assert np.max(np.abs(np.angle(v) - np.angle(u))) <= 1e-15
+    assert np.max(np.abs(gs.P_S(v) - v)) <= 1e-15
+    p = rng.uniform(0.5, 2.0, (8, 8))
+    vp = gs.P_S(u, p)
+    assert np.max(np.abs(np.abs(vp) - p)) <= 1e-15
+
+
+def test_PS_is_nearest_point_brute_force():
+    """No random point of S on a 4x4 grid is closer to u than P_S u."""
+    rng = np.random.default_rng(10)
+    u = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    d0 = np.linalg.norm(u - gs.P_S(u))
+    thetas = rng.uniform(0, 2 * math.pi, (10000, 4, 4))
+    d = np.linalg.norm((u[None] - np.exp(1j * thetas)).reshape(10000, -1), axis=1)
+    assert d0 < d.min()
+
+
+def test_PS_zero_tie_break():
+    u = np.zeros((4, 4), complex)
+    u[1, 2] = 3 - 4j
+    v = gs.P_S(u)
+    assert v[0, 0] == 1.0 and v[3, 3] == 1.0
+    assert abs(v[1, 2] - (0.6 - 0.8j)) <= 1e-15
+
+
+def test_PM_lands_in_M_and_is_idempotent():
+    rng = np.random.default_rng(11)
+    m = rng.uniform(0, 1, (16, 32))
+    mt = gs.matched_target(m)
+    u = rng.standard_normal((16, 32)) + 1j * rng.standard_normal((16, 32))
+    v = gs.P_M(u, mt)
+    assert np.max(np.abs(np.abs(gs.F(v)) - mt)) <= 1e-12
+    assert np.max(np.abs(gs.P_M(v, mt) - v)) <= 1e-12
+    # energy matching: ||m~|| = sqrt(N) = ||p||
+    assert abs(np.linalg.norm(mt) - math.sqrt(m.size)) <= 1e-12
+
+
+def test_PM_is_nearest_point_brute_force():
+    """No random point of M (F^{-1} of m~ with random phases) beats P_M u."""
+    rng = np.random.default_rng(12)
+    m = rng.uniform(0, 1, (4, 4))
+    mt = gs.matched_target(m)
+    u = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    d0 = np.linalg.norm(u - gs.P_M(u, mt))
+    thetas = rng.uniform(0, 2 * math.pi, (10000, 4, 4))
+    cands = gs.F_inv(mt[None] * np.exp(1j * thetas))
+    d = np.linalg.norm((u[None] - cands).reshape(10000, -1), axis=1)
+    assert d0 < d.min()
+
+
+def test_constant_phase_tie_break():
+    """A constant field has exact zeros off DC, so Eq. 5 takes theta = 0 there:
+    V_k = m~_k for k != 0, and V_0 = m~_0 exp(i c)."""
+    c = 0.7
+    rng = np.random.default_rng(13)
+    m = rng.uniform(0.1, 1, (16, 16))
+    mt = gs.matched_target(m)
+    U = gs.F(np.full((16, 16), np.exp(1j * c)))
+    V = gs.M_hat(U, mt)
+    expect = mt.astype(complex)
+    expect[0, 0] = mt[0, 0] * np.exp(1j * c)
+    assert np.max(np.abs(V - expect)) <= 1e-15
+
+
+# --------------------------------------------------------------------------
+# The iteration (Eq. 6), its error norms (Eq. 7) and invariances
+# --------------------------------------------------------------------------
+
+def _spots(h, w, seed, k=5):
+    from paper_1302_0120_amd import synth
+    rng = np.random.default_rng(seed)
+    m = synth.spot_amplitude(h, w, k, 1.5, 1.0, 1.0, rng)
+    phi = synth.uniform_phase(h, w, rng)
+    return m, phi
+
+
+def test_history_equals_distances():
+    """E_F^nu = ||u^nu - P_M u^nu|| / sqrt N and G^nu = ||P_M u^nu - u^{nu+1}|| / sqrt N,
+    measured in the SLM plane (the oracle measures them in the Fourier plane)."""
+    m, phi = _spots(32, 64, 1)
+    n = m.size
+    mt = gs.matched_target(m)
+    res = gs.gs_solve(m, phi, 6)
+    h = res["history"]
+    u = np.exp(1j * phi.astype(np.float64))
+    for nu in range(6):
+        v = gs.P_M(u, mt)
+        u_next = gs.P_S(v)
+        assert abs(h[2 * nu] - np.linalg.norm(u - v) / math.sqrt(n)) <= 1e-12
+        assert abs(h[2 * nu + 1] - np.linalg.norm(v - u_next) / math.sqrt(n)) <= 1e-12
+        u = u_next
+    assert np.max(np.abs(u - res["u"])) <= 1e-12
+    assert abs(h[12] - np.linalg.norm(u - gs.P_M(u, mt)) / math.sqrt(n)) <= 1e-12
+
+
+def test_monotone_chain():
+    """For alternating projections d(u,M) >= d(P_M u, S) >= d(P_S P_M u, M) >= ...:
+    each step's distance is at most the previous one (nearest-point property)."""
+    m, phi = _spots(64, 64, 1)
+    h = gs.gs_solve(m, phi, 100)["history"]
+    assert np.all(np.diff(h) <= 1e-12)
+    assert h[-1] < h[0]
+
+
+def test_unnormalised_transforms_and_target_scale_give_same_iterates():
+    """The device path runs unnormalised FFTs with a rescaled target and never
+    divides by N; the iterates must not change."""
+    m, phi = _spots(32, 32, 2)
+    res = gs.gs_solve(m, phi, 10)
+    u = np.exp(1j * phi.astype(np.float64))
+    m_raw = 7.3 * m.astype(np.float64)
+    for _ in range(10):
+        U = np.fft.fft2(u)            # unnormalised forward
+        V = m_raw * U / np.abs(U)
+        w = np.fft.ifft2(V) * u.size  # unnormalised inverse
+        u = w / np.abs(w)
+    assert np.max(np.abs(u - res["u"])) <= 1e-12
+
+
+def test_equivariances():
+    m, phi = _spots(32, 32, 3)
+    phi = phi.astype(np.float64)
+    base = gs.gs_solve(m, phi, 8)
+    # global phase: u^nu -> u^nu exp(i a), same errors
+    a = 0.9
+    r = gs.gs_solve(m, phi + a, 8)
+    assert np.max(np.abs(r["u"] - base["u"] * np.exp(1j * a))) <= 1e-12
+    assert np.max(np.abs(r["history"] - base["history"])) <= 1e-12
+    # circular shift of the SLM field: |F u| unchanged, iterates shifted
+    r = gs.gs_solve(m, np.roll(phi, (5, -3), axis=(0, 1)), 8)
+    assert np.max(np.abs(r["u"] - np.roll(base["u"], (5, -3), axis=(0, 1)))) <= 1e-12
+    # twin: conj(u(-x)) has the conjugate spectrum, same modulus
+    twin = -np.roll(phi[::-1, ::-1], (1, 1), axis=(0, 1))
+    r = gs.gs_solve(m, twin, 8)
+    base_twin = np.conj(np.roll(base["u"][::-1, ::-1], (1, 1), axis=(0, 1)))
+    assert np.max(np.abs(r["u"] - base_twin)) <= 1e-12
+
+
+def _consistent(h, w, seed_true=31, seed_init=32):
+    rng = np.random.default_rng(seed_true)
+    phit = rng.uniform(0, 2 * math.pi, (h, w))
+    m = np.abs(np.fft.fft2(np.exp(1j * phit)))  # |F| of a known mask, any scale
+    return m, phit, np.random.default_rng(seed_init)
+
+
+def test_consistent_target_fixed_point():
+    """Started at a solution of S cap M the iteration stays there: E_F ~ 0."""
+    m, phit, _ = _consistent(64, 64)
+    h = gs.gs_solve(m, phit, 20)["history"]
+    assert h.max() <= 1e-13
+
+
+def test_consistent_target_local_convergence():
+    """Started near a solution the error falls monotonically towards 0."""
+    m, phit, rng = _consistent(64, 64)
+    phi0 = phit + rng.uniform(-0.3, 0.3, phit.shape)
+    h = gs.gs_solve(m, phi0, 100)["history"]
+    assert np.all(np.diff(h) <= 1e-12)
+    assert h[0] > 0.05 and h[-1] <= 5e-3
+
+
+def test_mask_errors_match_history():
+    m, phi = _spots(32, 32, 4)
+    res = gs.gs_solve(m, phi, 3)
+    ef, g = gs.mask_errors(m, phi)
+    assert abs(ef - res["history"][0]) <= 1e-14
+    assert abs(g - res["history"][1]) <= 1e-14
+    assert gs.gs_solve(m, phi, 0)["history"].shape == (1,)
+
+
+def test_output_phase_in_range_and_unit_modulus():
+    m, phi = _spots(32, 32, 5)
+    res = gs.gs_solve(m, phi, 5)
+    assert np.all(res["phi"] <= math.pi) and np.all(res["phi"] > -math.pi)
+    assert np.max(np.abs(np.abs(res["u"]) - 1.0)) <= 1e-15
+
+
+# --------------------------------------------------------------------------
+# Physical error, Eq. 8
+# --------------------------------------------------------------------------
+
+def _golden_tolerances():
+    vals = {}
+    with open(os.path.join(GOLDEN, "physical_error_tolerances.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                k, v = line.split()
+                vals[k] = float(v)
+    return vals
+
+
+def test_physical_error_closed_form():
+    """Target = one lit pixel at b; mask = plane wave lighting pixel a != b.
+    The lit pixel is fully off: E_lit = t_d / t_l - t_d.  The dark pixel a
+    carries normalised intensity 1: E_dark = 1 - t_d."""
+    tol = _golden_tolerances()
+    t_l, t_d = tol["t_lit"], tol["t_dark"]
+    h, w = 8, 16
+    a, b = (2, 3), (5, 1)
+    ys = np.arange(h)[:, None]
+    xs = np.arange(w)[None, :]
+    u = np.exp(2j * math.pi * (a[0] * ys / h + a[1] * xs / w))
+    m = np.zeros((h, w))
+    m[b] = 1.0
+    e_lit, e_dark = gs.physical_error(m, u, t_l, t_d)
+    assert abs(e_lit - (t_d / t_l - t_d)) <= 1e-15
+    assert abs(e_dark - (1.0 - t_d)) <= 1e-12
+    # consistent target: no violation at all
+    m2 = np.zeros((h, w))
+    m2[a] = 1.0
+    assert gs.physical_error(m2, u, t_l, t_d) == (0.0, 0.0)
+
+
+# --------------------------------------------------------------------------
+# Intensity-loss gradient (the differentiable form beside the projections)
+# --------------------------------------------------------------------------
+
+def test_intensity_gradient_vs_finite_differences():
+    rng = np.random.default_rng(5)
+    n = 64
+    phi = rng.uniform(0, 2 * math.pi, (n, n))
+    it = rng.uniform(0, 2, (n, n))
+    it *= (n * n) / it.sum()
+    g = gs.intensity_loss_grad(phi, it)
+    hstep = 1e-6
+    for _ in range(8):
+        j = tuple(rng.integers(0, n, 2))
+        pp = phi.copy()
+        pm = phi.copy()
+        pp[j] += hstep
+        pm[j] -= hstep
+        fd = (gs.intensity_loss(pp, it) - gs.intensity_loss(pm, it)) / (2 * hstep)
+        assert abs(fd - g[j]) <= 1e-6 * max(1.0, abs(g[j])) + 1e-6 * np.abs(g).max()
+
+
+def test_intensity_gradient_invariants():
+    rng = np.random.default_rng(6)
+    phi = rng.uniform(0, 2 * math.pi, (32, 32))
+    it = rng.uniform(0, 2, (32, 32))
+    g = gs.intensity_loss_grad(phi, it)
+    # global-phase invariance of L: the gradient sums to zero
+    assert abs(g.sum()) <= 1e-9 * np.abs(g).sum()
+    # at an exact solution (I = |F e^{i phi}|^2) the gradient vanishes
+    it_exact = np.abs(gs.F(np.exp(1j * phi))) ** 2
+    assert np.abs(gs.intensity_loss_grad(phi, it_exact)).max() <= 1e-12
+    assert gs.intensity_loss(phi, it_exact) <= 1e-24
+
+
+def test_stored_history_regression():
+    """The oracle still reproduces the stored history of the 64x64 spot case
+    (written by tests/golden/make_golden.py from the oracle itself): guards
+    against unintended drift of the checker."""
+    from paper_1302_0120_amd import synth
+    stored = np.loadtxt(os.path.join(GOLDEN, "gs_spots64_history.txt"))
+    m, phi0 = synth.spot_problem(synth.SPOTS_64)
+    h = gs.gs_solve(m, phi0, 100)["history"]
+    assert stored.shape == h.shape
+    assert np.max(np.abs(h - stored)) <= 1e-13
