@@ -1,0 +1,123 @@
+"""Benchmark: Gerchberg-Saxton phase masks on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+A step is one complete solve of the 1024 x 1024 spot workload (100 spots,
+sigma 2 px, amplitudes in [0.5, 1], uniform random initial phase, seed 3):
+target normalisation, u^0, 100 iterations of Eq. 6 (two fused passes each),
+the FP64 error history and the output phase, replayed from the captured
+graph with inputs resident in device memory.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GS iters/s & ms per 1024² mask (fp32, 100 it); batched masks/s vs plain GS"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# Algorithmic bytes per pixel of one launch (see the design notes):
+COL_BYTES_PER_PX = 8 + 8 + 4   # read iterate, write iterate, read rescaled target
+ROW_BYTES_PER_PX = 8 + 8       # read iterate, write iterate
+
+
+def cpu_baseline(m, phi0, n_iter_sample):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload."""
+    from oracle import gs
+    t0 = time.perf_counter()
+    gs.gs_solve(m, phi0, n_iter_sample)
+    dt = time.perf_counter() - t0
+    return n_iter_sample / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--cpu-iters", type=int, default=64,
+                    help="iterations of the FP64 oracle timed for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); masks are independent, "
+              "so more GPUs would each run their own share", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1302_0120_amd import binding, synth
+
+    spec = synth.SPOTS_1024
+    h, w, n_iter = spec.height, spec.width, spec.n_iter
+    npx = h * w
+    m, phi0 = synth.spot_problem(spec)
+    dev = torch.device("cuda", 0)
+    md = torch.from_numpy(m).to(dev)
+    pd = torch.from_numpy(phi0).to(dev)
+    plan = binding.PhaseMask(h, w, device=dev)
+    out = torch.empty((h, w), dtype=torch.float32, device=dev)
+    hist = torch.empty(2 * n_iter + 1, dtype=torch.float64, device=dev)
+
+    for _ in range(args.warmup):
+        plan.solve(md, pd, n_iter, out=out, history=hist)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.solve(md, pd, n_iter, out=out, history=hist)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
+    final_ef = float(hist[-1].item())
+
+    # Dominant kernel: average duration of each fused pass from the launches'
+    # own start/end events over an iteration sequence on the same stream.
+    col_ms, row_ms = plan.time_passes(md, pd, reps=args.kernel_reps)
+    if col_ms >= row_ms:
+        kname, kms, kbytes = "column pass", col_ms, COL_BYTES_PER_PX * npx
+    else:
+        kname, kms, kbytes = "row pass", row_ms, ROW_BYTES_PER_PX * npx
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    solve_gbs = (COL_BYTES_PER_PX + ROW_BYTES_PER_PX) * npx * n_iter / (ms_per_step * 1e-3) / 1e9
+
+    line = {
+        "metric": METRIC,
+        "value": n_iter * args.steps / dt,
+        "unit": "GS it/s (1024x1024 mask)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "ms_per_mask": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "gs_spots_1024x1024_100it", "height": h, "width": w,
+                   "n_iter": n_iter, "n_spots": spec.n_spots, "sigma_px": spec.sigma,
+                   "amplitude": [spec.amp_low, spec.amp_high], "seed": spec.seed,
+                   "history": "fp64 E_F/G per iteration", "launch": "hip graph"},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel_us": kms * 1e3, "bytes_per_launch": kbytes},
+        "passes_us": {"column": col_ms * 1e3, "row": row_ms * 1e3},
+        "solve_algorithmic_gbs": solve_gbs,
+        "final_fourier_error": final_ef,
+    }
+    if not args.no_cpu_baseline:
+        rate, cdt = cpu_baseline(m, phi0, args.cpu_iters)
+        line["cpu_baseline"] = {
+            "value": rate, "unit": "GS it/s (1024x1024 mask)", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 NumPy oracle, first {args.cpu_iters} of the {n_iter} iterations of "
+                      f"the same 1024x1024 spot workload, single thread, {cdt:.1f} s"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * phasemask.h -- C ABI of the MI355X (gfx950) phase-mask library.
+ *
+ * The library computes phase-only spatial-light-modulator (SLM) masks by the
+ * method of alternating projections (Gerchberg-Saxton), Kramer, Hagemann and
+ * Luke, "Real-Time Phase Masks for Interactive Stimulation of Optogenetic
+ * Neurons" (arXiv:1302.0120):
+ *
+ *   find u in S cap M                                  (Eq. 3)
+ *   S = { u : |u_jk| = p_jk },  here p = 1              (Eq. 1)
+ *   M = { u : |(F u)_jk| = m_jk }                       (Eq. 2)
+ *   u^{nu+1} = P_S P_M u^nu                              (Eq. 6)
+ *
+ * with P_S of Eq. 4a and P_M of Eq. 4b / Eq. 5.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Images are row-major [height][width] (height = n_y rows, width = n_x),
+ *    contiguous, with no padding between rows.
+ *  * The Fourier plane is in natural DFT order: zero frequency at [0][0];
+ *    forward kernel exp(-2 pi i (k_y y / height + k_x x / width)).
+ *  * Complex arrays are interleaved pairs of float (re, im), 8 bytes per
+ *    element.
+ *  * Sizes: height and width must each be a power of two in [16, 4096];
+ *    anything else returns PM_EUNSUPPORTED.
+ *  * All array arguments are DEVICE pointers owned by the caller, on the
+ *    device that was current when the handle was created, unless a comment
+ *    says otherwise.  The library never frees them.  Alignment: the target
+ *    amplitude 16 bytes, complex arrays and doubles 8 bytes, other floats
+ *    4 bytes; a misaligned pointer returns PM_EINVAL.
+ *  * Every call is asynchronous on the handle's stream (see
+ *    phasemask_set_stream) unless a comment says otherwise: results are valid
+ *    once that stream's work up to the call has completed.  Calls on one
+ *    handle must not run concurrently from several host threads.
+ *  * Every call returns a pm_status.  Nothing throws across the ABI.  After
+ *    PM_EINVAL or PM_EUNSUPPORTED the handle is unchanged and still usable;
+ *    phasemask_last_error() gives a human-readable reason.
+ *  * Error norms are relative to ||p|| = sqrt(N), N = height * width, with
+ *    the target rescaled to the energy of the SLM field,
+ *    m~ = m sqrt(N) / ||m||, which leaves the iterates unchanged:
+ *      E_F = || |F u| - m~ || / sqrt(N)      = d(u, M) / ||p||      (Eq. 7 as
+ *            printed, since u lies in S)
+ *      G   = || |P_M u| - 1 || / sqrt(N)     = d(P_M u, S) / ||p||  (Eq. 7,
+ *            the sentence after it: points of M and their projections on S)
+ *    Zero tie-break of Eq. 4a / Eq. 5: a pixel or Fourier coefficient whose
+ *    squared modulus is below FLT_MIN takes the phase theta = 0.
+ */
+#ifndef PHASEMASK_H
+#define PHASEMASK_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pm_plan* pm_handle;
+
+typedef enum {
+    PM_OK = 0,
+    PM_EINVAL = -1,        /* bad argument (null pointer, negative count, ...) */
+    PM_EUNSUPPORTED = -2,  /* size not a power of two in [16, 4096]           */
+    PM_ENOMEM = -3,        /* device or host allocation failed                */
+    PM_EDEVICE = -4,       /* a HIP call or kernel launch failed              */
+    PM_ESTATE = -5         /* handle destroyed or in an unusable state        */
+} pm_status;
+
+/* Flags for phasemask_create. */
+#define PM_FLAG_NO_GRAPH 0x1u   /* launch kernels one by one instead of
+                                   replaying a captured HIP graph           */
+
+/*
+ * Create a plan for masks of height x width pixels (Sec. II: n_y = height,
+ * n_x = width).  Allocates the plan's device workspace (the iterate, the
+ * rescaled target, twiddle tables and reduction partials: about 12 bytes per
+ * pixel plus 16 bytes per pixel-iteration-row of partials) on the current
+ * device.  `stream` is a hipStream_t (NULL = the null stream) used by every
+ * later call until phasemask_set_stream changes it.
+ * Errors: PM_EINVAL if out is NULL; PM_EUNSUPPORTED for sizes outside the
+ * supported set; PM_ENOMEM, PM_EDEVICE.  On error *out is set to NULL.
+ */
+pm_status phasemask_create(pm_handle* out, int height, int width,
+                           unsigned flags, void* stream);
+
+/* Release the plan and its workspace.  Synchronises the handle's stream
+ * first.  Destroying NULL returns PM_EINVAL. */
+pm_status phasemask_destroy(pm_handle h);
+
+/* Use `stream` (a hipStream_t, NULL = null stream) for subsequent calls. */
+pm_status phasemask_set_stream(pm_handle h, void* stream);
+
+/*
+ * Run n_iter iterations of Eq. 6 starting from u^0 = exp(i init_phase) and
+ * write the phase of u^{n_iter}.
+ *
+ *   target_amplitude  float[height*width], m >= 0, finite, not all zero,
+ *                     natural DFT order (Eq. 2).  Only its direction matters
+ *                     for the iterates (any positive scale gives the same u).
+ *   init_phase        float[height*width], radians, any real value.
+ *   n_iter            >= 0.
+ *   out_phase         float[height*width]; receives atan2(Im u, Re u) in
+ *                     (-pi, pi].  May alias init_phase; must not overlap
+ *                     target_amplitude.
+ *   err_history       NULL, or double[2*n_iter + 1] receiving
+ *                     [E_F^0, G^0, E_F^1, G^1, ..., E_F^{n-1}, G^{n-1}, E_F^n]
+ *                     (E_F^nu measured on u^nu before projecting, G^nu on
+ *                     P_M u^nu; the final entry costs one extra transform).
+ *                     Reductions are in FP64 and deterministic: repeating a
+ *                     call gives bitwise identical results.
+ * Errors: PM_EINVAL for a NULL array, n_iter < 0, or overlapping output and
+ * target; PM_ENOMEM if the partial-sum buffer for n_iter cannot be grown;
+ * PM_EDEVICE if a launch fails.
+ */
+pm_status phasemask_solve(pm_handle h, const float* target_amplitude,
+                          const float* init_phase, int n_iter,
+                          float* out_phase, double* err_history);
+
+/*
+ * Errors of a given phase-only mask u = exp(i phase) against a target:
+ * errors[0] = E_F, errors[1] = G (definitions above; equal to entries 0 and
+ * 1 of the history of a solve started at `phase`).
+ *   target_amplitude, phase   as for phasemask_solve.
+ *   errors                    double[2], device.
+ * Errors: PM_EINVAL for NULL arrays; PM_EDEVICE.
+ */
+pm_status phasemask_error(pm_handle h, const float* target_amplitude,
+                          const float* phase, double* errors);
+
+/*
+ * Unnormalised complex 2-D DFT through the library's own FFT passes (the
+ * transform inside P_M, Eq. 4b):
+ *   inverse = 0:  out[k] = sum_x in[x] exp(-2 pi i (k_y y/height + k_x x/width))
+ *   inverse = 1:  out[x] = sum_k in[k] exp(+2 pi i (...))   (no 1/N factor)
+ * in, out: complex float[height*width] (interleaved re, im).  They may be
+ * the same buffer.
+ * Errors: PM_EINVAL for NULL arrays; PM_EDEVICE.
+ */
+pm_status phasemask_fft2(pm_handle h, const void* in, void* out, int inverse);
+
+/*
+ * Measurement (roofline accounting of the two passes that run n_iter times,
+ * Eq. 6): average device duration in milliseconds of one column pass
+ * (forward column FFT, Eq. 5 projection, inverse column FFT) and of one row
+ * pass (inverse row FFT, Eq. 4a projection, forward row FFT).  Prepares the
+ * iterate of a solve started at `phase` against `target_amplitude`, then runs
+ * `reps` iterations, each pass launched with its own start/end events
+ * (recorded by the kernel launch itself, so host launch gaps are excluded).
+ * The iterate left behind is discarded.  Synchronises the stream; col_ms and
+ * row_ms are HOST pointers.
+ * Errors: PM_EINVAL for NULL arguments or reps outside [1, 100000];
+ * PM_EDEVICE.
+ */
+pm_status phasemask_time_passes(pm_handle h, const float* target_amplitude,
+                                const float* phase, int reps,
+                                float* col_ms, float* row_ms);
+
+/* Plan facts.  Bytes of device workspace currently held by the plan. */
+size_t phasemask_workspace_bytes(pm_handle h);
+
+/* Static text for a status code. */
+const char* phasemask_status_string(pm_status s);
+
+/* Reason for the last non-PM_OK status returned on the calling host thread
+ * (static or thread-local text, valid until the next call). */
+const char* phasemask_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHASEMASK_H */

@@ -1,0 +1,186 @@
+"""Thin ctypes binding of the C ABI in include/phasemask.h.
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch provides device memory (tensors) and the stream (the current torch
+stream of the tensors' device is handed to the library before each call).
+If the library has not been built, importing this module raises ImportError:
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # must load before the library: the process then has one HIP runtime
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libphasemask.so")
+
+# Every function the header declares, with (restype, argtypes).
+_c_handle = ctypes.c_void_p
+_SIGNATURES = {
+    "phasemask_create": (ctypes.c_int, [ctypes.POINTER(_c_handle), ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_uint, ctypes.c_void_p]),
+    "phasemask_destroy": (ctypes.c_int, [_c_handle]),
+    "phasemask_set_stream": (ctypes.c_int, [_c_handle, ctypes.c_void_p]),
+    "phasemask_solve": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "phasemask_error": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "phasemask_fft2": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "phasemask_time_passes": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_float),
+                                             ctypes.POINTER(ctypes.c_float)]),
+    "phasemask_workspace_bytes": (ctypes.c_size_t, [_c_handle]),
+    "phasemask_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "phasemask_last_error": (ctypes.c_char_p, []),
+}
+
+PM_FLAG_NO_GRAPH = 0x1
+
+STATUS = {0: "PM_OK", -1: "PM_EINVAL", -2: "PM_EUNSUPPORTED", -3: "PM_ENOMEM",
+          -4: "PM_EDEVICE", -5: "PM_ESTATE"}
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(
+            f"{_LIB_PATH} is not built; run `python -m paper_1302_0120_amd.build` (HIP, gfx950)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class PhaseMaskError(RuntimeError):
+    """A non-PM_OK status from the library."""
+
+    def __init__(self, status: int, call: str):
+        self.status = status
+        why = lib.phasemask_last_error().decode(errors="replace")
+        super().__init__(f"{call}: {STATUS.get(status, status)}: {why}")
+
+
+def _check(status: int, call: str):
+    if status != 0:
+        raise PhaseMaskError(status, call)
+
+
+def _dev_ptr(t: torch.Tensor, dtype, shape, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+class PhaseMask:
+    """One plan for height x width masks on one device (see include/phasemask.h)."""
+
+    def __init__(self, height: int, width: int, flags: int = 0, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        self.height, self.width = int(height), int(width)
+        self.shape = (self.height, self.width)
+        h = _c_handle()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            _check(lib.phasemask_create(ctypes.byref(h), self.height, self.width, flags, stream),
+                   "phasemask_create")
+        self._h = h
+
+    def _stream(self):
+        if self._h is None:
+            raise PhaseMaskError(-5, "use after close")
+        _check(lib.phasemask_set_stream(self._h, torch.cuda.current_stream(self.device).cuda_stream),
+               "phasemask_set_stream")
+
+    def solve(self, target: torch.Tensor, init_phase: torch.Tensor, n_iter: int,
+              out: torch.Tensor | None = None, history: bool | torch.Tensor = True):
+        """Run n_iter GS iterations; returns (phase, history or None)."""
+        tp = _dev_ptr(target, torch.float32, self.shape, "target")
+        pp = _dev_ptr(init_phase, torch.float32, self.shape, "init_phase")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        op = _dev_ptr(out, torch.float32, self.shape, "out")
+        hist = None
+        if isinstance(history, torch.Tensor):
+            hist = history
+        elif history:
+            hist = torch.empty(2 * int(n_iter) + 1, dtype=torch.float64, device=self.device)
+        hp = 0 if hist is None else _dev_ptr(hist, torch.float64, (2 * int(n_iter) + 1,), "history")
+        self._stream()
+        _check(lib.phasemask_solve(self._h, tp, pp, int(n_iter), op, hp or None), "phasemask_solve")
+        return out, hist
+
+    def error(self, target: torch.Tensor, phase: torch.Tensor, out: torch.Tensor | None = None):
+        """(E_F, G) of exp(i phase) as a float64 device tensor of 2 entries."""
+        tp = _dev_ptr(target, torch.float32, self.shape, "target")
+        pp = _dev_ptr(phase, torch.float32, self.shape, "phase")
+        if out is None:
+            out = torch.empty(2, dtype=torch.float64, device=self.device)
+        ep = _dev_ptr(out, torch.float64, (2,), "errors")
+        self._stream()
+        _check(lib.phasemask_error(self._h, tp, pp, ep), "phasemask_error")
+        return out
+
+    def fft2(self, x: torch.Tensor, inverse: bool = False, out: torch.Tensor | None = None):
+        """Unnormalised complex64 2-D DFT (inverse without 1/N)."""
+        xp = _dev_ptr(x, torch.complex64, self.shape, "x")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.complex64, device=self.device)
+        op = _dev_ptr(out, torch.complex64, self.shape, "out")
+        self._stream()
+        _check(lib.phasemask_fft2(self._h, xp, op, 1 if inverse else 0), "phasemask_fft2")
+        return out
+
+    def time_passes(self, target: torch.Tensor, phase: torch.Tensor, reps: int = 100):
+        """(column-pass ms, row-pass ms): average kernel durations over `reps`
+        iterations, from events recorded by the launches themselves."""
+        tp = _dev_ptr(target, torch.float32, self.shape, "target")
+        pp = _dev_ptr(phase, torch.float32, self.shape, "phase")
+        c, r = ctypes.c_float(), ctypes.c_float()
+        self._stream()
+        _check(lib.phasemask_time_passes(self._h, tp, pp, int(reps), ctypes.byref(c), ctypes.byref(r)),
+               "phasemask_time_passes")
+        return float(c.value), float(r.value)
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(lib.phasemask_workspace_bytes(self._h)) if self._h is not None else 0
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _check(lib.phasemask_destroy(self._h), "phasemask_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_PLANS: dict = {}
+
+
+def plan_for(height: int, width: int, device=None) -> PhaseMask:
+    """A cached plan per (device, height, width)."""
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+    key = (dev, int(height), int(width))
+    if key not in _PLANS:
+        _PLANS[key] = PhaseMask(height, width, device=torch.device("cuda", dev))
+    return _PLANS[key]
+
+
+def solve(target: torch.Tensor, init_phase: torch.Tensor, n_iter: int, history: bool = True):
+    """GS phase mask for `target` from `init_phase` (device float32 [H][W])."""
+    p = plan_for(target.shape[0], target.shape[1], target.device)
+    return p.solve(target, init_phase, n_iter, history=history)

@@ -1,0 +1,449 @@
+// phasemask.cpp -- host side of the C ABI declared in include/phasemask.h:
+// plan creation (workspace, FP64-derived twiddle tables), argument checks,
+// the launch sequence of one solve, and its capture into a HIP graph.
+#include "phasemask.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <list>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "pm_common.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pm_status fail(pm_status s, const std::string& why) {
+    g_last_error = why;
+    return s;
+}
+
+pm_status fail_hip(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? PM_ENOMEM : PM_EDEVICE;
+}
+
+bool pow2_in_range(int n) { return n >= 16 && n <= 4096 && (n & (n - 1)) == 0; }
+
+int log2i(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+using RowLauncher = hipError_t (*)(int, const pm::RowParams&, int, hipStream_t, hipEvent_t, hipEvent_t);
+using ColLauncher = hipError_t (*)(int, const pm::ColParams&, int, hipStream_t, hipEvent_t, hipEvent_t);
+
+// Indexed by log2(L) - 4, L = 16 .. 4096.
+const RowLauncher kRowLaunch[9] = {pm::launch_row_16,  pm::launch_row_32,   pm::launch_row_64,
+                                   pm::launch_row_128, pm::launch_row_256,  pm::launch_row_512,
+                                   pm::launch_row_1024, pm::launch_row_2048, pm::launch_row_4096};
+const ColLauncher kColLaunch[9] = {pm::launch_col_16,  pm::launch_col_32,   pm::launch_col_64,
+                                   pm::launch_col_128, pm::launch_col_256,  pm::launch_col_512,
+                                   pm::launch_col_1024, pm::launch_col_2048, pm::launch_col_4096};
+
+struct GraphEntry {
+    int n_iter;
+    bool hist;
+    hipGraphExec_t exec;
+};
+
+constexpr int kNormGrid = 64;          // work-groups of the target-norm partial pass
+constexpr size_t kMaxCachedGraphs = 8;
+
+}  // namespace
+
+struct pm_plan {
+    int H = 0, W = 0, N = 0;
+    unsigned flags = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;      // caller's stream
+    hipStream_t cap_stream = nullptr;  // private stream used only for graph capture
+    int nwg_row = 0, nwg_col = 0, stride = 0;
+    float2* X = nullptr;
+    float* mhat = nullptr;
+    float2* twW = nullptr;
+    float2* twH = nullptr;
+    double* part_m = nullptr;
+    double* part = nullptr;
+    size_t part_entries = 0;           // capacity of `part` in history entries
+    pm::PmIo* io = nullptr;
+    size_t ws_bytes = 0;
+    std::list<GraphEntry> graphs;      // most recently used first
+    bool dead = false;
+};
+
+namespace {
+
+void drop_graphs(pm_plan* h) {
+    for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
+}
+
+void free_plan(pm_plan* h) {
+    drop_graphs(h);
+    (void)hipFree(h->X);
+    (void)hipFree(h->mhat);
+    (void)hipFree(h->twW);
+    (void)hipFree(h->twH);
+    (void)hipFree(h->part_m);
+    (void)hipFree(h->part);
+    (void)hipFree(h->io);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    delete h;
+}
+
+pm_status check_handle(pm_plan* h) {
+    if (h == nullptr) return fail(PM_EINVAL, "null handle");
+    if (h->dead) return fail(PM_ESTATE, "handle is in an unusable state");
+    return PM_OK;
+}
+
+// exp(-2 pi i k / L), k < L, in double, rounded once to float.
+std::vector<float2> twiddles(int L) {
+    std::vector<float2> t(L);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int k = 0; k < L; ++k) {
+        const double a = two_pi * (double)k / (double)L;
+        t[k] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
+    }
+    return t;
+}
+
+// Makes sure `part` holds `entries` history entries of partials.
+pm_status ensure_partials(pm_plan* h, size_t entries) {
+    if (entries <= h->part_entries) return PM_OK;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+    drop_graphs(h);  // captured graphs hold the old pointer
+    size_t want = h->part_entries ? h->part_entries : 64;
+    while (want < entries) want *= 2;
+    double* p = nullptr;
+    e = hipMalloc(&p, want * (size_t)h->stride * sizeof(double));
+    if (e != hipSuccess) return fail_hip(e, "hipMalloc(partials)");
+    (void)hipFree(h->part);
+    h->ws_bytes += (want - h->part_entries) * (size_t)h->stride * sizeof(double);
+    h->part = p;
+    h->part_entries = want;
+    return PM_OK;
+}
+
+pm::RowParams row_params(pm_plan* h, double* part) {
+    pm::RowParams r{};
+    r.X = h->X;
+    r.tw = h->twW;
+    r.io = h->io;
+    r.part = part;
+    r.H = h->H;
+    return r;
+}
+
+pm::ColParams col_params(pm_plan* h, double* part) {
+    pm::ColParams c{};
+    c.X = h->X;
+    c.mhat = h->mhat;
+    c.tw = h->twH;
+    c.part = part;
+    c.W = h->W;
+    c.invN = 1.0 / (double)h->N;
+    return c;
+}
+
+#define PM_TRY(expr, what)                          \
+    do {                                            \
+        hipError_t e_ = (expr);                     \
+        if (e_ != hipSuccess) return fail_hip(e_, what); \
+    } while (0)
+
+// Target normalisation + tiling (the rescaled m used by every column pass).
+pm_status enqueue_target(pm_plan* h, hipStream_t s) {
+    PM_TRY(pm::launch_norm_partial(h->io, h->N, h->part_m, kNormGrid, s), "target norm");
+    PM_TRY(pm::launch_target_tile(h->io, h->H, h->W, h->part_m, kNormGrid, h->mhat, s), "target tile");
+    return PM_OK;
+}
+
+// The whole solve after the pointer block is set: target preparation,
+// u^0, n_iter iterations, final error and history finalisation.
+pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist) {
+    const int lw = log2i(h->W) - 4, lh = log2i(h->H) - 4;
+    const RowLauncher row = kRowLaunch[lw];
+    const ColLauncher col = kColLaunch[lh];
+    auto pe = [&](int e) { return h->part + (size_t)e * h->stride; };
+
+    if (n_iter == 0) {
+        PM_TRY(pm::launch_wrap_phase(h->io, h->N, s), "wrap phase");
+        if (!hist) return PM_OK;
+        pm_status st = enqueue_target(h, s);
+        if (st != PM_OK) return st;
+        PM_TRY(row(pm::ROW_INIT, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+        PM_TRY(col(pm::COL_ERR, col_params(h, pe(0)), h->nwg_col, s, nullptr, nullptr), "column error");
+        PM_TRY(pm::launch_finalize(h->part, h->stride, h->nwg_col, h->nwg_row, 1.0 / h->N, h->io, 0, 1, s),
+               "finalize");
+        return PM_OK;
+    }
+    pm_status st = enqueue_target(h, s);
+    if (st != PM_OK) return st;
+    PM_TRY(row(pm::ROW_INIT, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+    for (int nu = 0; nu < n_iter; ++nu) {
+        PM_TRY(col(pm::COL_ITER, col_params(h, pe(2 * nu)), h->nwg_col, s, nullptr, nullptr), "column pass");
+        const bool last = nu == n_iter - 1;
+        const int mode = !last ? pm::ROW_ITER : (hist ? pm::ROW_LAST_FWD : pm::ROW_LAST);
+        PM_TRY(row(mode, row_params(h, pe(2 * nu + 1)), h->nwg_row, s, nullptr, nullptr), "row pass");
+    }
+    if (hist) {
+        PM_TRY(col(pm::COL_ERR, col_params(h, pe(2 * n_iter)), h->nwg_col, s, nullptr, nullptr), "column error");
+        PM_TRY(pm::launch_finalize(h->part, h->stride, h->nwg_col, h->nwg_row, 1.0 / h->N, h->io, 0,
+                                   2 * n_iter + 1, s),
+               "finalize");
+    }
+    return PM_OK;
+}
+
+// Replays (capturing on first use) the graph of one solve shape.
+pm_status launch_graph(pm_plan* h, int n_iter, bool hist) {
+    for (auto it = h->graphs.begin(); it != h->graphs.end(); ++it) {
+        if (it->n_iter == n_iter && it->hist == hist) {
+            h->graphs.splice(h->graphs.begin(), h->graphs, it);
+            PM_TRY(hipGraphLaunch(it->exec, h->stream), "hipGraphLaunch");
+            return PM_OK;
+        }
+    }
+    hipGraph_t graph = nullptr;
+    PM_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    pm_status st = enqueue_solve(h, h->cap_stream, n_iter, hist);
+    hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
+    if (st != PM_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (ec != hipSuccess) return fail_hip(ec, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail_hip(ei, "hipGraphInstantiate");
+    if (h->graphs.size() >= kMaxCachedGraphs) {
+        (void)hipGraphExecDestroy(h->graphs.back().exec);
+        h->graphs.pop_back();
+    }
+    h->graphs.push_front(GraphEntry{n_iter, hist, exec});
+    PM_TRY(hipGraphLaunch(exec, h->stream), "hipGraphLaunch");
+    return PM_OK;
+}
+
+bool misaligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) != 0; }
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* phasemask_status_string(pm_status s) {
+    switch (s) {
+        case PM_OK: return "PM_OK";
+        case PM_EINVAL: return "PM_EINVAL: invalid argument";
+        case PM_EUNSUPPORTED: return "PM_EUNSUPPORTED: unsupported size";
+        case PM_ENOMEM: return "PM_ENOMEM: out of memory";
+        case PM_EDEVICE: return "PM_EDEVICE: device error";
+        case PM_ESTATE: return "PM_ESTATE: bad handle state";
+    }
+    return "unknown pm_status";
+}
+
+const char* phasemask_last_error(void) { return g_last_error.c_str(); }
+
+pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags, void* stream) {
+    if (out == nullptr) return fail(PM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!pow2_in_range(height) || !pow2_in_range(width))
+        return fail(PM_EUNSUPPORTED, "height and width must be powers of two in [16, 4096]");
+    if ((flags & ~PM_FLAG_NO_GRAPH) != 0) return fail(PM_EINVAL, "unknown flag bits");
+    pm_plan* h = new (std::nothrow) pm_plan;
+    if (h == nullptr) return fail(PM_ENOMEM, "host allocation failed");
+    h->H = height;
+    h->W = width;
+    h->N = height * width;
+    h->flags = flags;
+    h->stream = (hipStream_t)stream;
+    h->nwg_row = height / pm::kGR;
+    h->nwg_col = width / pm::kC;
+    h->stride = h->nwg_row > h->nwg_col ? h->nwg_row : h->nwg_col;
+    if (h->stride < kNormGrid) h->stride = kNormGrid;
+
+    auto bail = [&](hipError_t e, const char* what) {
+        pm_status s = fail_hip(e, what);
+        free_plan(h);
+        return s;
+    };
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) return bail(e, "hipGetDevice");
+    const size_t n = (size_t)h->N;
+    if ((e = hipMalloc(&h->X, n * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(iterate)");
+    if ((e = hipMalloc(&h->mhat, n * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc(target)");
+    if ((e = hipMalloc(&h->twW, width * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
+    if ((e = hipMalloc(&h->twH, height * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
+    if ((e = hipMalloc(&h->part_m, kNormGrid * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(norm)");
+    if ((e = hipMalloc(&h->io, sizeof(pm::PmIo))) != hipSuccess) return bail(e, "hipMalloc(io)");
+    h->ws_bytes = n * (sizeof(float2) + sizeof(float)) + (size_t)(width + height) * sizeof(float2) +
+                  kNormGrid * sizeof(double) + sizeof(pm::PmIo);
+    const std::vector<float2> tw_w = twiddles(width), tw_h = twiddles(height);
+    if ((e = hipMemcpy(h->twW, tw_w.data(), width * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "hipMemcpy(twiddles)");
+    if ((e = hipMemcpy(h->twH, tw_h.data(), height * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "hipMemcpy(twiddles)");
+    if ((e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        return bail(e, "hipStreamCreate");
+    *out = h;
+    return PM_OK;
+}
+
+pm_status phasemask_destroy(pm_handle h) {
+    if (h == nullptr) return fail(PM_EINVAL, "null handle");
+    (void)hipStreamSynchronize(h->stream);
+    free_plan(h);
+    return PM_OK;
+}
+
+pm_status phasemask_set_stream(pm_handle h, void* stream) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    h->stream = (hipStream_t)stream;
+    return PM_OK;
+}
+
+size_t phasemask_workspace_bytes(pm_handle h) { return h ? h->ws_bytes : 0; }
+
+pm_status phasemask_solve(pm_handle h, const float* target_amplitude, const float* init_phase, int n_iter,
+                          float* out_phase, double* err_history) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    if (!target_amplitude || !init_phase || !out_phase) return fail(PM_EINVAL, "null array argument");
+    if (n_iter < 0) return fail(PM_EINVAL, "n_iter must be >= 0");
+    if (misaligned(target_amplitude, 16)) return fail(PM_EINVAL, "target must be 16-byte aligned");
+    if (misaligned(init_phase, 4) || misaligned(out_phase, 4) || misaligned(err_history, 8))
+        return fail(PM_EINVAL, "misaligned array argument");
+    const size_t nb = (size_t)h->N * sizeof(float);
+    if (overlaps(out_phase, nb, target_amplitude, nb)) return fail(PM_EINVAL, "out_phase overlaps the target");
+    const bool hist = err_history != nullptr;
+    if (hist && overlaps(err_history, (2 * (size_t)n_iter + 1) * sizeof(double), target_amplitude, nb))
+        return fail(PM_EINVAL, "err_history overlaps the target");
+    st = ensure_partials(h, 2 * (size_t)n_iter + 1);
+    if (st != PM_OK) return st;
+    pm::PmIo io{target_amplitude, init_phase, out_phase, err_history};
+    PM_TRY(pm::launch_set_io(h->io, io, h->stream), "set io");
+    if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_solve(h, h->stream, n_iter, hist);
+    return launch_graph(h, n_iter, hist);
+}
+
+pm_status phasemask_error(pm_handle h, const float* target_amplitude, const float* phase, double* errors) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    if (!target_amplitude || !phase || !errors) return fail(PM_EINVAL, "null array argument");
+    if (misaligned(target_amplitude, 16)) return fail(PM_EINVAL, "target must be 16-byte aligned");
+    if (misaligned(phase, 4) || misaligned(errors, 8)) return fail(PM_EINVAL, "misaligned array argument");
+    st = ensure_partials(h, 2);
+    if (st != PM_OK) return st;
+    pm::PmIo io{target_amplitude, phase, nullptr, errors};
+    hipStream_t s = h->stream;
+    PM_TRY(pm::launch_set_io(h->io, io, s), "set io");
+    st = enqueue_target(h, s);
+    if (st != PM_OK) return st;
+    const RowLauncher row = kRowLaunch[log2i(h->W) - 4];
+    const ColLauncher col = kColLaunch[log2i(h->H) - 4];
+    PM_TRY(row(pm::ROW_INIT, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+    PM_TRY(col(pm::COL_ITER, col_params(h, h->part), h->nwg_col, s, nullptr, nullptr), "column pass");
+    PM_TRY(row(pm::ROW_GAP, row_params(h, h->part + h->stride), h->nwg_row, s, nullptr, nullptr), "row gap");
+    PM_TRY(pm::launch_finalize(h->part, h->stride, h->nwg_col, h->nwg_row, 1.0 / h->N, h->io, 0, 2, s),
+           "finalize");
+    return PM_OK;
+}
+
+pm_status phasemask_fft2(pm_handle h, const void* in, void* out, int inverse) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    if (!in || !out) return fail(PM_EINVAL, "null array argument");
+    if (misaligned(in, 8) || misaligned(out, 8)) return fail(PM_EINVAL, "complex arrays must be 8-byte aligned");
+    hipStream_t s = h->stream;
+    const RowLauncher row = kRowLaunch[log2i(h->W) - 4];
+    const ColLauncher col = kColLaunch[log2i(h->H) - 4];
+    pm::RowParams rp = row_params(h, nullptr);
+    pm::ColParams cp = col_params(h, nullptr);
+    if (!inverse) {
+        rp.nat_in = (const float2*)in;
+        cp.nat_out = (float2*)out;
+        PM_TRY(row(pm::ROW_FFT_FWD, rp, h->nwg_row, s, nullptr, nullptr), "row fft");
+        PM_TRY(col(pm::COL_FFT_FWD, cp, h->nwg_col, s, nullptr, nullptr), "column fft");
+    } else {
+        cp.nat_in = (const float2*)in;
+        rp.nat_out = (float2*)out;
+        PM_TRY(col(pm::COL_FFT_INV, cp, h->nwg_col, s, nullptr, nullptr), "column ifft");
+        PM_TRY(row(pm::ROW_FFT_INV, rp, h->nwg_row, s, nullptr, nullptr), "row ifft");
+    }
+    return PM_OK;
+}
+
+pm_status phasemask_time_passes(pm_handle h, const float* target_amplitude, const float* phase, int reps,
+                                float* col_ms, float* row_ms) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    if (!target_amplitude || !phase || !col_ms || !row_ms) return fail(PM_EINVAL, "null argument");
+    if (reps < 1 || reps > 100000) return fail(PM_EINVAL, "reps must be in [1, 100000]");
+    if (misaligned(target_amplitude, 16)) return fail(PM_EINVAL, "target must be 16-byte aligned");
+    if (misaligned(phase, 4)) return fail(PM_EINVAL, "misaligned array argument");
+    st = ensure_partials(h, 2);
+    if (st != PM_OK) return st;
+    hipStream_t s = h->stream;
+    pm::PmIo io{target_amplitude, phase, nullptr, nullptr};
+    PM_TRY(pm::launch_set_io(h->io, io, s), "set io");
+    st = enqueue_target(h, s);
+    if (st != PM_OK) return st;
+    const RowLauncher row = kRowLaunch[log2i(h->W) - 4];
+    const ColLauncher col = kColLaunch[log2i(h->H) - 4];
+    PM_TRY(row(pm::ROW_INIT, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+    std::vector<hipEvent_t> ev(4 * (size_t)reps, nullptr);
+    auto cleanup = [&]() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    for (auto& e : ev) {
+        hipError_t ee = hipEventCreate(&e);
+        if (ee != hipSuccess) {
+            cleanup();
+            return fail_hip(ee, "hipEventCreate");
+        }
+    }
+    hipError_t err = hipSuccess;
+    for (int r = 0; r < reps && err == hipSuccess; ++r) {
+        err = col(pm::COL_ITER, col_params(h, h->part), h->nwg_col, s, ev[4 * r], ev[4 * r + 1]);
+        if (err == hipSuccess)
+            err = row(pm::ROW_ITER, row_params(h, h->part + h->stride), h->nwg_row, s, ev[4 * r + 2],
+                      ev[4 * r + 3]);
+    }
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    double tc = 0.0, tr = 0.0;
+    for (int r = 0; r < reps && err == hipSuccess; ++r) {
+        float a = 0.f, b = 0.f;
+        err = hipEventElapsedTime(&a, ev[4 * r], ev[4 * r + 1]);
+        if (err == hipSuccess) err = hipEventElapsedTime(&b, ev[4 * r + 2], ev[4 * r + 3]);
+        tc += a;
+        tr += b;
+    }
+    cleanup();
+    if (err != hipSuccess) return fail_hip(err, "timed passes");
+    *col_ms = (float)(tc / reps);
+    *row_ms = (float)(tr / reps);
+    return PM_OK;
+}
+
+}  // extern "C"

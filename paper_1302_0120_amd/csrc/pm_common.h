@@ -1,0 +1,115 @@
+// pm_common.h -- types shared by the host plan code and the kernel
+// translation units (no kernels here).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace pm {
+
+// Iterate layout in device memory ("strip-tiled"): the [H][W] complex field is
+// split into W/kC strips of kC adjacent columns; strip s is stored as a
+// contiguous [H][kC] block, so element (y, x) sits at
+//     ((x / kC) * H + y) * kC + (x % kC).
+// A column pass reads one strip as one contiguous block; a row pass that
+// owns kGR adjacent rows reads kGR*kC contiguous elements (128 bytes) per
+// strip.  The rescaled target uses the same layout.
+constexpr int kC = 4;    // columns per strip = columns per column work-group
+constexpr int kGR = 4;   // rows per row work-group
+
+// Per-call pointers.  Kernels replayed from a captured graph read them from
+// this device-resident block, which a one-thread kernel rewrites before each
+// replay, so one graph serves any caller buffers.
+struct PmIo {
+    const float* target;   // [H][W] target amplitude m
+    const float* phase_in; // [H][W] initial phase
+    float* phase_out;      // [H][W] output phase
+    double* hist;          // error history (or the two errors of a mask), may be null
+};
+
+// Row-pass modes (bit sets).
+enum : int {
+    RIN_PHASE = 1,    // read a phase image, form exp(i phi)
+    RIN_TILED = 2,    // read the tiled iterate
+    RIN_NAT = 4,      // read a natural-layout complex image
+    R_INV = 8,        // inverse row transform
+    R_PS = 16,        // P_S (Eq. 4a) + gap partial sum
+    R_FWD = 32,       // forward row transform, write the tiled iterate
+    ROUT_PHASE = 64,  // write atan2 of the projected field
+    ROUT_NAT = 128,   // write a natural-layout complex image
+};
+constexpr int ROW_INIT = RIN_PHASE | R_FWD;
+constexpr int ROW_ITER = RIN_TILED | R_INV | R_PS | R_FWD;
+constexpr int ROW_LAST = RIN_TILED | R_INV | R_PS | ROUT_PHASE;
+constexpr int ROW_LAST_FWD = RIN_TILED | R_INV | R_PS | ROUT_PHASE | R_FWD;
+constexpr int ROW_GAP = RIN_TILED | R_INV | R_PS;
+constexpr int ROW_FFT_FWD = RIN_NAT | R_FWD;
+constexpr int ROW_FFT_INV = RIN_TILED | R_INV | ROUT_NAT;
+
+// Column-pass modes (bit sets).
+enum : int {
+    CIN_TILED = 1,
+    CIN_NAT = 2,
+    C_FWD = 4,        // forward column transform
+    C_PROJ = 8,       // M-hat (Eq. 5) + Fourier-error partial sum
+    C_ERR = 16,       // Fourier-error partial sum only
+    C_INV = 32,       // inverse column transform
+    COUT_TILED = 64,
+    COUT_NAT = 128,
+};
+constexpr int COL_ITER = CIN_TILED | C_FWD | C_PROJ | C_INV | COUT_TILED;
+constexpr int COL_ERR = CIN_TILED | C_FWD | C_ERR;
+constexpr int COL_FFT_FWD = CIN_TILED | C_FWD | COUT_NAT;
+constexpr int COL_FFT_INV = CIN_NAT | C_INV | COUT_TILED;
+
+struct RowParams {
+    float2* X;             // tiled iterate
+    const float2* tw;      // exp(-2 pi i k / W), k < W
+    const PmIo* io;
+    const float2* nat_in;  // natural-layout input (RIN_NAT)
+    float2* nat_out;       // natural-layout output (ROUT_NAT)
+    double* part;          // one gap partial per work-group (R_PS)
+    int H;
+};
+
+struct ColParams {
+    float2* X;             // tiled iterate
+    const float* mhat;     // tiled target divided by its 2-norm
+    const float2* tw;      // exp(-2 pi i k / H), k < H
+    const float2* nat_in;
+    float2* nat_out;
+    double* part;          // one Fourier-error partial per work-group
+    int W;
+    double invN;           // 1 / (H W)
+};
+
+// Launchers, one pair per supported transform length (16 .. 4096), defined
+// in the per-length kernel translation units.  `grid` is the number of
+// work-groups; the block size is fixed by the length.  With non-null
+// events the launch records the kernel's own start and end on them
+// (hipExtLaunchKernelGGL), for timing a single pass.
+#define PM_DECLARE_LAUNCHERS(L)                                                        \
+    hipError_t launch_row_##L(int mode, const RowParams& p, int grid, hipStream_t s,    \
+                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);      \
+    hipError_t launch_col_##L(int mode, const ColParams& p, int grid, hipStream_t s,    \
+                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+PM_DECLARE_LAUNCHERS(16)
+PM_DECLARE_LAUNCHERS(32)
+PM_DECLARE_LAUNCHERS(64)
+PM_DECLARE_LAUNCHERS(128)
+PM_DECLARE_LAUNCHERS(256)
+PM_DECLARE_LAUNCHERS(512)
+PM_DECLARE_LAUNCHERS(1024)
+PM_DECLARE_LAUNCHERS(2048)
+PM_DECLARE_LAUNCHERS(4096)
+#undef PM_DECLARE_LAUNCHERS
+
+// Small kernels (pm_aux.hip).
+hipError_t launch_set_io(PmIo* io, const PmIo& val, hipStream_t s);
+hipError_t launch_norm_partial(const PmIo* io, int n, double* part, int grid, hipStream_t s);
+hipError_t launch_target_tile(const PmIo* io, int H, int W, const double* part, int npart,
+                              float* mhat, hipStream_t s);
+hipError_t launch_finalize(const double* part, int stride, int nwg_col, int nwg_row, double invN,
+                           const PmIo* io, int first_entry, int count, hipStream_t s);
+hipError_t launch_wrap_phase(const PmIo* io, int n, hipStream_t s);
+
+}  // namespace pm

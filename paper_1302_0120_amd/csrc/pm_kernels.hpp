@@ -1,0 +1,206 @@
+// pm_kernels.hpp -- the fused row and column passes of one Gerchberg-Saxton
+// iteration (Eq. 6), templated on the transform length.
+//
+// One iteration = two passes over the iterate in HBM/L2:
+//   column pass:  forward column FFT -> M-hat of Eq. 5 (keep the phase of
+//                 each Fourier coefficient, take the target modulus) ->
+//                 inverse column FFT, plus the FP64 Fourier-error partials;
+//   row pass:     inverse row FFT (completes P_M, Eq. 4b) -> P_S of Eq. 4a
+//                 (unit modulus) -> forward row FFT of the next iteration,
+//                 plus the FP64 gap partials.
+// The very first row pass forms exp(i phi0) instead (u^0 in S, Eq. 1); the
+// last one writes the phase of u^n.
+#pragma once
+#include <float.h>
+
+#include "pm_common.h"
+#include "pm_fft.hpp"
+
+namespace pm {
+
+// Deterministic work-group sum of one double per thread: a fixed xor
+// butterfly inside each wave, then wave results added in wave order by
+// thread 0.  The result is valid in thread 0 only.  All threads must call.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    constexpr int WS = NT < 64 ? NT : 64;
+    constexpr int NW = (NT + 63) / 64;
+#pragma unroll
+    for (int off = WS / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WS);
+    if constexpr (NW == 1) {
+        return v;
+    } else {
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        if (lane == 0) red[wave] = v;
+        __syncthreads();
+        double s = 0.0;
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w) s += red[w];
+        }
+        return s;
+    }
+}
+
+template <int L>
+struct LineShape {
+    static constexpr int P = points_per_thread(L);  // points per thread
+    static constexpr int T = L / P;                 // threads per line
+    static constexpr int LP = lds_line_len(L);      // padded LDS line
+};
+
+// Column pass over one strip of kC columns (one work-group per strip).
+// Thread (j, c) = (tid / kC, tid % kC) owns column c of the strip and the
+// rows j + T t; for a fixed t the work-group's loads cover consecutive
+// rows of the strip, i.e. one contiguous run of memory.
+template <int H, int MODE>
+__global__ void __launch_bounds__(kC * LineShape<H>::T)
+k_col(ColParams a) {
+    constexpr int P = LineShape<H>::P;
+    constexpr int T = LineShape<H>::T;
+    constexpr int NT = kC * T;
+    constexpr int LP = LineShape<H>::LP;
+    __shared__ float2 lds[kC * LP];
+    __shared__ double red[(NT + 63) / 64];
+
+    const int tid = threadIdx.x;
+    const int c = tid & (kC - 1);
+    const int j = tid / kC;
+    const int s = blockIdx.x;
+    const size_t sb = (size_t)s * H * kC;
+    float2 v[P];
+
+    if constexpr ((MODE & CIN_NAT) != 0) {
+#pragma unroll
+        for (int t = 0; t < P; ++t) v[t] = a.nat_in[(size_t)(j + T * t) * a.W + s * kC + c];
+    } else {
+#pragma unroll
+        for (int t = 0; t < P; ++t) v[t] = a.X[sb + (size_t)(j + T * t) * kC + c];
+    }
+    float2* line = lds + c * LP;
+
+    if constexpr ((MODE & C_FWD) != 0) fft_line<H, P, false>(v, j, line, a.tw);
+
+    if constexpr ((MODE & (C_PROJ | C_ERR)) != 0) {
+        // U = unnormalised DFT of u, so |U|/N is the unitary modulus over
+        // sqrt(N); mhat = m / ||m||.  E_F^2 = sum (|U|/N - mhat)^2.
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            const float m = a.mhat[sb + (size_t)(j + T * t) * kC + c];
+            const float2 U = v[t];
+            const float a2 = U.x * U.x + U.y * U.y;
+            const double d = (double)sqrtf(a2) * a.invN - (double)m;
+            acc = fma(d, d, acc);
+            if constexpr ((MODE & C_PROJ) != 0) {
+                if (a2 >= FLT_MIN) {
+                    const float r = m * rsqrtf(a2);
+                    v[t] = make_float2(U.x * r, U.y * r);
+                } else {
+                    v[t] = make_float2(m, 0.0f);
+                }
+            }
+        }
+        const double tot = block_sum<NT>(acc, red);
+        if (tid == 0) a.part[blockIdx.x] = tot;
+    }
+
+    if constexpr ((MODE & C_INV) != 0) fft_line<H, P, true>(v, j, line, a.tw);
+
+    if constexpr ((MODE & COUT_TILED) != 0) {
+#pragma unroll
+        for (int t = 0; t < P; ++t) a.X[sb + (size_t)(j + T * t) * kC + c] = v[t];
+    }
+    if constexpr ((MODE & COUT_NAT) != 0) {
+#pragma unroll
+        for (int t = 0; t < P; ++t) a.nat_out[(size_t)(j + T * t) * a.W + s * kC + c] = v[t];
+    }
+}
+
+// Row pass over kGR adjacent rows (one work-group per row group).
+// Lane layout tid = (jhi, rho, c) with c fastest: thread index within the
+// row j = jhi * kC + c, row = group * kGR + rho.  For a fixed t the
+// element (row, j + T t) lies in strip jhi + (T / kC) t at column c, so a
+// wave's loads are runs of kGR * kC contiguous elements.
+template <int W, int MODE>
+__global__ void __launch_bounds__(kGR * LineShape<W>::T)
+k_row(RowParams a) {
+    constexpr int P = LineShape<W>::P;
+    constexpr int T = LineShape<W>::T;
+    constexpr int NT = kGR * T;
+    constexpr int LP = LineShape<W>::LP;
+    static_assert(T % kC == 0, "row threads must cover whole strips");
+    __shared__ float2 lds[kGR * LP];
+    __shared__ double red[(NT + 63) / 64];
+
+    const int tid = threadIdx.x;
+    const int c = tid & (kC - 1);
+    const int rho = (tid / kC) & (kGR - 1);
+    const int jhi = tid / (kC * kGR);
+    const int j = jhi * kC + c;
+    const int row = blockIdx.x * kGR + rho;
+    const size_t H = (size_t)a.H;
+    auto tiled = [&](int t) -> size_t {
+        return ((size_t)(jhi + (T / kC) * t) * H + row) * kC + c;
+    };
+    auto natural = [&](int t) -> size_t { return (size_t)row * W + j + T * t; };
+    float2 v[P];
+
+    if constexpr ((MODE & RIN_PHASE) != 0) {
+        const float* ph = a.io->phase_in;
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            float sn, cs;
+            sincosf(ph[natural(t)], &sn, &cs);
+            v[t] = make_float2(cs, sn);
+        }
+    } else if constexpr ((MODE & RIN_NAT) != 0) {
+#pragma unroll
+        for (int t = 0; t < P; ++t) v[t] = a.nat_in[natural(t)];
+    } else {
+#pragma unroll
+        for (int t = 0; t < P; ++t) v[t] = a.X[tiled(t)];
+    }
+    float2* line = lds + rho * LP;
+
+    if constexpr ((MODE & R_INV) != 0) fft_line<W, P, true>(v, j, line, a.tw);
+
+    if constexpr ((MODE & R_PS) != 0) {
+        // w = P_M u^nu with unit scale (the target was divided by ||m||, so
+        // the unnormalised inverse leaves |w| on the scale of p = 1).
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            const float2 w = v[t];
+            const float a2 = w.x * w.x + w.y * w.y;
+            const double d = (double)sqrtf(a2) - 1.0;
+            acc = fma(d, d, acc);
+            if (a2 >= FLT_MIN) {
+                const float r = rsqrtf(a2);
+                v[t] = make_float2(w.x * r, w.y * r);
+            } else {
+                v[t] = make_float2(1.0f, 0.0f);
+            }
+        }
+        const double tot = block_sum<NT>(acc, red);
+        if (tid == 0) a.part[blockIdx.x] = tot;
+    }
+
+    if constexpr ((MODE & ROUT_PHASE) != 0) {
+        float* out = a.io->phase_out;
+#pragma unroll
+        for (int t = 0; t < P; ++t) out[natural(t)] = atan2f(v[t].y, v[t].x);
+    }
+    if constexpr ((MODE & ROUT_NAT) != 0) {
+#pragma unroll
+        for (int t = 0; t < P; ++t) a.nat_out[natural(t)] = v[t];
+    }
+    if constexpr ((MODE & R_FWD) != 0) {
+        fft_line<W, P, false>(v, j, line, a.tw);
+#pragma unroll
+        for (int t = 0; t < P; ++t) a.X[tiled(t)] = v[t];
+    }
+}
+
+}  // namespace pm

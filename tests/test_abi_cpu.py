@@ -1,0 +1,72 @@
+"""The C-ABI library loads and exports every entry point its header declares;
+host-side argument checks answer without touching the device.  CPU only:
+nothing here launches a kernel."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "phasemask.h")
+LIB = os.path.join(ROOT, "paper_1302_0120_amd", "libphasemask.so")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(phasemask_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libphasemask.so is not built (run python -m paper_1302_0120_amd.build)")
+    import torch  # noqa: F401  (same HIP runtime as the product binding)
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for must in ("phasemask_create", "phasemask_solve", "phasemask_error", "phasemask_destroy"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_the_header():
+    from paper_1302_0120_amd import binding
+    assert sorted(binding._SIGNATURES) == _declared_functions()
+
+
+def test_status_strings(lib):
+    lib.phasemask_status_string.restype = ctypes.c_char_p
+    for code, tag in [(0, b"PM_OK"), (-1, b"PM_EINVAL"), (-2, b"PM_EUNSUPPORTED"),
+                      (-3, b"PM_ENOMEM"), (-4, b"PM_EDEVICE"), (-5, b"PM_ESTATE")]:
+        assert lib.phasemask_status_string(code).startswith(tag)
+
+
+def test_host_side_argument_errors(lib):
+    """Rejected before any HIP call: NULL out, bad sizes, NULL handles."""
+    lib.phasemask_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_uint, ctypes.c_void_p]
+    lib.phasemask_last_error.restype = ctypes.c_char_p
+    h = ctypes.c_void_p(1234)
+    assert lib.phasemask_create(None, 64, 64, 0, None) == -1
+    for hh, ww in [(48, 64), (64, 8), (8192, 64), (64, 0), (-64, 64), (64, 4097)]:
+        assert lib.phasemask_create(ctypes.byref(h), hh, ww, 0, None) == -2
+        assert h.value is None
+        assert b"power" in lib.phasemask_last_error()
+    assert lib.phasemask_create(ctypes.byref(h), 64, 64, 0x80, None) == -1
+    assert lib.phasemask_destroy(None) == -1
+    lib.phasemask_solve.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.phasemask_solve(None, None, None, 1, None, None) == -1
+    assert lib.phasemask_error(None, None, None, None) == -1
+    assert lib.phasemask_fft2(None, None, None, 0) == -1
+    assert lib.phasemask_set_stream(None, None) == -1
+    lib.phasemask_workspace_bytes.restype = ctypes.c_size_t
+    assert lib.phasemask_workspace_bytes(None) == 0
