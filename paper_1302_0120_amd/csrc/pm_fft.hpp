@@ -17,7 +17,8 @@
 //     first read / last write can go straight to or from global memory.
 //   * Radix sequence: P, P, ..., then the remaining factor (each divides P).
 //   * Twiddles come from a table tw[i] = exp(-2 pi i i / L) computed on the
-//     host in double precision and rounded once to float.
+//     host in double precision and rounded once to float; each thread loads
+//     the ones it needs into registers at kernel start.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -133,18 +134,67 @@ __device__ __forceinline__ void dft(float2 (&x)[R]) {
 }
 
 // Padded LDS index: one spare element after every 16, against bank conflicts
-// of the strided Stockham writes.
+// of the strided Stockham writes.  Lines of one work-group are a further 8
+// elements apart (16 banks), so the 4 lines that share a wave fall on
+// different banks.
 __device__ __forceinline__ constexpr int lds_pad(int i) { return i + (i >> 4); }
-__host__ __device__ constexpr int lds_line_len(int L) { return L + L / 16; }
+#ifndef PM_LDS_LINE_EXTRA
+#define PM_LDS_LINE_EXTRA 8
+#endif
+__host__ __device__ constexpr int lds_line_len(int L) { return L + L / 16 + PM_LDS_LINE_EXTRA; }
 
 // Radix of the stage that starts at sub-transform length NS.
 __host__ __device__ constexpr int stage_radix(int L, int P, int NS) {
     return (L / NS) >= P ? P : (L / NS);
 }
 
-// One Stockham stage on the thread's P register points (see header).
-template <int L, int P, int NS, bool INV>
-__device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, const float2* __restrict__ tw) {
+// Twiddles a thread multiplies in the stages that start at NS and later:
+// (P/R)(R-1) per stage with NS > 1.
+__host__ __device__ constexpr int twiddles_from(int L, int P, int NS) {
+    return NS >= L ? 0
+                   : (NS > 1 ? (P / stage_radix(L, P, NS)) * (stage_radix(L, P, NS) - 1) : 0) +
+                         twiddles_from(L, P, NS * stage_radix(L, P, NS));
+}
+
+// The thread's twiddle factors for a whole line transform, loaded once from
+// the table before any barrier (so their latency overlaps the data loads);
+// the inverse transform uses their conjugates.
+template <int L, int P>
+struct LineTwiddles {
+    static constexpr int COUNT = twiddles_from(L, P, 1) > 0 ? twiddles_from(L, P, 1) : 1;
+    float2 w[COUNT];
+};
+
+template <int L, int P, int NS, int OFF>
+__device__ __forceinline__ void load_twiddles_from(LineTwiddles<L, P>& tw, int j, const float2* __restrict__ table) {
+    if constexpr (NS < L) {
+        constexpr int T = L / P;
+        constexpr int R = stage_radix(L, P, NS);
+        constexpr int M = P / R;
+        if constexpr (NS > 1) {
+            constexpr int STRIDE = L / (NS * R);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int k = (j + T * m) & (NS - 1);
+#pragma unroll
+                for (int q = 1; q < R; ++q) tw.w[OFF + m * (R - 1) + (q - 1)] = table[q * k * STRIDE];
+            }
+            load_twiddles_from<L, P, NS * R, OFF + M * (R - 1)>(tw, j, table);
+        } else {
+            load_twiddles_from<L, P, NS * R, OFF>(tw, j, table);
+        }
+    }
+}
+
+template <int L, int P>
+__device__ __forceinline__ void load_twiddles(LineTwiddles<L, P>& tw, int j, const float2* __restrict__ table) {
+    load_twiddles_from<L, P, 1, 0>(tw, j, table);
+}
+
+// One Stockham stage on the thread's P register points (see header); OFF is
+// this stage's first entry in the thread's twiddle registers.
+template <int L, int P, int NS, int OFF, bool INV>
+__device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, const LineTwiddles<L, P>& tw) {
     constexpr int T = L / P;
     constexpr int R = stage_radix(L, P, NS);
     constexpr int M = P / R;
@@ -157,10 +207,9 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, c
         const int b = j + T * m;
         const int k = b & (NS - 1);
         if constexpr (NS > 1) {
-            constexpr int STRIDE = L / (NS * R);
 #pragma unroll
             for (int q = 1; q < R; ++q) {
-                float2 w = tw[q * k * STRIDE];
+                float2 w = tw.w[OFF + m * (R - 1) + (q - 1)];
                 if constexpr (INV) w.y = -w.y;
                 x[q] = cmul(x[q], w);
             }
@@ -180,15 +229,15 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, c
 #pragma unroll
         for (int t = 0; t < P; ++t) v[t] = line[lds_pad(j + T * t)];
         __syncthreads();
-        fft_stage<L, P, NS * R, INV>(v, j, line, tw);
+        fft_stage<L, P, NS * R, (NS > 1 ? OFF + M * (R - 1) : OFF), INV>(v, j, line, tw);
     }
 }
 
 // Full length-L transform of one line; every thread of the work-group must
 // call it (it contains work-group barriers).
 template <int L, int P, bool INV>
-__device__ __forceinline__ void fft_line(float2 (&v)[P], int j, float2* line, const float2* __restrict__ tw) {
-    fft_stage<L, P, 1, INV>(v, j, line, tw);
+__device__ __forceinline__ void fft_line(float2 (&v)[P], int j, float2* line, const LineTwiddles<L, P>& tw) {
+    fft_stage<L, P, 1, 0, INV>(v, j, line, tw);
 }
 
 // Points per thread for a line of L points.

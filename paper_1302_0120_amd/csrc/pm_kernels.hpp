@@ -69,6 +69,13 @@ k_col(ColParams a) {
     const int j = tid / kC;
     const int s = blockIdx.x;
     const size_t sb = (size_t)s * H * kC;
+    LineTwiddles<H, P> tw;
+    load_twiddles(tw, j, a.tw);
+    float mt[P];
+    if constexpr ((MODE & (C_PROJ | C_ERR)) != 0) {
+#pragma unroll
+        for (int t = 0; t < P; ++t) mt[t] = a.mhat[sb + (size_t)(j + T * t) * kC + c];
+    }
     float2 v[P];
 
     if constexpr ((MODE & CIN_NAT) != 0) {
@@ -80,7 +87,7 @@ k_col(ColParams a) {
     }
     float2* line = lds + c * LP;
 
-    if constexpr ((MODE & C_FWD) != 0) fft_line<H, P, false>(v, j, line, a.tw);
+    if constexpr ((MODE & C_FWD) != 0) fft_line<H, P, false>(v, j, line, tw);
 
     if constexpr ((MODE & (C_PROJ | C_ERR)) != 0) {
         // U = unnormalised DFT of u, so |U|/N is the unitary modulus over
@@ -88,7 +95,7 @@ k_col(ColParams a) {
         double acc = 0.0;
 #pragma unroll
         for (int t = 0; t < P; ++t) {
-            const float m = a.mhat[sb + (size_t)(j + T * t) * kC + c];
+            const float m = mt[t];
             const float2 U = v[t];
             const float a2 = U.x * U.x + U.y * U.y;
             const double d = (double)sqrtf(a2) * a.invN - (double)m;
@@ -106,7 +113,7 @@ k_col(ColParams a) {
         if (tid == 0) a.part[blockIdx.x] = tot;
     }
 
-    if constexpr ((MODE & C_INV) != 0) fft_line<H, P, true>(v, j, line, a.tw);
+    if constexpr ((MODE & C_INV) != 0) fft_line<H, P, true>(v, j, line, tw);
 
     if constexpr ((MODE & COUT_TILED) != 0) {
 #pragma unroll
@@ -145,6 +152,8 @@ k_row(RowParams a) {
         return ((size_t)(jhi + (T / kC) * t) * H + row) * kC + c;
     };
     auto natural = [&](int t) -> size_t { return (size_t)row * W + j + T * t; };
+    LineTwiddles<W, P> tw;
+    load_twiddles(tw, j, a.tw);
     float2 v[P];
 
     if constexpr ((MODE & RIN_PHASE) != 0) {
@@ -164,7 +173,7 @@ k_row(RowParams a) {
     }
     float2* line = lds + rho * LP;
 
-    if constexpr ((MODE & R_INV) != 0) fft_line<W, P, true>(v, j, line, a.tw);
+    if constexpr ((MODE & R_INV) != 0) fft_line<W, P, true>(v, j, line, tw);
 
     if constexpr ((MODE & R_PS) != 0) {
         // w = P_M u^nu with unit scale (the target was divided by ||m||, so
@@ -197,7 +206,7 @@ k_row(RowParams a) {
         for (int t = 0; t < P; ++t) a.nat_out[natural(t)] = v[t];
     }
     if constexpr ((MODE & R_FWD) != 0) {
-        fft_line<W, P, false>(v, j, line, a.tw);
+        fft_line<W, P, false>(v, j, line, tw);
 #pragma unroll
         for (int t = 0; t < P; ++t) a.X[tiled(t)] = v[t];
     }
