@@ -43,6 +43,17 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     }
 }
 
+// Store of one iterate element that the next pass reads on other XCDs: a
+// relaxed device-scope store writes through this XCD's L2, so the data is in
+// the shared Infinity Cache when the kernel ends instead of waiting for the
+// end-of-kernel L2 write-back (about 1.5 us per pass at 1024 x 1024).
+__device__ __forceinline__ void store_shared(float2* p, float2 v) {
+    const unsigned long long bits =
+        ((unsigned long long)__float_as_uint(v.y) << 32) | (unsigned long long)__float_as_uint(v.x);
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), bits, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int L>
 struct LineShape {
     static constexpr int P = points_per_thread(L);  // points per thread
@@ -117,7 +128,7 @@ k_col(ColParams a) {
 
     if constexpr ((MODE & COUT_TILED) != 0) {
 #pragma unroll
-        for (int t = 0; t < P; ++t) a.X[sb + (size_t)(j + T * t) * kC + c] = v[t];
+        for (int t = 0; t < P; ++t) store_shared(&a.X[sb + (size_t)(j + T * t) * kC + c], v[t]);
     }
     if constexpr ((MODE & COUT_NAT) != 0) {
 #pragma unroll
@@ -208,7 +219,7 @@ k_row(RowParams a) {
     if constexpr ((MODE & R_FWD) != 0) {
         fft_line<W, P, false>(v, j, line, tw);
 #pragma unroll
-        for (int t = 0; t < P; ++t) a.X[tiled(t)] = v[t];
+        for (int t = 0; t < P; ++t) store_shared(&a.X[tiled(t)], v[t]);
     }
 }
 
