@@ -191,14 +191,33 @@ __device__ __forceinline__ void load_twiddles(LineTwiddles<L, P>& tw, int j, con
     load_twiddles_from<L, P, 1, 0>(tw, j, table);
 }
 
+// LDS exchange buffers per line: two (alternating, one barrier per
+// exchange) when that leaves room for two work-groups per CU, else one (two
+// barriers per exchange).  `stride` is the distance between the buffers.
+template <int L, int G>
+struct LdsPlan {
+    static constexpr int LP = lds_line_len(L);
+    static constexpr int NBUF = (2 * G * LP * 8 <= 80 * 1024) ? 2 : 1;
+    static constexpr int FLOATS2 = NBUF * G * LP;  // float2 elements per work-group
+    static constexpr int STRIDE = G * LP;
+};
+
+// Number of LDS exchanges in one line transform (= stages - 1).
+__host__ __device__ constexpr int exchanges_from(int L, int P, int NS) {
+    return NS * stage_radix(L, P, NS) >= L ? 0 : 1 + exchanges_from(L, P, NS * stage_radix(L, P, NS));
+}
+
 // One Stockham stage on the thread's P register points (see header); OFF is
-// this stage's first entry in the thread's twiddle registers.
-template <int L, int P, int NS, int OFF, bool INV>
-__device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, const LineTwiddles<L, P>& tw) {
+// this stage's first entry in the thread's twiddle registers, PAR the LDS
+// buffer this stage's exchange uses when NBUF == 2.
+template <int L, int P, int NS, int OFF, bool INV, int NBUF, int PAR>
+__device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, int stride,
+                                          const LineTwiddles<L, P>& tw) {
     constexpr int T = L / P;
     constexpr int R = stage_radix(L, P, NS);
     constexpr int M = P / R;
     constexpr bool LAST = (NS * R == L);
+    float2* buf = (NBUF == 2 && PAR == 1) ? line + stride : line;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         float2 x[R];
@@ -221,23 +240,35 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, c
         } else {
             const int base = (b - k) * R + k;
 #pragma unroll
-            for (int q = 0; q < R; ++q) line[lds_pad(base + q * NS)] = x[q];
+            for (int q = 0; q < R; ++q) buf[lds_pad(base + q * NS)] = x[q];
         }
     }
     if constexpr (!LAST) {
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < P; ++t) v[t] = line[lds_pad(j + T * t)];
-        __syncthreads();
-        fft_stage<L, P, NS * R, (NS > 1 ? OFF + M * (R - 1) : OFF), INV>(v, j, line, tw);
+        for (int t = 0; t < P; ++t) v[t] = buf[lds_pad(j + T * t)];
+        // With one buffer the next stage's writes must wait for every read;
+        // with two they go to the other buffer, whose last reads finished
+        // before the barrier above.
+        if constexpr (NBUF == 1) __syncthreads();
+        fft_stage<L, P, NS * R, (NS > 1 ? OFF + M * (R - 1) : OFF), INV, NBUF, PAR ^ 1>(v, j, line,
+                                                                                     stride, tw);
     }
 }
 
 // Full length-L transform of one line; every thread of the work-group must
-// call it (it contains work-group barriers).
-template <int L, int P, bool INV>
-__device__ __forceinline__ void fft_line(float2 (&v)[P], int j, float2* line, const LineTwiddles<L, P>& tw) {
-    fft_stage<L, P, 1, 0, INV>(v, j, line, tw);
+// call it (it contains work-group barriers).  Consecutive transforms in one
+// kernel must pass PAR = the parity after the previous one
+// (fft_parity_after) so that the buffers keep alternating.
+template <int L, int P, bool INV, int NBUF, int PAR>
+__device__ __forceinline__ void fft_line(float2 (&v)[P], int j, float2* line, int stride,
+                                         const LineTwiddles<L, P>& tw) {
+    fft_stage<L, P, 1, 0, INV, NBUF, PAR>(v, j, line, stride, tw);
+}
+
+template <int L, int P, int PAR>
+__host__ __device__ constexpr int fft_parity_after() {
+    return (PAR + exchanges_from(L, P, 1)) & 1;
 }
 
 // Points per thread for a line of L points.

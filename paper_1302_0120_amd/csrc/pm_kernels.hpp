@@ -72,7 +72,8 @@ k_col(ColParams a) {
     constexpr int T = LineShape<H>::T;
     constexpr int NT = kC * T;
     constexpr int LP = LineShape<H>::LP;
-    __shared__ float2 lds[kC * LP];
+    using LD = LdsPlan<H, kC>;
+    __shared__ float2 lds[LD::FLOATS2];
     __shared__ double red[(NT + 63) / 64];
 
     const int tid = threadIdx.x;
@@ -98,7 +99,8 @@ k_col(ColParams a) {
     }
     float2* line = lds + c * LP;
 
-    if constexpr ((MODE & C_FWD) != 0) fft_line<H, P, false>(v, j, line, tw);
+    constexpr int PAR1 = (MODE & C_FWD) != 0 ? fft_parity_after<H, P, 0>() : 0;
+    if constexpr ((MODE & C_FWD) != 0) fft_line<H, P, false, LD::NBUF, 0>(v, j, line, LD::STRIDE, tw);
 
     if constexpr ((MODE & (C_PROJ | C_ERR)) != 0) {
         // U = unnormalised DFT of u, so |U|/N is the unitary modulus over
@@ -109,22 +111,23 @@ k_col(ColParams a) {
             const float m = mt[t];
             const float2 U = v[t];
             const float a2 = U.x * U.x + U.y * U.y;
-            const double d = (double)sqrtf(a2) * a.invN - (double)m;
+            // |U|^2 >= FLT_MIN excludes denormals, so the raw hardware
+            // reciprocal square root applies; below it the tie-break of
+            // Eq. 5 takes phase 0 and |U| counts as 0.
+            const bool nz = a2 >= FLT_MIN;
+            const float r = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
+            const double d = (double)(a2 * r) * a.invN - (double)m;
             acc = fma(d, d, acc);
             if constexpr ((MODE & C_PROJ) != 0) {
-                if (a2 >= FLT_MIN) {
-                    const float r = m * rsqrtf(a2);
-                    v[t] = make_float2(U.x * r, U.y * r);
-                } else {
-                    v[t] = make_float2(m, 0.0f);
-                }
+                const float q = m * r;
+                v[t] = nz ? make_float2(U.x * q, U.y * q) : make_float2(m, 0.0f);
             }
         }
         const double tot = block_sum<NT>(acc, red);
         if (tid == 0) a.part[blockIdx.x] = tot;
     }
 
-    if constexpr ((MODE & C_INV) != 0) fft_line<H, P, true>(v, j, line, tw);
+    if constexpr ((MODE & C_INV) != 0) fft_line<H, P, true, LD::NBUF, PAR1>(v, j, line, LD::STRIDE, tw);
 
     if constexpr ((MODE & COUT_TILED) != 0) {
 #pragma unroll
@@ -149,7 +152,8 @@ k_row(RowParams a) {
     constexpr int NT = kGR * T;
     constexpr int LP = LineShape<W>::LP;
     static_assert(T % kC == 0, "row threads must cover whole strips");
-    __shared__ float2 lds[kGR * LP];
+    using LD = LdsPlan<W, kGR>;
+    __shared__ float2 lds[LD::FLOATS2];
     __shared__ double red[(NT + 63) / 64];
 
     const int tid = threadIdx.x;
@@ -184,7 +188,8 @@ k_row(RowParams a) {
     }
     float2* line = lds + rho * LP;
 
-    if constexpr ((MODE & R_INV) != 0) fft_line<W, P, true>(v, j, line, tw);
+    constexpr int PAR1 = (MODE & R_INV) != 0 ? fft_parity_after<W, P, 0>() : 0;
+    if constexpr ((MODE & R_INV) != 0) fft_line<W, P, true, LD::NBUF, 0>(v, j, line, LD::STRIDE, tw);
 
     if constexpr ((MODE & R_PS) != 0) {
         // w = P_M u^nu with unit scale (the target was divided by ||m||, so
@@ -194,14 +199,12 @@ k_row(RowParams a) {
         for (int t = 0; t < P; ++t) {
             const float2 w = v[t];
             const float a2 = w.x * w.x + w.y * w.y;
-            const double d = (double)sqrtf(a2) - 1.0;
+            // Tie-break of Eq. 4a below FLT_MIN (phase 0), as in the column pass.
+            const bool nz = a2 >= FLT_MIN;
+            const float r = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
+            const double d = (double)(a2 * r) - 1.0;
             acc = fma(d, d, acc);
-            if (a2 >= FLT_MIN) {
-                const float r = rsqrtf(a2);
-                v[t] = make_float2(w.x * r, w.y * r);
-            } else {
-                v[t] = make_float2(1.0f, 0.0f);
-            }
+            v[t] = nz ? make_float2(w.x * r, w.y * r) : make_float2(1.0f, 0.0f);
         }
         const double tot = block_sum<NT>(acc, red);
         if (tid == 0) a.part[blockIdx.x] = tot;
@@ -217,7 +220,7 @@ k_row(RowParams a) {
         for (int t = 0; t < P; ++t) a.nat_out[natural(t)] = v[t];
     }
     if constexpr ((MODE & R_FWD) != 0) {
-        fft_line<W, P, false>(v, j, line, tw);
+        fft_line<W, P, false, LD::NBUF, PAR1>(v, j, line, LD::STRIDE, tw);
 #pragma unroll
         for (int t = 0; t < P; ++t) store_shared(&a.X[tiled(t)], v[t]);
     }
