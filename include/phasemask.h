@@ -138,6 +138,41 @@ pm_status phasemask_error(pm_handle h, const float* target_amplitude,
 pm_status phasemask_fft2(pm_handle h, const void* in, void* out, int inverse);
 
 /*
+ * Batched plans: `count` independent masks of uneven sizes solved together,
+ * e.g. the masks of one frame of an interactive stimulation loop (the paper
+ * asks for frame rates of 0.1 to 1 kHz, Sec. I).  Every iteration of Eq. 6
+ * runs as one column-pass launch and one row-pass launch over all masks;
+ * the whole solve is one captured graph.
+ *   heights, widths   HOST arrays of `count` sizes, each a power of two in
+ *                     [64, 1024] (else PM_EUNSUPPORTED).
+ * Errors: PM_EINVAL for NULL arguments or count < 1; PM_ENOMEM; PM_EDEVICE.
+ * A batched handle works with phasemask_solve_batched, phasemask_set_stream,
+ * phasemask_workspace_bytes and phasemask_destroy; other entry points
+ * return PM_ESTATE for it.
+ */
+pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights,
+                                   const int* widths, unsigned flags, void* stream);
+
+/*
+ * n_iter iterations of Eq. 6 for every mask of a batched plan.
+ *   targets, init_phases, out_phases   DEVICE arrays of `count` device
+ *                     pointers (8-byte aligned), entry i pointing at mask i's
+ *                     float[height_i * width_i] image, laid out and
+ *                     constrained as for phasemask_solve (targets 16-byte
+ *                     aligned; out_phases[i] may alias init_phases[i]).
+ *   final_err         NULL, or DEVICE double[count] receiving E_F^n of each
+ *                     returned mask (the last history entry of a one-mask
+ *                     solve).
+ * Results equal `count` separate phasemask_solve calls on the same inputs
+ * (the phases bitwise; the errors up to the order of the FP64 sums).
+ * Errors: PM_EINVAL for NULL pointer arrays, n_iter < 0 or misaligned
+ * arguments; PM_ESTATE for a one-mask handle; PM_EDEVICE.
+ */
+pm_status phasemask_solve_batched(pm_handle h, const float* const* targets,
+                                  const float* const* init_phases, int n_iter,
+                                  float* const* out_phases, double* final_err);
+
+/*
  * Measurement (roofline accounting of the two passes that run n_iter times,
  * Eq. 6): average device duration in milliseconds of one column pass
  * (forward column FFT, Eq. 5 projection, inverse column FFT) and of one row

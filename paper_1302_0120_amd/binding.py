@@ -26,6 +26,11 @@ _SIGNATURES = {
                                        ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_error": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_fft2": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "phasemask_create_batched": (ctypes.c_int, [ctypes.POINTER(_c_handle), ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                                ctypes.c_uint, ctypes.c_void_p]),
+    "phasemask_solve_batched": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                               ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_time_passes": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                              ctypes.POINTER(ctypes.c_float),
                                              ctypes.POINTER(ctypes.c_float)]),
@@ -151,6 +156,76 @@ class PhaseMask:
         _check(lib.phasemask_time_passes(self._h, tp, pp, int(reps), ctypes.byref(c), ctypes.byref(r)),
                "phasemask_time_passes")
         return float(c.value), float(r.value)
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(lib.phasemask_workspace_bytes(self._h)) if self._h is not None else 0
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _check(lib.phasemask_destroy(self._h), "phasemask_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchedPhaseMask:
+    """One plan for a batch of masks of uneven sizes (powers of two in
+    [64, 1024] per side), solved together (see include/phasemask.h)."""
+
+    def __init__(self, shapes, flags: int = 0, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        self.shapes = [(int(h), int(w)) for h, w in shapes]
+        n = len(self.shapes)
+        hs = (ctypes.c_int * n)(*[h for h, _ in self.shapes])
+        ws = (ctypes.c_int * n)(*[w for _, w in self.shapes])
+        h = _c_handle()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            _check(lib.phasemask_create_batched(ctypes.byref(h), n, hs, ws, flags, stream),
+                   "phasemask_create_batched")
+        self._h = h
+        self._ptr_cache: dict = {}
+
+    def _ptr_array(self, tensors, dtype, name):
+        ptrs = tuple(_dev_ptr(t, dtype, shp, f"{name}[{i}]")
+                     for i, (t, shp) in enumerate(zip(tensors, self.shapes)))
+        arr = self._ptr_cache.get(ptrs)
+        if arr is None:
+            if len(self._ptr_cache) > 64:
+                self._ptr_cache.clear()
+            arr = torch.tensor(ptrs, dtype=torch.int64).to(self.device)
+            self._ptr_cache[ptrs] = arr
+        return arr
+
+    def solve(self, targets, init_phases, n_iter: int, outs=None, final_err: bool | torch.Tensor = True):
+        """n_iter GS iterations for every mask; returns (list of phases,
+        final E_F per mask as a float64 device tensor, or None)."""
+        if len(targets) != len(self.shapes) or len(init_phases) != len(self.shapes):
+            raise ValueError(f"expected {len(self.shapes)} targets and phases")
+        if outs is None:
+            outs = [torch.empty(shp, dtype=torch.float32, device=self.device) for shp in self.shapes]
+        tp = self._ptr_array(targets, torch.float32, "targets")
+        pp = self._ptr_array(init_phases, torch.float32, "init_phases")
+        op = self._ptr_array(outs, torch.float32, "outs")
+        err = None
+        if isinstance(final_err, torch.Tensor):
+            err = final_err
+        elif final_err:
+            err = torch.empty(len(self.shapes), dtype=torch.float64, device=self.device)
+        ep = 0 if err is None else _dev_ptr(err, torch.float64, (len(self.shapes),), "final_err")
+        if self._h is None:
+            raise PhaseMaskError(-5, "use after close")
+        _check(lib.phasemask_set_stream(self._h, torch.cuda.current_stream(self.device).cuda_stream),
+               "phasemask_set_stream")
+        _check(lib.phasemask_solve_batched(self._h, tp.data_ptr(), pp.data_ptr(), int(n_iter),
+                                           op.data_ptr(), ep or None), "phasemask_solve_batched")
+        return outs, err
 
     @property
     def workspace_bytes(self) -> int:

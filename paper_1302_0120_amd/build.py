@@ -54,6 +54,10 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         obj = os.path.join(BUILD, f"pm_pass_{L}.o")
         steps.append([hipcc, *HIPFLAGS, f"-DPM_L={L}", "-c",
                       os.path.join(CSRC, "pm_pass.hip"), "-o", obj])
+    for which in range(6):
+        steps.append([hipcc, *HIPFLAGS, f"-DPM_BATCH_WHICH={which}", "-c",
+                      os.path.join(CSRC, "pm_batch.hip"),
+                      "-o", os.path.join(BUILD, f"pm_batch_{which}.o")])
     steps.append([hipcc, *HIPFLAGS, "-c", os.path.join(CSRC, "pm_aux.hip"),
                   "-o", os.path.join(BUILD, "pm_aux.o")])
     steps.append([hipcc, *HIPFLAGS, "-x", "hip", "-c", os.path.join(CSRC, "phasemask.cpp"),

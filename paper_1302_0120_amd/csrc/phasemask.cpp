@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <list>
 #include <new>
 #include <string>
@@ -79,6 +80,19 @@ struct pm_plan {
     size_t ws_bytes = 0;
     std::list<GraphEntry> graphs;      // most recently used first
     bool dead = false;
+
+    // Batched plans (phasemask_create_batched) only.
+    bool batched = false;
+    int count = 0;
+    int n_col_tasks = 0, n_row_tasks = 0, n_prep_tasks = 0;
+    void* batch_ws = nullptr;          // iterates and rescaled targets of every mask
+    pm::BatchMask* masks = nullptr;
+    pm::BatchTask* col_tasks = nullptr;
+    pm::BatchTask* row_tasks = nullptr;
+    pm::BatchTask* prep_tasks = nullptr;
+    int* mask_prep0 = nullptr;
+    pm::BatchIo* bio = nullptr;
+    float2* tw_batch = nullptr;
 };
 
 namespace {
@@ -90,6 +104,14 @@ void drop_graphs(pm_plan* h) {
 
 void free_plan(pm_plan* h) {
     drop_graphs(h);
+    (void)hipFree(h->batch_ws);
+    (void)hipFree(h->masks);
+    (void)hipFree(h->col_tasks);
+    (void)hipFree(h->row_tasks);
+    (void)hipFree(h->prep_tasks);
+    (void)hipFree(h->mask_prep0);
+    (void)hipFree(h->bio);
+    (void)hipFree(h->tw_batch);
     (void)hipFree(h->X);
     (void)hipFree(h->mhat);
     (void)hipFree(h->twW);
@@ -101,9 +123,11 @@ void free_plan(pm_plan* h) {
     delete h;
 }
 
-pm_status check_handle(pm_plan* h) {
+pm_status check_handle(pm_plan* h, bool batched = false) {
     if (h == nullptr) return fail(PM_EINVAL, "null handle");
     if (h->dead) return fail(PM_ESTATE, "handle is in an unusable state");
+    if (h->batched != batched)
+        return fail(PM_ESTATE, batched ? "handle is not a batched plan" : "handle is a batched plan");
     return PM_OK;
 }
 
@@ -140,6 +164,7 @@ pm::RowParams row_params(pm_plan* h, double* part) {
     pm::RowParams r{};
     r.X = h->X;
     r.tw = h->twW;
+    r.tw_step = 1;
     r.io = h->io;
     r.part = part;
     r.H = h->H;
@@ -151,6 +176,7 @@ pm::ColParams col_params(pm_plan* h, double* part) {
     c.X = h->X;
     c.mhat = h->mhat;
     c.tw = h->twH;
+    c.tw_step = 1;
     c.part = part;
     c.W = h->W;
     c.invN = 1.0 / (double)h->N;
@@ -192,10 +218,13 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist) {
     pm_status st = enqueue_target(h, s);
     if (st != PM_OK) return st;
     PM_TRY(row(pm::ROW_INIT, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+    // Without a history the passes skip their error partial sums.
+    const int col_mode = hist ? pm::COL_ITER : pm::COL_ITER_NE;
+    const int row_mode = hist ? pm::ROW_ITER : pm::ROW_ITER_NE;
     for (int nu = 0; nu < n_iter; ++nu) {
-        PM_TRY(col(pm::COL_ITER, col_params(h, pe(2 * nu)), h->nwg_col, s, nullptr, nullptr), "column pass");
+        PM_TRY(col(col_mode, col_params(h, pe(2 * nu)), h->nwg_col, s, nullptr, nullptr), "column pass");
         const bool last = nu == n_iter - 1;
-        const int mode = !last ? pm::ROW_ITER : (hist ? pm::ROW_LAST_FWD : pm::ROW_LAST);
+        const int mode = !last ? row_mode : (hist ? pm::ROW_LAST_FWD : pm::ROW_LAST_NE);
         PM_TRY(row(mode, row_params(h, pe(2 * nu + 1)), h->nwg_row, s, nullptr, nullptr), "row pass");
     }
     if (hist) {
@@ -206,6 +235,8 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist) {
     }
     return PM_OK;
 }
+
+pm_status enqueue_batch(pm_plan* h, hipStream_t s, int n_iter, bool err);
 
 // Replays (capturing on first use) the graph of one solve shape.
 pm_status launch_graph(pm_plan* h, int n_iter, bool hist) {
@@ -218,7 +249,8 @@ pm_status launch_graph(pm_plan* h, int n_iter, bool hist) {
     }
     hipGraph_t graph = nullptr;
     PM_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    pm_status st = enqueue_solve(h, h->cap_stream, n_iter, hist);
+    pm_status st = h->batched ? enqueue_batch(h, h->cap_stream, n_iter, hist)
+                              : enqueue_solve(h, h->cap_stream, n_iter, hist);
     hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
     if (st != PM_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -235,6 +267,58 @@ pm_status launch_graph(pm_plan* h, int n_iter, bool hist) {
     }
     h->graphs.push_front(GraphEntry{n_iter, hist, exec});
     PM_TRY(hipGraphLaunch(exec, h->stream), "hipGraphLaunch");
+    return PM_OK;
+}
+
+// ----- batched solves ----------------------------------------------------------
+
+// Lines per work-group of the batched passes for a transform of length L
+// (kBatchThreads threads, points_per_thread(L) points each).
+int batch_lines(int L) {
+    const int P = L >= 256 ? 16 : (L >= 32 ? 8 : 4);
+    return pm::kBatchThreads / (L / P);
+}
+
+bool batch_len_ok(int n) {
+    return n >= pm::kBatchMinLen && n <= pm::kBatchMaxLen && (n & (n - 1)) == 0;
+}
+
+pm::BatchParams batch_params(pm_plan* h, const pm::BatchTask* tasks) {
+    pm::BatchParams p{};
+    p.masks = h->masks;
+    p.tasks = tasks;
+    p.tw = h->tw_batch;
+    p.io = h->bio;
+    p.part = h->part;
+    return p;
+}
+
+// Whole batched solve after the pointer block is set.
+pm_status enqueue_batch(pm_plan* h, hipStream_t s, int n_iter, bool err) {
+    const pm::BatchParams pc = batch_params(h, h->col_tasks);
+    const pm::BatchParams pr = batch_params(h, h->row_tasks);
+    if (n_iter == 0) {
+        PM_TRY(pm::launch_batch_wrap(h->bio, h->masks, h->prep_tasks, h->n_prep_tasks, s), "batch wrap");
+        if (!err) return PM_OK;
+    }
+    PM_TRY(pm::launch_batch_norm(h->bio, h->prep_tasks, h->n_prep_tasks, h->part_m, s), "batch norm");
+    PM_TRY(pm::launch_batch_tile(h->bio, h->masks, h->prep_tasks, h->n_prep_tasks, h->mask_prep0, h->part_m, s),
+           "batch tile");
+    PM_TRY(pm::launch_batch_row<pm::ROW_INIT>(pr, h->n_row_tasks, s), "batch row init");
+    for (int nu = 0; nu < n_iter; ++nu) {
+        PM_TRY(pm::launch_batch_col<pm::COL_ITER_NE>(pc, h->n_col_tasks, s), "batch column pass");
+        if (nu < n_iter - 1) {
+            PM_TRY(pm::launch_batch_row<pm::ROW_ITER_NE>(pr, h->n_row_tasks, s), "batch row pass");
+        } else if (err) {
+            PM_TRY(pm::launch_batch_row<pm::ROW_LAST_FWD_NE>(pr, h->n_row_tasks, s), "batch last row pass");
+        } else {
+            PM_TRY(pm::launch_batch_row<pm::ROW_LAST_NE>(pr, h->n_row_tasks, s), "batch last row pass");
+        }
+    }
+    if (err) {
+        PM_TRY(pm::launch_batch_col<pm::COL_ERR>(pc, h->n_col_tasks, s), "batch column error");
+        PM_TRY(pm::launch_batch_finalize(h->bio, h->masks, h->count, h->part, s), "batch finalize");
+    }
     return PM_OK;
 }
 
@@ -316,7 +400,7 @@ pm_status phasemask_destroy(pm_handle h) {
 }
 
 pm_status phasemask_set_stream(pm_handle h, void* stream) {
-    pm_status st = check_handle(h);
+    pm_status st = check_handle(h, h != nullptr && h->batched);
     if (st != PM_OK) return st;
     h->stream = (hipStream_t)stream;
     return PM_OK;
@@ -391,6 +475,116 @@ pm_status phasemask_fft2(pm_handle h, const void* in, void* out, int inverse) {
         PM_TRY(row(pm::ROW_FFT_INV, rp, h->nwg_row, s, nullptr, nullptr), "row ifft");
     }
     return PM_OK;
+}
+
+pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights, const int* widths,
+                                   unsigned flags, void* stream) {
+    if (out == nullptr) return fail(PM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || heights == nullptr || widths == nullptr) return fail(PM_EINVAL, "need count >= 1 and sizes");
+    if ((flags & ~PM_FLAG_NO_GRAPH) != 0) return fail(PM_EINVAL, "unknown flag bits");
+    for (int i = 0; i < count; ++i)
+        if (!batch_len_ok(heights[i]) || !batch_len_ok(widths[i]))
+            return fail(PM_EUNSUPPORTED, "batched sizes must be powers of two in [64, 1024]");
+    pm_plan* h = new (std::nothrow) pm_plan;
+    if (h == nullptr) return fail(PM_ENOMEM, "host allocation failed");
+    h->batched = true;
+    h->count = count;
+    h->flags = flags;
+    h->stream = (hipStream_t)stream;
+    auto bail = [&](hipError_t e, const char* what) {
+        pm_status st = fail_hip(e, what);
+        free_plan(h);
+        return st;
+    };
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) return bail(e, "hipGetDevice");
+
+    // Work order: larger masks first, so their work-groups start first.
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (long)heights[a] * widths[a] > (long)heights[b] * widths[b];
+    });
+    std::vector<pm::BatchMask> masks(count);
+    std::vector<pm::BatchTask> col, row, prep;
+    std::vector<int> prep0(count);
+    size_t off = 0;
+    std::vector<size_t> xoff(count), moff(count);
+    for (int i = 0; i < count; ++i) {
+        const size_t n = (size_t)heights[i] * widths[i];
+        xoff[i] = off;
+        off += ((n * sizeof(float2) + 255) / 256) * 256;
+        moff[i] = off;
+        off += ((n * sizeof(float) + 255) / 256) * 256;
+    }
+    for (int i : order) {
+        const int H = heights[i], W = widths[i];
+        pm::BatchMask& mk = masks[i];
+        mk.H = H;
+        mk.W = W;
+        const int gc = batch_lines(H) / pm::kC;  // strips per column work-group
+        mk.col_wg0 = (int)col.size();
+        for (int s0 = 0; s0 < W / pm::kC; s0 += gc) col.push_back(pm::BatchTask{i, s0});
+        mk.col_wgs = (int)col.size() - mk.col_wg0;
+        const int gr = batch_lines(W);
+        for (int r0 = 0; r0 < H; r0 += gr) row.push_back(pm::BatchTask{i, r0});
+        prep0[i] = (int)prep.size();
+        for (int p0 = 0; p0 < H * W; p0 += pm::kPrepPixels) prep.push_back(pm::BatchTask{i, p0});
+    }
+    h->n_col_tasks = (int)col.size();
+    h->n_row_tasks = (int)row.size();
+    h->n_prep_tasks = (int)prep.size();
+    if ((e = hipMalloc(&h->batch_ws, off)) != hipSuccess) return bail(e, "hipMalloc(batch workspace)");
+    for (int i = 0; i < count; ++i) {
+        masks[i].X = (float2*)((char*)h->batch_ws + xoff[i]);
+        masks[i].mhat = (float*)((char*)h->batch_ws + moff[i]);
+    }
+    const size_t npart = (size_t)std::max(h->n_col_tasks, h->n_row_tasks);
+    if ((e = hipMalloc(&h->masks, count * sizeof(pm::BatchMask))) != hipSuccess) return bail(e, "hipMalloc(masks)");
+    if ((e = hipMalloc(&h->col_tasks, col.size() * sizeof(pm::BatchTask))) != hipSuccess) return bail(e, "hipMalloc(tasks)");
+    if ((e = hipMalloc(&h->row_tasks, row.size() * sizeof(pm::BatchTask))) != hipSuccess) return bail(e, "hipMalloc(tasks)");
+    if ((e = hipMalloc(&h->prep_tasks, prep.size() * sizeof(pm::BatchTask))) != hipSuccess) return bail(e, "hipMalloc(tasks)");
+    if ((e = hipMalloc(&h->mask_prep0, count * sizeof(int))) != hipSuccess) return bail(e, "hipMalloc(prep index)");
+    if ((e = hipMalloc(&h->part, npart * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(partials)");
+    if ((e = hipMalloc(&h->part_m, prep.size() * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(norm)");
+    if ((e = hipMalloc(&h->bio, sizeof(pm::BatchIo))) != hipSuccess) return bail(e, "hipMalloc(io)");
+    if ((e = hipMalloc(&h->tw_batch, pm::kBatchMaxLen * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
+    h->part_entries = 1;
+    h->stride = (int)npart;
+    const std::vector<float2> tw = twiddles(pm::kBatchMaxLen);
+    struct Up { void* dst; const void* src; size_t n; } ups[] = {
+        {h->masks, masks.data(), count * sizeof(pm::BatchMask)},
+        {h->col_tasks, col.data(), col.size() * sizeof(pm::BatchTask)},
+        {h->row_tasks, row.data(), row.size() * sizeof(pm::BatchTask)},
+        {h->prep_tasks, prep.data(), prep.size() * sizeof(pm::BatchTask)},
+        {h->mask_prep0, prep0.data(), count * sizeof(int)},
+        {h->tw_batch, tw.data(), tw.size() * sizeof(float2)}};
+    for (const Up& u : ups)
+        if ((e = hipMemcpy(u.dst, u.src, u.n, hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "hipMemcpy(plan)");
+    if ((e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        return bail(e, "hipStreamCreate");
+    h->ws_bytes = off + npart * sizeof(double) + prep.size() * (sizeof(double) + sizeof(pm::BatchTask)) +
+                  (col.size() + row.size()) * sizeof(pm::BatchTask) + count * (sizeof(pm::BatchMask) + sizeof(int)) +
+                  sizeof(pm::BatchIo) + pm::kBatchMaxLen * sizeof(float2);
+    *out = h;
+    return PM_OK;
+}
+
+pm_status phasemask_solve_batched(pm_handle h, const float* const* targets, const float* const* init_phases,
+                                  int n_iter, float* const* out_phases, double* final_err) {
+    pm_status st = check_handle(h, true);
+    if (st != PM_OK) return st;
+    if (!targets || !init_phases || !out_phases) return fail(PM_EINVAL, "null pointer-array argument");
+    if (n_iter < 0) return fail(PM_EINVAL, "n_iter must be >= 0");
+    if (misaligned(targets, 8) || misaligned(init_phases, 8) || misaligned(out_phases, 8) ||
+        misaligned(final_err, 8))
+        return fail(PM_EINVAL, "misaligned argument");
+    pm::BatchIo io{targets, init_phases, out_phases, final_err};
+    PM_TRY(pm::launch_set_batch_io(h->bio, io, h->stream), "set batch io");
+    const bool err = final_err != nullptr;
+    if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_batch(h, h->stream, n_iter, err);
+    return launch_graph(h, n_iter, err);
 }
 
 pm_status phasemask_time_passes(pm_handle h, const float* target_amplitude, const float* phase, int reps,

@@ -92,6 +92,127 @@ __global__ void __launch_bounds__(kAuxThreads) k_wrap_phase(const PmIo* io, int 
     }
 }
 
+// ----- batched preparation ---------------------------------------------------
+
+__global__ void k_set_batch_io(BatchIo* io, BatchIo val) {
+    const unsigned long long vals[4] = {
+        (unsigned long long)val.targets, (unsigned long long)val.phases_in,
+        (unsigned long long)val.phases_out, (unsigned long long)val.final_err};
+    const int i = threadIdx.x;
+    if (i < 4) reinterpret_cast<unsigned long long*>(io)[i] = vals[i];
+}
+
+// Sum of m^2 over one task's kPrepPixels pixels (4 float4 per thread).
+__global__ void __launch_bounds__(kAuxThreads)
+k_batch_norm(const BatchIo* io, const BatchTask* tasks, double* part_m) {
+    static_assert(kPrepPixels == kAuxThreads * 16, "4 float4 per thread");
+    __shared__ double red[kAuxThreads / 64];
+    const BatchTask task = tasks[blockIdx.x];
+    const float4* m4 = reinterpret_cast<const float4*>(io->targets[task.mask] + task.first);
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float4 q = m4[t * kAuxThreads + threadIdx.x];
+        acc = fma((double)q.x, (double)q.x, acc);
+        acc = fma((double)q.y, (double)q.y, acc);
+        acc = fma((double)q.z, (double)q.z, acc);
+        acc = fma((double)q.w, (double)q.w, acc);
+    }
+    const double tot = block_sum<kAuxThreads>(acc, red);
+    if (threadIdx.x == 0) part_m[blockIdx.x] = tot;
+}
+
+// mhat = m / ||m|| (strip-tiled) for one task's pixels; the norm is summed
+// from the mask's partials in a fixed order by every work-group.
+__global__ void __launch_bounds__(kAuxThreads)
+k_batch_tile(const BatchIo* io, const BatchMask* masks, const BatchTask* tasks, const int* mask_prep0,
+             const double* part_m) {
+    __shared__ double red[kAuxThreads / 64];
+    __shared__ double inv_norm;
+    const BatchTask task = tasks[blockIdx.x];
+    const BatchMask mk = masks[task.mask];
+    const int p0 = mask_prep0[task.mask];
+    const int np = mk.H * mk.W / kPrepPixels;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += kAuxThreads) acc += part_m[p0 + i];
+    const double tot = block_sum<kAuxThreads>(acc, red);
+    if (threadIdx.x == 0) inv_norm = tot > 0.0 ? 1.0 / sqrt(tot) : 0.0;
+    __syncthreads();
+    const double inv = inv_norm;
+    const float4* m4 = reinterpret_cast<const float4*>(io->targets[task.mask]);
+    float4* out4 = reinterpret_cast<float4*>(mk.mhat);
+    const int w4 = mk.W / 4;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int i = task.first / 4 + t * kAuxThreads + threadIdx.x;
+        const int y = i / w4;
+        const int q = i - y * w4;
+        const float4 m = m4[i];
+        float4 o;
+        o.x = (float)((double)m.x * inv);
+        o.y = (float)((double)m.y * inv);
+        o.z = (float)((double)m.z * inv);
+        o.w = (float)((double)m.w * inv);
+        out4[(size_t)q * mk.H + y] = o;
+    }
+}
+
+// phases_out = atan2(sin phi, cos phi) for a zero-iteration batched solve.
+__global__ void __launch_bounds__(kAuxThreads)
+k_batch_wrap(const BatchIo* io, const BatchTask* tasks) {
+    const BatchTask task = tasks[blockIdx.x];
+    const float* in = io->phases_in[task.mask] + task.first;
+    float* out = io->phases_out[task.mask] + task.first;
+    for (int i = threadIdx.x; i < kPrepPixels; i += kAuxThreads) {
+        float sn, cs;
+        sincosf(in[i], &sn, &cs);
+        out[i] = atan2f(sn, cs);
+    }
+}
+
+// final_err[mask] = sqrt(sum of the mask's column-pass partials).
+__global__ void __launch_bounds__(kAuxThreads)
+k_batch_finalize(const BatchIo* io, const BatchMask* masks, const double* part) {
+    __shared__ double red[kAuxThreads / 64];
+    const BatchMask mk = masks[blockIdx.x];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < mk.col_wgs; i += kAuxThreads) acc += part[mk.col_wg0 + i];
+    const double tot = block_sum<kAuxThreads>(acc, red);
+    if (threadIdx.x == 0 && io->final_err != nullptr) io->final_err[blockIdx.x] = sqrt(tot);
+}
+
+hipError_t launch_set_batch_io(BatchIo* io, const BatchIo& val, hipStream_t s) {
+    k_set_batch_io<<<1, 64, 0, s>>>(io, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_norm(const BatchIo* io, const BatchTask* tasks, int ntasks, double* part_m,
+                             hipStream_t s) {
+    k_batch_norm<<<ntasks, kAuxThreads, 0, s>>>(io, tasks, part_m);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_tile(const BatchIo* io, const BatchMask* masks, const BatchTask* tasks, int ntasks,
+                             const int* mask_prep0, const double* part_m, hipStream_t s) {
+    k_batch_tile<<<ntasks, kAuxThreads, 0, s>>>(io, masks, tasks, mask_prep0, part_m);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_wrap(const BatchIo* io, const BatchMask* masks, const BatchTask* tasks, int ntasks,
+                             hipStream_t s) {
+    (void)masks;
+    k_batch_wrap<<<ntasks, kAuxThreads, 0, s>>>(io, tasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const BatchIo* io, const BatchMask* masks, int count, const double* part,
+                                 hipStream_t s) {
+    k_batch_finalize<<<count, kAuxThreads, 0, s>>>(io, masks, part);
+    return hipGetLastError();
+}
+
+// ----- one-mask helpers -------------------------------------------------------
+
 hipError_t launch_set_io(PmIo* io, const PmIo& val, hipStream_t s) {
     k_set_io<<<1, 64, 0, s>>>(io, val);
     return hipGetLastError();

@@ -36,6 +36,7 @@ enum : int {
     R_FWD = 32,       // forward row transform, write the tiled iterate
     ROUT_PHASE = 64,  // write atan2 of the projected field
     ROUT_NAT = 128,   // write a natural-layout complex image
+    R_NOERR = 256,    // P_S without the gap partial sum
 };
 constexpr int ROW_INIT = RIN_PHASE | R_FWD;
 constexpr int ROW_ITER = RIN_TILED | R_INV | R_PS | R_FWD;
@@ -44,6 +45,9 @@ constexpr int ROW_LAST_FWD = RIN_TILED | R_INV | R_PS | ROUT_PHASE | R_FWD;
 constexpr int ROW_GAP = RIN_TILED | R_INV | R_PS;
 constexpr int ROW_FFT_FWD = RIN_NAT | R_FWD;
 constexpr int ROW_FFT_INV = RIN_TILED | R_INV | ROUT_NAT;
+constexpr int ROW_ITER_NE = ROW_ITER | R_NOERR;
+constexpr int ROW_LAST_NE = ROW_LAST | R_NOERR;
+constexpr int ROW_LAST_FWD_NE = ROW_LAST_FWD | R_NOERR;
 
 // Column-pass modes (bit sets).
 enum : int {
@@ -55,26 +59,30 @@ enum : int {
     C_INV = 32,       // inverse column transform
     COUT_TILED = 64,
     COUT_NAT = 128,
+    C_NOERR = 256,    // M-hat without the Fourier-error partial sum
 };
 constexpr int COL_ITER = CIN_TILED | C_FWD | C_PROJ | C_INV | COUT_TILED;
 constexpr int COL_ERR = CIN_TILED | C_FWD | C_ERR;
 constexpr int COL_FFT_FWD = CIN_TILED | C_FWD | COUT_NAT;
 constexpr int COL_FFT_INV = CIN_NAT | C_INV | COUT_TILED;
+constexpr int COL_ITER_NE = COL_ITER | C_NOERR;
 
 struct RowParams {
     float2* X;             // tiled iterate
-    const float2* tw;      // exp(-2 pi i k / W), k < W
+    const float2* tw;      // twiddle table exp(-2 pi i k / (W tw_step))
+    int tw_step;
     const PmIo* io;
     const float2* nat_in;  // natural-layout input (RIN_NAT)
     float2* nat_out;       // natural-layout output (ROUT_NAT)
-    double* part;          // one gap partial per work-group (R_PS)
+    double* part;          // one gap partial per work-group (R_PS), null without
     int H;
 };
 
 struct ColParams {
     float2* X;             // tiled iterate
     const float* mhat;     // tiled target divided by its 2-norm
-    const float2* tw;      // exp(-2 pi i k / H), k < H
+    const float2* tw;      // twiddle table exp(-2 pi i k / (H tw_step))
+    int tw_step;
     const float2* nat_in;
     float2* nat_out;
     double* part;          // one Fourier-error partial per work-group
@@ -102,6 +110,63 @@ PM_DECLARE_LAUNCHERS(1024)
 PM_DECLARE_LAUNCHERS(2048)
 PM_DECLARE_LAUNCHERS(4096)
 #undef PM_DECLARE_LAUNCHERS
+
+// ---------------------------------------------------------------------------
+// Batched solves: masks of several sizes (powers of two in
+// [kBatchMinLen, kBatchMaxLen] per side) advance together, one column-pass
+// kernel and one row-pass kernel per iteration for the whole batch.  Every
+// work-group has kBatchThreads threads and takes one task (a mask and its
+// first strip or row); it owns kBatchThreads / T lines of that mask.
+constexpr int kBatchThreads = 256;
+constexpr int kBatchMinLen = 64;
+constexpr int kBatchMaxLen = 1024;
+constexpr int kPrepPixels = 4096;  // pixels per task of the batched target preparation
+
+struct BatchMask {
+    int H, W;
+    int col_wg0, col_wgs;  // this mask's column-pass work-groups (first, count)
+    float2* X;             // tiled iterate
+    float* mhat;           // tiled rescaled target
+};
+
+struct BatchTask {
+    int mask;
+    int first;             // first strip (column pass), first row (row pass), first pixel (prep)
+};
+
+struct BatchIo {
+    const float* const* targets;     // device array of count device pointers
+    const float* const* phases_in;
+    float* const* phases_out;
+    double* final_err;               // count doubles, may be null
+};
+
+struct BatchParams {
+    const BatchMask* masks;
+    const BatchTask* tasks;          // one per work-group of this launch
+    const float2* tw;                // exp(-2 pi i k / kBatchMaxLen)
+    const BatchIo* io;
+    double* part;                    // one partial per work-group (error passes)
+};
+
+// Batched passes; MODE is one of the column / row modes.  Explicit
+// instantiations live in pm_batch.hip.
+template <int MODE>
+hipError_t launch_batch_col(const BatchParams& p, int grid, hipStream_t s);
+template <int MODE>
+hipError_t launch_batch_row(const BatchParams& p, int grid, hipStream_t s);
+
+// Batched preparation kernels (pm_aux.hip).  Prep tasks cover kPrepPixels
+// pixels of one mask each; mask_prep0[i] is mask i's first prep task.
+hipError_t launch_set_batch_io(BatchIo* io, const BatchIo& val, hipStream_t s);
+hipError_t launch_batch_norm(const BatchIo* io, const BatchTask* tasks, int ntasks, double* part_m,
+                             hipStream_t s);
+hipError_t launch_batch_tile(const BatchIo* io, const BatchMask* masks, const BatchTask* tasks,
+                             int ntasks, const int* mask_prep0, const double* part_m, hipStream_t s);
+hipError_t launch_batch_wrap(const BatchIo* io, const BatchMask* masks, const BatchTask* tasks,
+                             int ntasks, hipStream_t s);
+hipError_t launch_batch_finalize(const BatchIo* io, const BatchMask* masks, int count,
+                                 const double* part, hipStream_t s);
 
 // Small kernels (pm_aux.hip).
 hipError_t launch_set_io(PmIo* io, const PmIo& val, hipStream_t s);

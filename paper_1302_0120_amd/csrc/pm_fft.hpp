@@ -166,7 +166,8 @@ struct LineTwiddles {
 };
 
 template <int L, int P, int NS, int OFF>
-__device__ __forceinline__ void load_twiddles_from(LineTwiddles<L, P>& tw, int j, const float2* __restrict__ table) {
+__device__ __forceinline__ void load_twiddles_from(LineTwiddles<L, P>& tw, int j, const float2* __restrict__ table,
+                                                   int step) {
     if constexpr (NS < L) {
         constexpr int T = L / P;
         constexpr int R = stage_radix(L, P, NS);
@@ -177,18 +178,21 @@ __device__ __forceinline__ void load_twiddles_from(LineTwiddles<L, P>& tw, int j
             for (int m = 0; m < M; ++m) {
                 const int k = (j + T * m) & (NS - 1);
 #pragma unroll
-                for (int q = 1; q < R; ++q) tw.w[OFF + m * (R - 1) + (q - 1)] = table[q * k * STRIDE];
+                for (int q = 1; q < R; ++q) tw.w[OFF + m * (R - 1) + (q - 1)] = table[q * k * STRIDE * step];
             }
-            load_twiddles_from<L, P, NS * R, OFF + M * (R - 1)>(tw, j, table);
+            load_twiddles_from<L, P, NS * R, OFF + M * (R - 1)>(tw, j, table, step);
         } else {
-            load_twiddles_from<L, P, NS * R, OFF>(tw, j, table);
+            load_twiddles_from<L, P, NS * R, OFF>(tw, j, table, step);
         }
     }
 }
 
+// `table` holds exp(-2 pi i k / (L step)); entry k step is exp(-2 pi i k / L),
+// so one table of the largest length serves every shorter power of two.
 template <int L, int P>
-__device__ __forceinline__ void load_twiddles(LineTwiddles<L, P>& tw, int j, const float2* __restrict__ table) {
-    load_twiddles_from<L, P, 1, 0>(tw, j, table);
+__device__ __forceinline__ void load_twiddles(LineTwiddles<L, P>& tw, int j, const float2* __restrict__ table,
+                                              int step) {
+    load_twiddles_from<L, P, 1, 0>(tw, j, table, step);
 }
 
 // LDS exchange buffers per line: two (alternating, one barrier per

@@ -1,7 +1,8 @@
 // pm_kernels.hpp -- the fused row and column passes of one Gerchberg-Saxton
-// iteration (Eq. 6), templated on the transform length.
+// iteration (Eq. 6), templated on the transform length and on the number of
+// lines a work-group owns.
 //
-// One iteration = two passes over the iterate in HBM/L2:
+// One iteration = two passes over the iterate:
 //   column pass:  forward column FFT -> M-hat of Eq. 5 (keep the phase of
 //                 each Fourier coefficient, take the target modulus) ->
 //                 inverse column FFT, plus the FP64 Fourier-error partials;
@@ -10,6 +11,10 @@
 //                 plus the FP64 gap partials.
 // The very first row pass forms exp(i phi0) instead (u^0 in S, Eq. 1); the
 // last one writes the phase of u^n.
+//
+// The bodies (col_body, row_body) serve both the one-mask kernels below and
+// the batched kernels, which pick the body per work-group from the size of
+// the mask it works on.
 #pragma once
 #include <float.h>
 
@@ -61,35 +66,35 @@ struct LineShape {
     static constexpr int LP = lds_line_len(L);      // padded LDS line
 };
 
-// Column pass over one strip of kC columns (one work-group per strip).
-// Thread (j, c) = (tid / kC, tid % kC) owns column c of the strip and the
-// rows j + T t; for a fixed t the work-group's loads cover consecutive
-// rows of the strip, i.e. one contiguous run of memory.
-template <int H, int MODE>
-__global__ void __launch_bounds__(kC * LineShape<H>::T)
-k_col(ColParams a) {
+// Column pass over G columns = G / kC adjacent strips, starting at strip
+// `strip0` (G a multiple of kC).  Thread tid = (sl, j, c), c fastest: strip
+// strip0 + sl, column c of that strip, rows j + T t.  For a fixed t a wave's
+// loads are 64 / kC consecutive rows of one strip: one contiguous run.
+// `lds` holds LdsPlan<H, G>::FLOATS2 elements, `red` NT / 64 doubles.
+template <int H, int G, int MODE>
+__device__ __forceinline__ void col_body(const ColParams& a, int strip0, double* part_slot,
+                                         float2* lds, double* red) {
     constexpr int P = LineShape<H>::P;
     constexpr int T = LineShape<H>::T;
-    constexpr int NT = kC * T;
+    constexpr int NT = G * T;
     constexpr int LP = LineShape<H>::LP;
-    using LD = LdsPlan<H, kC>;
-    __shared__ float2 lds[LD::FLOATS2];
-    __shared__ double red[(NT + 63) / 64];
+    using LD = LdsPlan<H, G>;
+    static_assert(G % kC == 0, "whole strips per work-group");
 
     const int tid = threadIdx.x;
     const int c = tid & (kC - 1);
-    const int j = tid / kC;
-    const int s = blockIdx.x;
+    const int j = (tid / kC) % T;
+    const int sl = tid / (kC * T);
+    const int s = strip0 + sl;
     const size_t sb = (size_t)s * H * kC;
     LineTwiddles<H, P> tw;
-    load_twiddles(tw, j, a.tw);
+    load_twiddles(tw, j, a.tw, a.tw_step);
     float mt[P];
     if constexpr ((MODE & (C_PROJ | C_ERR)) != 0) {
 #pragma unroll
         for (int t = 0; t < P; ++t) mt[t] = a.mhat[sb + (size_t)(j + T * t) * kC + c];
     }
     float2 v[P];
-
     if constexpr ((MODE & CIN_NAT) != 0) {
 #pragma unroll
         for (int t = 0; t < P; ++t) v[t] = a.nat_in[(size_t)(j + T * t) * a.W + s * kC + c];
@@ -97,7 +102,7 @@ k_col(ColParams a) {
 #pragma unroll
         for (int t = 0; t < P; ++t) v[t] = a.X[sb + (size_t)(j + T * t) * kC + c];
     }
-    float2* line = lds + c * LP;
+    float2* line = lds + (sl * kC + c) * LP;
 
     constexpr int PAR1 = (MODE & C_FWD) != 0 ? fft_parity_after<H, P, 0>() : 0;
     if constexpr ((MODE & C_FWD) != 0) fft_line<H, P, false, LD::NBUF, 0>(v, j, line, LD::STRIDE, tw);
@@ -105,6 +110,7 @@ k_col(ColParams a) {
     if constexpr ((MODE & (C_PROJ | C_ERR)) != 0) {
         // U = unnormalised DFT of u, so |U|/N is the unitary modulus over
         // sqrt(N); mhat = m / ||m||.  E_F^2 = sum (|U|/N - mhat)^2.
+        constexpr bool ERR = (MODE & C_NOERR) == 0;
         double acc = 0.0;
 #pragma unroll
         for (int t = 0; t < P; ++t) {
@@ -116,15 +122,19 @@ k_col(ColParams a) {
             // Eq. 5 takes phase 0 and |U| counts as 0.
             const bool nz = a2 >= FLT_MIN;
             const float r = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
-            const double d = (double)(a2 * r) * a.invN - (double)m;
-            acc = fma(d, d, acc);
+            if constexpr (ERR) {
+                const double d = (double)(a2 * r) * a.invN - (double)m;
+                acc = fma(d, d, acc);
+            }
             if constexpr ((MODE & C_PROJ) != 0) {
                 const float q = m * r;
                 v[t] = nz ? make_float2(U.x * q, U.y * q) : make_float2(m, 0.0f);
             }
         }
-        const double tot = block_sum<NT>(acc, red);
-        if (tid == 0) a.part[blockIdx.x] = tot;
+        if constexpr (ERR) {
+            const double tot = block_sum<NT>(acc, red);
+            if (tid == 0) *part_slot = tot;
+        }
     }
 
     if constexpr ((MODE & C_INV) != 0) fft_line<H, P, true, LD::NBUF, PAR1>(v, j, line, LD::STRIDE, tw);
@@ -139,44 +149,41 @@ k_col(ColParams a) {
     }
 }
 
-// Row pass over kGR adjacent rows (one work-group per row group).
-// Lane layout tid = (jhi, rho, c) with c fastest: thread index within the
-// row j = jhi * kC + c, row = group * kGR + rho.  For a fixed t the
-// element (row, j + T t) lies in strip jhi + (T / kC) t at column c, so a
-// wave's loads are runs of kGR * kC contiguous elements.
-template <int W, int MODE>
-__global__ void __launch_bounds__(kGR * LineShape<W>::T)
-k_row(RowParams a) {
+// Row pass over G adjacent rows starting at `row0`.  Thread tid = (jhi, rho,
+// c), c fastest: row row0 + rho, thread index within the row j = jhi kC + c.
+// For a fixed t the element (row, j + T t) lies in strip jhi + (T / kC) t at
+// column c, so a wave's loads are runs of G kC contiguous elements.
+template <int W, int G, int MODE>
+__device__ __forceinline__ void row_body(const RowParams& a, int row0, const float* phase_in,
+                                         float* phase_out, double* part_slot, float2* lds,
+                                         double* red) {
     constexpr int P = LineShape<W>::P;
     constexpr int T = LineShape<W>::T;
-    constexpr int NT = kGR * T;
+    constexpr int NT = G * T;
     constexpr int LP = LineShape<W>::LP;
     static_assert(T % kC == 0, "row threads must cover whole strips");
-    using LD = LdsPlan<W, kGR>;
-    __shared__ float2 lds[LD::FLOATS2];
-    __shared__ double red[(NT + 63) / 64];
+    using LD = LdsPlan<W, G>;
 
     const int tid = threadIdx.x;
     const int c = tid & (kC - 1);
-    const int rho = (tid / kC) & (kGR - 1);
-    const int jhi = tid / (kC * kGR);
+    const int rho = (tid / kC) % G;
+    const int jhi = tid / (kC * G);
     const int j = jhi * kC + c;
-    const int row = blockIdx.x * kGR + rho;
+    const int row = row0 + rho;
     const size_t H = (size_t)a.H;
     auto tiled = [&](int t) -> size_t {
         return ((size_t)(jhi + (T / kC) * t) * H + row) * kC + c;
     };
     auto natural = [&](int t) -> size_t { return (size_t)row * W + j + T * t; };
     LineTwiddles<W, P> tw;
-    load_twiddles(tw, j, a.tw);
+    load_twiddles(tw, j, a.tw, a.tw_step);
     float2 v[P];
 
     if constexpr ((MODE & RIN_PHASE) != 0) {
-        const float* ph = a.io->phase_in;
 #pragma unroll
         for (int t = 0; t < P; ++t) {
             float sn, cs;
-            sincosf(ph[natural(t)], &sn, &cs);
+            sincosf(phase_in[natural(t)], &sn, &cs);
             v[t] = make_float2(cs, sn);
         }
     } else if constexpr ((MODE & RIN_NAT) != 0) {
@@ -194,6 +201,7 @@ k_row(RowParams a) {
     if constexpr ((MODE & R_PS) != 0) {
         // w = P_M u^nu with unit scale (the target was divided by ||m||, so
         // the unnormalised inverse leaves |w| on the scale of p = 1).
+        constexpr bool ERR = (MODE & R_NOERR) == 0;
         double acc = 0.0;
 #pragma unroll
         for (int t = 0; t < P; ++t) {
@@ -202,18 +210,21 @@ k_row(RowParams a) {
             // Tie-break of Eq. 4a below FLT_MIN (phase 0), as in the column pass.
             const bool nz = a2 >= FLT_MIN;
             const float r = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
-            const double d = (double)(a2 * r) - 1.0;
-            acc = fma(d, d, acc);
+            if constexpr (ERR) {
+                const double d = (double)(a2 * r) - 1.0;
+                acc = fma(d, d, acc);
+            }
             v[t] = nz ? make_float2(w.x * r, w.y * r) : make_float2(1.0f, 0.0f);
         }
-        const double tot = block_sum<NT>(acc, red);
-        if (tid == 0) a.part[blockIdx.x] = tot;
+        if constexpr (ERR) {
+            const double tot = block_sum<NT>(acc, red);
+            if (tid == 0) *part_slot = tot;
+        }
     }
 
     if constexpr ((MODE & ROUT_PHASE) != 0) {
-        float* out = a.io->phase_out;
 #pragma unroll
-        for (int t = 0; t < P; ++t) out[natural(t)] = atan2f(v[t].y, v[t].x);
+        for (int t = 0; t < P; ++t) phase_out[natural(t)] = atan2f(v[t].y, v[t].x);
     }
     if constexpr ((MODE & ROUT_NAT) != 0) {
 #pragma unroll
@@ -224,6 +235,29 @@ k_row(RowParams a) {
 #pragma unroll
         for (int t = 0; t < P; ++t) store_shared(&a.X[tiled(t)], v[t]);
     }
+}
+
+// One-mask kernels: kC columns (one strip) or kGR rows per work-group.
+template <int H, int MODE>
+__global__ void __launch_bounds__(kC * LineShape<H>::T)
+k_col(ColParams a) {
+    constexpr int NT = kC * LineShape<H>::T;
+    __shared__ float2 lds[LdsPlan<H, kC>::FLOATS2];
+    __shared__ double red[(NT + 63) / 64];
+    col_body<H, kC, MODE>(a, blockIdx.x, a.part + blockIdx.x, lds, red);
+}
+
+template <int W, int MODE>
+__global__ void __launch_bounds__(kGR * LineShape<W>::T)
+k_row(RowParams a) {
+    constexpr int NT = kGR * LineShape<W>::T;
+    __shared__ float2 lds[LdsPlan<W, kGR>::FLOATS2];
+    __shared__ double red[(NT + 63) / 64];
+    const float* pin = nullptr;
+    float* pout = nullptr;
+    if constexpr ((MODE & RIN_PHASE) != 0) pin = a.io->phase_in;
+    if constexpr ((MODE & ROUT_PHASE) != 0) pout = a.io->phase_out;
+    row_body<W, kGR, MODE>(a, blockIdx.x * kGR, pin, pout, a.part + blockIdx.x, lds, red);
 }
 
 }  // namespace pm

@@ -40,6 +40,8 @@ hipError_t PM_CAT(launch_row_, PM_L)(int mode, const RowParams& p, int grid, hip
         case ROW_GAP: return launch(k_row<PM_L, ROW_GAP>, grid, block, s, ev0, ev1, p);
         case ROW_FFT_FWD: return launch(k_row<PM_L, ROW_FFT_FWD>, grid, block, s, ev0, ev1, p);
         case ROW_FFT_INV: return launch(k_row<PM_L, ROW_FFT_INV>, grid, block, s, ev0, ev1, p);
+        case ROW_ITER_NE: return launch(k_row<PM_L, ROW_ITER_NE>, grid, block, s, ev0, ev1, p);
+        case ROW_LAST_NE: return launch(k_row<PM_L, ROW_LAST_NE>, grid, block, s, ev0, ev1, p);
         default: return hipErrorInvalidValue;
     }
 }
@@ -52,6 +54,7 @@ hipError_t PM_CAT(launch_col_, PM_L)(int mode, const ColParams& p, int grid, hip
         case COL_ERR: return launch(k_col<PM_L, COL_ERR>, grid, block, s, ev0, ev1, p);
         case COL_FFT_FWD: return launch(k_col<PM_L, COL_FFT_FWD>, grid, block, s, ev0, ev1, p);
         case COL_FFT_INV: return launch(k_col<PM_L, COL_FFT_INV>, grid, block, s, ev0, ev1, p);
+        case COL_ITER_NE: return launch(k_col<PM_L, COL_ITER_NE>, grid, block, s, ev0, ev1, p);
         default: return hipErrorInvalidValue;
     }
 }

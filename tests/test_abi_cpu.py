@@ -70,3 +70,21 @@ def test_host_side_argument_errors(lib):
     assert lib.phasemask_set_stream(None, None) == -1
     lib.phasemask_workspace_bytes.restype = ctypes.c_size_t
     assert lib.phasemask_workspace_bytes(None) == 0
+
+
+def test_batched_host_side_argument_errors(lib):
+    lib.phasemask_create_batched.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                             ctypes.c_uint, ctypes.c_void_p]
+    h = ctypes.c_void_p(99)
+    hs = (ctypes.c_int * 2)(256, 512)
+    ws = (ctypes.c_int * 2)(256, 2048)
+    assert lib.phasemask_create_batched(None, 2, hs, hs, 0, None) == -1
+    assert lib.phasemask_create_batched(ctypes.byref(h), 0, hs, hs, 0, None) == -1
+    assert lib.phasemask_create_batched(ctypes.byref(h), 2, hs, ws, 0, None) == -2
+    assert h.value is None
+    small = (ctypes.c_int * 1)(32)
+    assert lib.phasemask_create_batched(ctypes.byref(h), 1, small, small, 0, None) == -2
+    lib.phasemask_solve_batched.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                            ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.phasemask_solve_batched(None, None, None, 1, None, None) == -1

@@ -1,0 +1,137 @@
+"""GPU parity of batched solves: every mask of a batch must come out exactly as
+a one-mask solve of the same inputs (phases bitwise, final errors up to the
+order of FP64 sums), and match the FP64 oracle to the one-mask tolerances."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import gs
+from paper_1302_0120_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pmb():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1302_0120_amd import binding
+    return binding
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+SHAPES = [(64, 64), (128, 256), (256, 256), (512, 64), (64, 1024), (512, 512), (1024, 1024),
+          (256, 128)]
+
+
+def _problems(shapes, seed0=300):
+    out = []
+    for i, (h, w) in enumerate(shapes):
+        rng = np.random.default_rng(seed0 + i)
+        m = synth.spot_amplitude(h, w, 1 + i * 7, 2.0, 0.5, 1.0, rng)
+        out.append((m, synth.uniform_phase(h, w, rng)))
+    return out
+
+
+def test_batched_equals_one_mask_solves(pmb):
+    probs = _problems(SHAPES)
+    n_iter = 6
+    print(f"batched vs one-mask, {len(SHAPES)} masks, n={n_iter}", flush=True)
+    bp = pmb.BatchedPhaseMask(SHAPES)
+    targets = [_dev(m) for m, _ in probs]
+    phases = [_dev(p) for _, p in probs]
+    outs, err = bp.solve(targets, phases, n_iter)
+    err = err.cpu().numpy()
+    for i, (h, w) in enumerate(SHAPES):
+        single = pmb.PhaseMask(h, w)
+        ph, hist = single.solve(targets[i], phases[i], n_iter)
+        assert torch.equal(outs[i], ph), (i, (h, w))
+        ef = hist[-1].item()
+        assert abs(err[i] - ef) <= 1e-12 * ef, (i, err[i], ef)
+
+
+def test_batched_one_iteration_and_final_error_vs_oracle(pmb):
+    shapes = [(64, 64), (256, 128), (512, 512), (1024, 1024)]
+    probs = _problems(shapes, 400)
+    bp = pmb.BatchedPhaseMask(shapes)
+    targets = [_dev(m) for m, _ in probs]
+    phases = [_dev(p) for _, p in probs]
+    outs1, _ = bp.solve(targets, phases, 1)
+    outs, err = bp.solve(targets, phases, 30)
+    err = err.cpu().numpy()
+    for i, (m, p) in enumerate(probs):
+        ref1 = gs.gs_solve(m, p, 1)
+        u1 = np.exp(1j * outs1[i].cpu().numpy().astype(np.float64))
+        assert np.linalg.norm(u1 - ref1["u"]) / np.linalg.norm(ref1["u"]) <= 1e-5
+        ref = gs.gs_solve(m, p, 30)["history"][-1]
+        assert abs(err[i] - ref) / ref <= 1e-3, (i, err[i], ref)
+        # the reported error is the error of the returned mask
+        assert abs(err[i] - gs.mask_errors(m, outs[i].cpu().numpy())[0]) / ref <= 1e-5
+
+
+def test_batched_zero_iterations_and_no_error(pmb):
+    shapes = [(64, 128), (128, 64)]
+    probs = _problems(shapes, 500)
+    bp = pmb.BatchedPhaseMask(shapes)
+    targets = [_dev(m) for m, _ in probs]
+    phases = [_dev(p * np.float32(3.0)) for _, p in probs]
+    outs, err = bp.solve(targets, phases, 0)
+    for i, (m, p) in enumerate(probs):
+        o = outs[i].cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(o) <= math.pi)
+        assert np.max(np.abs(np.exp(1j * o) - np.exp(1j * (3.0 * p.astype(np.float64))))) <= 2e-6
+        ef = gs.mask_errors(m, (p * np.float32(3.0)))[0]
+        assert abs(err[i].item() - ef) / ef <= 1e-5
+    outs2, err2 = bp.solve(targets, phases, 3, final_err=False)
+    assert err2 is None
+    outs3, _ = bp.solve(targets, phases, 3)
+    assert all(torch.equal(a, b) for a, b in zip(outs2, outs3))
+
+
+def test_batched_graph_and_eager_identical(pmb):
+    shapes = [(256, 256), (64, 512)]
+    probs = _problems(shapes, 600)
+    targets = [_dev(m) for m, _ in probs]
+    phases = [_dev(p) for _, p in probs]
+    a, ea = pmb.BatchedPhaseMask(shapes).solve(targets, phases, 4)
+    b, eb = pmb.BatchedPhaseMask(shapes, flags=pmb.PM_FLAG_NO_GRAPH).solve(targets, phases, 4)
+    assert all(torch.equal(x, y) for x, y in zip(a, b)) and torch.equal(ea, eb)
+
+
+def test_batched_workload_64_mixed_masks(pmb):
+    """The 64-mask uneven batch (sizes from {256, 512, 1024}^2, 1-200 spots
+    each), 100 iterations in one graph launch; final errors of sampled masks
+    against the oracle, and every mask's error is that of its returned phase
+    in the monotone-chain sense (below the error of its initial phase)."""
+    probs = synth.batched_problems()
+    shapes = [m.shape for m, _ in probs]
+    print(f"batched workload: {len(shapes)} masks, sum N = {sum(h * w for h, w in shapes)}", flush=True)
+    bp = pmb.BatchedPhaseMask(shapes)
+    targets = [_dev(m) for m, _ in probs]
+    phases = [_dev(p) for _, p in probs]
+    outs, err = bp.solve(targets, phases, 100)
+    err = err.cpu().numpy()
+    assert np.all(np.isfinite(err))
+    for i in (0, 17, 63):  # sampled masks: the oracle runs 100 iterations on each
+        m, p = probs[i]
+        ref = gs.gs_solve(m, p, 100)["history"][-1]
+        assert abs(err[i] - ref) / ref <= 1e-3, (i, shapes[i], err[i], ref)
+    for i in range(0, 64, 9):
+        m, p = probs[i]
+        assert err[i] < gs.mask_errors(m, p)[0]
+
+
+def test_batched_handle_kind_errors(pmb):
+    bp = pmb.BatchedPhaseMask([(64, 64)])
+    m = torch.ones(64, 64, device="cuda")
+    st = pmb.lib.phasemask_solve(bp._h, m.data_ptr(), m.data_ptr(), 1, m.data_ptr(), None)
+    assert st == -5
+    with pytest.raises(pmb.PhaseMaskError) as ei:
+        pmb.BatchedPhaseMask([(64, 2048)])
+    assert ei.value.status == -2
