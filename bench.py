@@ -51,6 +51,58 @@ def cpu_baseline(m, phi0, n_iter_sample):
     return n_iter_sample / dt, dt
 
 
+def bench_batched(torch, binding, synth, steps):
+    """64 masks of sizes drawn from {256, 512, 1024}^2 (1-200 spots each), 100
+    iterations: one batched graph launch versus the same masks solved one by
+    one with the one-mask path (each with its own plan and graph).  Both
+    report the final Fourier error of every mask."""
+    n_iter = 100
+    probs = synth.batched_problems()
+    shapes = [m.shape for m, _ in probs]
+    dev = torch.device("cuda", 0)
+    targets = [torch.from_numpy(m).to(dev) for m, _ in probs]
+    phases = [torch.from_numpy(p).to(dev) for _, p in probs]
+    outs = [torch.empty_like(p) for p in phases]
+    err = torch.empty(len(probs), dtype=torch.float64, device=dev)
+    bp = binding.BatchedPhaseMask(shapes, device=dev)
+    bp.solve(targets, phases, n_iter, outs=outs, final_err=err)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bp.solve(targets, phases, n_iter, outs=outs, final_err=err)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+
+    plans = {}
+    hists = [torch.empty(2 * n_iter + 1, dtype=torch.float64, device=dev) for _ in probs]
+    def plain():
+        for i, shp in enumerate(shapes):
+            if shp not in plans:
+                plans[shp] = binding.PhaseMask(*shp, device=dev)
+            plans[shp].solve(targets[i], phases[i], n_iter, out=outs[i], history=hists[i])
+    plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plain()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / steps
+    sum_px = sum(h * w for h, w in shapes)
+    gbs = (COL_BYTES_PER_PX + ROW_BYTES_PER_PX) * sum_px * n_iter / t_batch / 1e9
+    return {
+        "workload": "64 masks, sizes uniform over {256,512,1024}^2 (seed 4), 1-200 spots, 100 it",
+        "sum_pixels": sum_px,
+        "masks_per_s": len(probs) / t_batch,
+        "ms_per_batch": t_batch * 1e3,
+        "plain_masks_per_s": len(probs) / t_plain,
+        "plain_ms": t_plain * 1e3,
+        "speedup_vs_plain": t_plain / t_batch,
+        "algorithmic_gbs": gbs,
+        "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+        "max_final_error": float(err.max().item()),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +112,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=64,
                     help="iterations of the FP64 oracle timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-versus-plain measurement")
+    ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 64 MiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -140,6 +195,8 @@ def main():
         "solve_algorithmic_gbs": solve_gbs,
         "final_fourier_error": final_ef,
     }
+    if not args.no_batched:
+        line["batched"] = bench_batched(torch, binding, synth, args.batched_steps)
     if not args.no_cpu_baseline:
         rate, cdt = cpu_baseline(m, phi0, args.cpu_iters)
         line["cpu_baseline"] = {
