@@ -173,6 +173,36 @@ pm_status phasemask_solve_batched(pm_handle h, const float* const* targets,
                                   float* const* out_phases, double* final_err);
 
 /*
+ * Intensity loss and its gradient (differentiable phase optimisation beside
+ * the projections; not in the paper, which notes that other reconstruction
+ * algorithms plug into the same machinery, Sec. V).  For each of `batch`
+ * phases of the plan's size:
+ *   L_b(phi) = sum_k ( |(F exp(i phi_b))_k|^2 - I_{b,k} )^2,  F unitary
+ *   dL_b/dphi_j = 4 Im( exp(-i phi_j) (F^H (r . U))_j ),  r = |U|^2 - I_b.
+ * A phase-only field has sum_k |U_k|^2 = N, so targets scaled to
+ * sum_k I_k = N are the natural choice (the library does not rescale).
+ *
+ * Forward:  phase, target_intensity   float[batch][height][width];
+ *           loss                      DEVICE double[batch];
+ *           saved                     DEVICE complex float[batch][height*width]
+ *                                     (8-byte aligned) that the backward
+ *                                     call reads; its layout is internal.
+ * Backward: grad_loss                 DEVICE double[batch], the upstream
+ *                                     gradient of each loss;
+ *           grad_phase                float[batch][height][width] receives
+ *                                     grad_loss_b * dL_b/dphi.
+ *           phase and saved must be the forward call's, unchanged.
+ * Errors: PM_EINVAL for NULL or misaligned arrays or batch outside
+ * [1, 65535]; PM_ENOMEM; PM_EDEVICE.
+ */
+pm_status phasemask_intensity_loss_fwd(pm_handle h, int batch, const float* phase,
+                                       const float* target_intensity, double* loss,
+                                       void* saved);
+pm_status phasemask_intensity_loss_bwd(pm_handle h, int batch, const float* phase,
+                                       const void* saved, const double* grad_loss,
+                                       float* grad_phase);
+
+/*
  * Measurement (roofline accounting of the two passes that run n_iter times,
  * Eq. 6): average device duration in milliseconds of one column pass
  * (forward column FFT, Eq. 5 projection, inverse column FFT) and of one row

@@ -31,6 +31,10 @@ _SIGNATURES = {
                                                 ctypes.c_uint, ctypes.c_void_p]),
     "phasemask_solve_batched": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                                ctypes.c_void_p, ctypes.c_void_p]),
+    "phasemask_intensity_loss_fwd": (ctypes.c_int, [_c_handle, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "phasemask_intensity_loss_bwd": (ctypes.c_int, [_c_handle, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_time_passes": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                              ctypes.POINTER(ctypes.c_float),
                                              ctypes.POINTER(ctypes.c_float)]),
@@ -146,6 +150,31 @@ class PhaseMask:
         _check(lib.phasemask_fft2(self._h, xp, op, 1 if inverse else 0), "phasemask_fft2")
         return out
 
+    def intensity_loss_fwd(self, phase: torch.Tensor, target_intensity: torch.Tensor):
+        """Per-sample loss (float64 [batch]) and the saved buffer for backward."""
+        b = phase.shape[0] if phase.dim() == 3 else 1
+        shp = (b, *self.shape) if phase.dim() == 3 else self.shape
+        pp = _dev_ptr(phase, torch.float32, shp, "phase")
+        ip = _dev_ptr(target_intensity, torch.float32, shp, "target_intensity")
+        loss = torch.empty(b, dtype=torch.float64, device=self.device)
+        saved = torch.empty((b, *self.shape), dtype=torch.complex64, device=self.device)
+        self._stream()
+        _check(lib.phasemask_intensity_loss_fwd(self._h, b, pp, ip, loss.data_ptr(), saved.data_ptr()),
+               "phasemask_intensity_loss_fwd")
+        return loss, saved
+
+    def intensity_loss_bwd(self, phase: torch.Tensor, saved: torch.Tensor, grad_loss: torch.Tensor):
+        b = saved.shape[0]
+        shp = (b, *self.shape) if phase.dim() == 3 else self.shape
+        pp = _dev_ptr(phase, torch.float32, shp, "phase")
+        sp = _dev_ptr(saved, torch.complex64, (b, *self.shape), "saved")
+        gl = _dev_ptr(grad_loss, torch.float64, (b,), "grad_loss")
+        grad = torch.empty_like(phase)
+        self._stream()
+        _check(lib.phasemask_intensity_loss_bwd(self._h, b, pp, sp, gl, grad.data_ptr()),
+               "phasemask_intensity_loss_bwd")
+        return grad
+
     def time_passes(self, target: torch.Tensor, phase: torch.Tensor, reps: int = 100):
         """(column-pass ms, row-pass ms): average kernel durations over `reps`
         iterations, from events recorded by the launches themselves."""
@@ -253,6 +282,35 @@ def plan_for(height: int, width: int, device=None) -> PhaseMask:
     if key not in _PLANS:
         _PLANS[key] = PhaseMask(height, width, device=torch.device("cuda", dev))
     return _PLANS[key]
+
+
+class IntensityLoss(torch.autograd.Function):
+    """loss_b = sum_k (|F exp(i phase_b)|_k^2 - I_{b,k})^2 with unitary F, for
+    phase [H][W] or [B][H][W] (float32, device).  Returns float64 losses
+    (scalar for a 2-D phase, [B] otherwise); backward runs the hand-written
+    adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, phase, target_intensity):
+        phase = phase.contiguous()
+        h, w = phase.shape[-2], phase.shape[-1]
+        plan = plan_for(h, w, phase.device)
+        loss, saved = plan.intensity_loss_fwd(phase, target_intensity.contiguous())
+        ctx.save_for_backward(phase, saved)
+        ctx.plan = plan
+        return loss if phase.dim() == 3 else loss[0]
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        phase, saved = ctx.saved_tensors
+        g = grad_loss.reshape(-1).to(torch.float64).contiguous()
+        if g.numel() == 1 and saved.shape[0] > 1:
+            g = g.expand(saved.shape[0]).contiguous()
+        return ctx.plan.intensity_loss_bwd(phase, saved, g), None
+
+
+def intensity_loss(phase: torch.Tensor, target_intensity: torch.Tensor) -> torch.Tensor:
+    return IntensityLoss.apply(phase, target_intensity)
 
 
 def solve(target: torch.Tensor, init_phase: torch.Tensor, n_iter: int, history: bool = True):

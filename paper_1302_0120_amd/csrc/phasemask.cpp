@@ -40,6 +40,15 @@ int log2i(int n) {
     return l;
 }
 
+using AdjRowLauncher = hipError_t (*)(int, const pm::AdjParams&, int, hipStream_t);
+using AdjColLauncher = hipError_t (*)(const pm::AdjParams&, int, hipStream_t);
+const AdjRowLauncher kAdjRow[9] = {pm::launch_adj_row_16,  pm::launch_adj_row_32,   pm::launch_adj_row_64,
+                                   pm::launch_adj_row_128, pm::launch_adj_row_256,  pm::launch_adj_row_512,
+                                   pm::launch_adj_row_1024, pm::launch_adj_row_2048, pm::launch_adj_row_4096};
+const AdjColLauncher kAdjCol[9] = {pm::launch_adj_col_16,  pm::launch_adj_col_32,   pm::launch_adj_col_64,
+                                   pm::launch_adj_col_128, pm::launch_adj_col_256,  pm::launch_adj_col_512,
+                                   pm::launch_adj_col_1024, pm::launch_adj_col_2048, pm::launch_adj_col_4096};
+
 using RowLauncher = hipError_t (*)(int, const pm::RowParams&, int, hipStream_t, hipEvent_t, hipEvent_t);
 using ColLauncher = hipError_t (*)(int, const pm::ColParams&, int, hipStream_t, hipEvent_t, hipEvent_t);
 
@@ -585,6 +594,55 @@ pm_status phasemask_solve_batched(pm_handle h, const float* const* targets, cons
     const bool err = final_err != nullptr;
     if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_batch(h, h->stream, n_iter, err);
     return launch_graph(h, n_iter, err);
+}
+
+pm_status phasemask_intensity_loss_fwd(pm_handle h, int batch, const float* phase,
+                                       const float* target_intensity, double* loss, void* saved) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    if (!phase || !target_intensity || !loss || !saved) return fail(PM_EINVAL, "null array argument");
+    if (batch < 1 || batch > 65535) return fail(PM_EINVAL, "batch must be in [1, 65535]");
+    if (misaligned(phase, 4) || misaligned(target_intensity, 4) || misaligned(loss, 8) || misaligned(saved, 8))
+        return fail(PM_EINVAL, "misaligned array argument");
+    st = ensure_partials(h, (size_t)batch);
+    if (st != PM_OK) return st;
+    pm::AdjParams p{};
+    p.saved = (float2*)saved;
+    p.phase = phase;
+    p.inten = target_intensity;
+    p.part = h->part;
+    p.twW = h->twW;
+    p.twH = h->twH;
+    p.H = h->H;
+    p.W = h->W;
+    p.nwg = h->nwg_col;
+    hipStream_t s = h->stream;
+    PM_TRY(kAdjRow[log2i(h->W) - 4](pm::ROW_INIT, p, batch, s), "loss row pass");
+    PM_TRY(kAdjCol[log2i(h->H) - 4](p, batch, s), "loss column pass");
+    PM_TRY(pm::launch_sum_rows(h->part, h->nwg_col, loss, batch, s), "loss sum");
+    return PM_OK;
+}
+
+pm_status phasemask_intensity_loss_bwd(pm_handle h, int batch, const float* phase, const void* saved,
+                                       const double* grad_loss, float* grad_phase) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    if (!phase || !saved || !grad_loss || !grad_phase) return fail(PM_EINVAL, "null array argument");
+    if (batch < 1 || batch > 65535) return fail(PM_EINVAL, "batch must be in [1, 65535]");
+    if (misaligned(phase, 4) || misaligned(saved, 8) || misaligned(grad_loss, 8) || misaligned(grad_phase, 4))
+        return fail(PM_EINVAL, "misaligned array argument");
+    pm::AdjParams p{};
+    p.saved = (float2*)saved;
+    p.phase = phase;
+    p.grad = grad_phase;
+    p.grad_loss = grad_loss;
+    p.twW = h->twW;
+    p.twH = h->twH;
+    p.H = h->H;
+    p.W = h->W;
+    p.nwg = h->nwg_col;
+    PM_TRY(kAdjRow[log2i(h->W) - 4](pm::ROW_GRAD, p, batch, h->stream), "gradient row pass");
+    return PM_OK;
 }
 
 pm_status phasemask_time_passes(pm_handle h, const float* target_amplitude, const float* phase, int reps,

@@ -211,6 +211,21 @@ hipError_t launch_batch_finalize(const BatchIo* io, const BatchMask* masks, int 
     return hipGetLastError();
 }
 
+// out[b] = sum of one row of partials, fixed order (one work-group per row).
+__global__ void __launch_bounds__(kAuxThreads) k_sum_rows(const double* part, int nwg, double* out) {
+    __shared__ double red[kAuxThreads / 64];
+    const double* p = part + (size_t)blockIdx.x * nwg;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nwg; i += kAuxThreads) acc += p[i];
+    const double tot = block_sum<kAuxThreads>(acc, red);
+    if (threadIdx.x == 0) out[blockIdx.x] = tot;
+}
+
+hipError_t launch_sum_rows(const double* part, int nwg, double* out, int count, hipStream_t s) {
+    k_sum_rows<<<count, kAuxThreads, 0, s>>>(part, nwg, out);
+    return hipGetLastError();
+}
+
 // ----- one-mask helpers -------------------------------------------------------
 
 hipError_t launch_set_io(PmIo* io, const PmIo& val, hipStream_t s) {

@@ -37,6 +37,7 @@ enum : int {
     ROUT_PHASE = 64,  // write atan2 of the projected field
     ROUT_NAT = 128,   // write a natural-layout complex image
     R_NOERR = 256,    // P_S without the gap partial sum
+    ROUT_GRAD = 512,  // intensity-loss gradient 4 gscale Im(e^{-i phi} g)
 };
 constexpr int ROW_INIT = RIN_PHASE | R_FWD;
 constexpr int ROW_ITER = RIN_TILED | R_INV | R_PS | R_FWD;
@@ -48,6 +49,7 @@ constexpr int ROW_FFT_INV = RIN_TILED | R_INV | ROUT_NAT;
 constexpr int ROW_ITER_NE = ROW_ITER | R_NOERR;
 constexpr int ROW_LAST_NE = ROW_LAST | R_NOERR;
 constexpr int ROW_LAST_FWD_NE = ROW_LAST_FWD | R_NOERR;
+constexpr int ROW_GRAD = RIN_TILED | R_INV | ROUT_GRAD;
 
 // Column-pass modes (bit sets).
 enum : int {
@@ -60,12 +62,14 @@ enum : int {
     COUT_TILED = 64,
     COUT_NAT = 128,
     C_NOERR = 256,    // M-hat without the Fourier-error partial sum
+    C_LOSS = 512,     // intensity residual r = |U|^2/N - I, loss partials, U <- r U
 };
 constexpr int COL_ITER = CIN_TILED | C_FWD | C_PROJ | C_INV | COUT_TILED;
 constexpr int COL_ERR = CIN_TILED | C_FWD | C_ERR;
 constexpr int COL_FFT_FWD = CIN_TILED | C_FWD | COUT_NAT;
 constexpr int COL_FFT_INV = CIN_NAT | C_INV | COUT_TILED;
 constexpr int COL_ITER_NE = COL_ITER | C_NOERR;
+constexpr int COL_LOSS = CIN_TILED | C_FWD | C_LOSS | C_INV | COUT_TILED;
 
 struct RowParams {
     float2* X;             // tiled iterate
@@ -76,6 +80,7 @@ struct RowParams {
     float2* nat_out;       // natural-layout output (ROUT_NAT)
     double* part;          // one gap partial per work-group (R_PS), null without
     int H;
+    float gscale;          // ROUT_GRAD: gradient scale 4 g_out / N
 };
 
 struct ColParams {
@@ -88,6 +93,20 @@ struct ColParams {
     double* part;          // one Fourier-error partial per work-group
     int W;
     double invN;           // 1 / (H W)
+    const float* inten;    // C_LOSS: target intensity, natural layout [H][W]
+};
+
+// Intensity-loss passes over a batch of same-size phases (blockIdx.y = sample).
+struct AdjParams {
+    float2* saved;              // [batch][N] tiled work buffer, kept from forward to backward
+    const float* phase;         // [batch][H][W]
+    const float* inten;         // [batch][H][W] target intensity
+    float* grad;                // [batch][H][W] gradient (backward)
+    const double* grad_loss;    // [batch] upstream gradient of each sample's loss (backward)
+    double* part;               // [batch][nwg] loss partials (forward)
+    const float2* twW;
+    const float2* twH;
+    int H, W, nwg;
 };
 
 // Launchers, one pair per supported transform length (16 .. 4096), defined
@@ -100,6 +119,20 @@ struct ColParams {
                               hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);      \
     hipError_t launch_col_##L(int mode, const ColParams& p, int grid, hipStream_t s,    \
                               hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+#define PM_DECLARE_ADJ_LAUNCHERS(L)                                                              \
+    hipError_t launch_adj_row_##L(int mode, const AdjParams& p, int batch, hipStream_t s);  \
+    hipError_t launch_adj_col_##L(const AdjParams& p, int batch, hipStream_t s);
+PM_DECLARE_ADJ_LAUNCHERS(16)
+PM_DECLARE_ADJ_LAUNCHERS(32)
+PM_DECLARE_ADJ_LAUNCHERS(64)
+PM_DECLARE_ADJ_LAUNCHERS(128)
+PM_DECLARE_ADJ_LAUNCHERS(256)
+PM_DECLARE_ADJ_LAUNCHERS(512)
+PM_DECLARE_ADJ_LAUNCHERS(1024)
+PM_DECLARE_ADJ_LAUNCHERS(2048)
+PM_DECLARE_ADJ_LAUNCHERS(4096)
+#undef PM_DECLARE_ADJ_LAUNCHERS
+
 PM_DECLARE_LAUNCHERS(16)
 PM_DECLARE_LAUNCHERS(32)
 PM_DECLARE_LAUNCHERS(64)
@@ -176,5 +209,7 @@ hipError_t launch_target_tile(const PmIo* io, int H, int W, const double* part, 
 hipError_t launch_finalize(const double* part, int stride, int nwg_col, int nwg_row, double invN,
                            const PmIo* io, int first_entry, int count, hipStream_t s);
 hipError_t launch_wrap_phase(const PmIo* io, int n, hipStream_t s);
+// out[b] = sum of part[b * nwg .. b * nwg + nwg) in a fixed order, b < count.
+hipError_t launch_sum_rows(const double* part, int nwg, double* out, int count, hipStream_t s);
 
 }  // namespace pm

@@ -137,6 +137,24 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
         }
     }
 
+    if constexpr ((MODE & C_LOSS) != 0) {
+        // Intensity loss L = sum_k (|U_k|^2 - I_k)^2 with unitary U: the
+        // unnormalised U here gives |U_unitary|^2 = |U|^2 / N (exact scaling).
+        // The residual-weighted field r U feeds the adjoint transform; its
+        // 1/sqrt(N) factors are folded into the gradient scale.
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            const float I = a.inten[(size_t)(j + T * t) * a.W + s * kC + c];
+            const float2 U = v[t];
+            const float r = (U.x * U.x + U.y * U.y) * (float)a.invN - I;
+            acc = fma((double)r, (double)r, acc);
+            v[t] = make_float2(U.x * r, U.y * r);
+        }
+        const double tot = block_sum<NT>(acc, red);
+        if (tid == 0) *part_slot = tot;
+    }
+
     if constexpr ((MODE & C_INV) != 0) fft_line<H, P, true, LD::NBUF, PAR1>(v, j, line, LD::STRIDE, tw);
 
     if constexpr ((MODE & COUT_TILED) != 0) {
@@ -230,6 +248,16 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
 #pragma unroll
         for (int t = 0; t < P; ++t) a.nat_out[natural(t)] = v[t];
     }
+    if constexpr ((MODE & ROUT_GRAD) != 0) {
+        // v = unnormalised inverse of r U, i.e. N F^H(r U) up to the scale the
+        // column pass left out; dL/dphi = 4 Im(e^{-i phi} F^H(r U)).
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            float sn, cs;
+            sincosf(phase_in[natural(t)], &sn, &cs);
+            phase_out[natural(t)] = a.gscale * (cs * v[t].y - sn * v[t].x);
+        }
+    }
     if constexpr ((MODE & R_FWD) != 0) {
         fft_line<W, P, false, LD::NBUF, PAR1>(v, j, line, LD::STRIDE, tw);
 #pragma unroll
@@ -258,6 +286,48 @@ k_row(RowParams a) {
     if constexpr ((MODE & RIN_PHASE) != 0) pin = a.io->phase_in;
     if constexpr ((MODE & ROUT_PHASE) != 0) pout = a.io->phase_out;
     row_body<W, kGR, MODE>(a, blockIdx.x * kGR, pin, pout, a.part + blockIdx.x, lds, red);
+}
+
+// Intensity-loss kernels over a batch of same-size phases, sample = blockIdx.y.
+// Forward: ROW_INIT (exp(i phi), row FFT) then the column kernel (COL_LOSS).
+// Backward: ROW_GRAD.
+template <int W, int MODE>
+__global__ void __launch_bounds__(kGR * LineShape<W>::T)
+k_row_adj(AdjParams p) {
+    constexpr int NT = kGR * LineShape<W>::T;
+    __shared__ float2 lds[LdsPlan<W, kGR>::FLOATS2];
+    __shared__ double red[(NT + 63) / 64];
+    const size_t n = (size_t)p.H * W;
+    const size_t b = blockIdx.y;
+    RowParams a{};
+    a.X = p.saved + b * n;
+    a.tw = p.twW;
+    a.tw_step = 1;
+    a.H = p.H;
+    float* out = nullptr;
+    if constexpr ((MODE & ROUT_GRAD) != 0) {
+        a.gscale = (float)(4.0 * p.grad_loss[b] / (double)n);
+        out = p.grad + b * n;
+    }
+    row_body<W, kGR, MODE>(a, blockIdx.x * kGR, p.phase + b * n, out, nullptr, lds, red);
+}
+
+template <int H>
+__global__ void __launch_bounds__(kC * LineShape<H>::T)
+k_col_adj(AdjParams p) {
+    constexpr int NT = kC * LineShape<H>::T;
+    __shared__ float2 lds[LdsPlan<H, kC>::FLOATS2];
+    __shared__ double red[(NT + 63) / 64];
+    const size_t n = (size_t)H * p.W;
+    const size_t b = blockIdx.y;
+    ColParams a{};
+    a.X = p.saved + b * n;
+    a.tw = p.twH;
+    a.tw_step = 1;
+    a.W = p.W;
+    a.invN = 1.0 / (double)n;
+    a.inten = p.inten + b * n;
+    col_body<H, kC, COL_LOSS>(a, blockIdx.x, p.part + b * p.nwg + blockIdx.x, lds, red);
 }
 
 }  // namespace pm

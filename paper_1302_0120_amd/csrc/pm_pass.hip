@@ -59,4 +59,20 @@ hipError_t PM_CAT(launch_col_, PM_L)(int mode, const ColParams& p, int grid, hip
     }
 }
 
+hipError_t PM_CAT(launch_adj_row_, PM_L)(int mode, const AdjParams& p, int batch, hipStream_t s) {
+    const dim3 grid(p.H / kGR, batch), block(kGR * LineShape<PM_L>::T);
+    switch (mode) {
+        case ROW_INIT: k_row_adj<PM_L, ROW_INIT><<<grid, block, 0, s>>>(p); break;
+        case ROW_GRAD: k_row_adj<PM_L, ROW_GRAD><<<grid, block, 0, s>>>(p); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t PM_CAT(launch_adj_col_, PM_L)(const AdjParams& p, int batch, hipStream_t s) {
+    const dim3 grid(p.W / kC, batch), block(kC * LineShape<PM_L>::T);
+    k_col_adj<PM_L><<<grid, block, 0, s>>>(p);
+    return hipGetLastError();
+}
+
 }  // namespace pm

@@ -1,0 +1,105 @@
+"""GPU parity of the intensity loss and its hand-written adjoint against the
+FP64 oracle (whose gradient is pinned by finite differences on the CPU).
+
+Tolerances: the loss within 1e-5 relative; the gradient within 1e-4 relative
+L2.  The gradient is 4 Im(e^{-i phi} F^H(r U)) with r = |U|^2 - I formed in
+FP32 from a transform with relative error ~1e-6, and the residual r is a
+difference of O(1) terms, so its relative error on pixels where |U|^2 ~ I
+is larger; 1e-4 over the whole field bounds that."""
+import numpy as np
+import pytest
+
+from oracle import gs
+from paper_1302_0120_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pmb():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1302_0120_amd import binding
+    return binding
+
+
+def _targets(batch, n, seed):
+    ts, ps = [], []
+    for b in range(batch):
+        rng = np.random.default_rng(seed + b)
+        m = synth.spot_amplitude(n, n, 20, 2.0, 0.5, 1.0, rng).astype(np.float64)
+        it = m * m
+        ts.append((it * (n * n / it.sum())).astype(np.float32))
+        ps.append(synth.uniform_phase(n, n, rng))
+    return np.stack(ts), np.stack(ps)
+
+
+@pytest.mark.parametrize("n,batch", [(64, 1), (128, 3), (512, 2)])
+def test_loss_and_gradient_vs_oracle(pmb, n, batch):
+    print(f"adjoint {n}x{n} batch {batch}", flush=True)
+    it, ph = _targets(batch, n, 50 + n)
+    plan = pmb.PhaseMask(n, n)
+    ph_d = torch.from_numpy(ph).cuda()
+    it_d = torch.from_numpy(it).cuda()
+    loss, saved = plan.intensity_loss_fwd(ph_d, it_d)
+    gl = torch.full((batch,), 0.5, dtype=torch.float64, device="cuda")
+    grad = plan.intensity_loss_bwd(ph_d, saved, gl).cpu().numpy()
+    loss = loss.cpu().numpy()
+    for b in range(batch):
+        ref_l = gs.intensity_loss(ph[b], it[b])
+        ref_g = 0.5 * gs.intensity_loss_grad(ph[b], it[b])
+        assert abs(loss[b] - ref_l) / ref_l <= 1e-5, (b, loss[b], ref_l)
+        assert np.linalg.norm(grad[b] - ref_g) / np.linalg.norm(ref_g) <= 1e-4
+
+
+def test_autograd_function_and_batch_consistency(pmb):
+    n, batch = 128, 3
+    it, ph = _targets(batch, n, 70)
+    ph_d = torch.from_numpy(ph).cuda().requires_grad_(True)
+    it_d = torch.from_numpy(it).cuda()
+    loss = pmb.intensity_loss(ph_d, it_d)
+    assert loss.shape == (batch,) and loss.dtype == torch.float64
+    loss.sum().backward()
+    g_batch = ph_d.grad.clone()
+    for b in range(batch):
+        p1 = torch.from_numpy(ph[b]).cuda().requires_grad_(True)
+        l1 = pmb.intensity_loss(p1, it_d[b])
+        assert l1.dim() == 0 and l1.item() == loss[b].item()
+        l1.backward()
+        assert torch.equal(p1.grad, g_batch[b])
+    ref = gs.intensity_loss_grad(ph[1], it[1])
+    assert np.linalg.norm(g_batch[1].cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-4
+
+
+def test_gradient_vanishes_at_exact_solution(pmb):
+    n = 64
+    rng = np.random.default_rng(5)
+    ph = rng.uniform(0, 2 * np.pi, (n, n)).astype(np.float32)
+    it = (np.abs(gs.F(np.exp(1j * ph.astype(np.float64)))) ** 2).astype(np.float32)
+    plan = pmb.PhaseMask(n, n)
+    ph_d = torch.from_numpy(ph).cuda()
+    loss, saved = plan.intensity_loss_fwd(ph_d, torch.from_numpy(it).cuda())
+    g = plan.intensity_loss_bwd(ph_d, saved, torch.ones(1, dtype=torch.float64, device="cuda"))
+    # FP32 floor: |U|^2 from a unit-modulus field carries ~1e-7 relative error
+    assert loss.item() <= 1e-8 * n * n
+    assert g.abs().max().item() <= 1e-3
+
+
+def test_adam_steps_reduce_loss(pmb):
+    n, batch = 128, 2
+    it, ph = _targets(batch, n, 90)
+    it_d = torch.from_numpy(it).cuda()
+    p = torch.from_numpy(ph).cuda().requires_grad_(True)
+    opt = torch.optim.Adam([p], lr=0.03)
+    first = None
+    for _ in range(40):
+        opt.zero_grad()
+        loss = pmb.intensity_loss(p, it_d).sum()
+        if first is None:
+            first = loss.item()
+        loss.backward()
+        opt.step()
+    last = pmb.intensity_loss(p.detach(), it_d).sum().item()
+    assert last < 0.5 * first
