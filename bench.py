@@ -103,6 +103,77 @@ def bench_batched(torch, binding, synth, steps):
     }
 
 
+def bench_adjoint(torch, binding, synth, lr, steps=200):
+    """16 x 512^2 phases, 50-spot intensity targets I = m^2 scaled to sum N:
+    200 Adam steps on the intensity loss (forward and adjoint kernels) versus
+    200 GS iterations on the amplitude m = sqrt(I), compared by the
+    Fourier-plane error E_F of the resulting masks."""
+    import numpy as np
+    batch, n = 16, 512
+    it_np, ph_np = synth.intensity_problems(batch=batch, size=n, n_spots=50)
+    it_np = (it_np.astype(np.float64) * (n * n / it_np.astype(np.float64).sum(axis=(1, 2), keepdims=True)))
+    it_np = it_np.astype(np.float32)
+    m_np = np.sqrt(it_np.astype(np.float64)).astype(np.float32)
+    dev = torch.device("cuda", 0)
+    it_d = torch.from_numpy(it_np).to(dev)
+    m_list = [torch.from_numpy(m_np[b]).to(dev) for b in range(batch)]
+    ph0 = torch.from_numpy(ph_np).to(dev)
+    bp = binding.BatchedPhaseMask([(n, n)] * batch, device=dev)
+
+    def ef_of(phases):
+        _, e = bp.solve(m_list, [phases[b] for b in range(batch)], 0)
+        return e
+
+    # Adam on the intensity loss
+    p = ph0.clone().requires_grad_(True)
+    opt = torch.optim.Adam([p], lr=lr)
+
+    def adam_step():
+        opt.zero_grad(set_to_none=False)
+        loss = binding.intensity_loss(p, it_d).sum()
+        loss.backward()
+        opt.step()
+    adam_step()  # warm-up (plan creation, optimizer state)
+    with torch.no_grad():
+        p.copy_(ph0)
+    opt = torch.optim.Adam([p], lr=lr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        adam_step()
+    torch.cuda.synchronize()
+    t_adam = time.perf_counter() - t0
+    ef_adam = ef_of(p.detach()).mean().item()
+
+    # GS on the amplitudes, same initial phases, batched
+    outs = [torch.empty((n, n), dtype=torch.float32, device=dev) for _ in range(batch)]
+    phs = [ph0[b] for b in range(batch)]
+    bp.solve(m_list, phs, steps, outs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, e_gs = bp.solve(m_list, phs, steps, outs=outs)
+    torch.cuda.synchronize()
+    t_gs = time.perf_counter() - t0
+    ef_gs = e_gs.mean().item()
+    # GS iterations (mean history over the batch) needed to reach Adam's error
+    hist = torch.zeros(2 * steps + 1, dtype=torch.float64, device=dev)
+    plan = binding.PhaseMask(n, n, device=dev)
+    for b in range(batch):
+        _, h = plan.solve(m_list[b], phs[b], steps)
+        hist += h
+    ef_hist = (hist[0::2] / batch).cpu().numpy()
+    reach = np.nonzero(ef_hist <= ef_adam)[0]
+    nu_equal = int(reach[0]) if reach.size else None
+    return {
+        "workload": "16 x 512^2 phases, 50-spot intensity targets (seeds 500+b), sum I = N",
+        "adam": {"steps": steps, "lr": lr, "ms_per_step": t_adam * 1e3 / steps,
+                 "total_ms": t_adam * 1e3, "final_fourier_error_mean": ef_adam},
+        "gs": {"iterations": steps, "total_ms": t_gs * 1e3, "final_fourier_error_mean": ef_gs},
+        "gs_iterations_to_adam_error": nu_equal,
+        "gs_ms_to_adam_error": (t_gs * 1e3 * nu_equal / steps) if nu_equal is not None else None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +186,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-versus-plain measurement")
     ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the Adam-versus-GS measurement")
+    ap.add_argument("--adam-lr", type=float, default=0.1,
+                    help="chosen from {0.01, 0.03, 0.1} by the final Fourier error of the workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 64 MiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -197,6 +272,8 @@ def main():
     }
     if not args.no_batched:
         line["batched"] = bench_batched(torch, binding, synth, args.batched_steps)
+    if not args.no_adjoint:
+        line["adjoint"] = bench_adjoint(torch, binding, synth, args.adam_lr)
     if not args.no_cpu_baseline:
         rate, cdt = cpu_baseline(m, phi0, args.cpu_iters)
         line["cpu_baseline"] = {
