@@ -68,6 +68,8 @@ typedef enum {
 /* Flags for phasemask_create. */
 #define PM_FLAG_NO_GRAPH 0x1u   /* launch kernels one by one instead of
                                    replaying a captured HIP graph           */
+#define PM_FLAG_NO_TUNE 0x2u    /* batched plans: use FFT schedule 0 instead
+                                   of timing the schedules at creation      */
 
 /*
  * Create a plan for masks of height x width pixels (Sec. II: n_y = height,
@@ -145,7 +147,17 @@ pm_status phasemask_fft2(pm_handle h, const void* in, void* out, int inverse);
  * the whole solve is one captured graph.
  *   heights, widths   HOST arrays of `count` sizes, each a power of two in
  *                     [64, 1024] (else PM_EUNSUPPORTED).
- * Errors: PM_EINVAL for NULL arguments or count < 1; PM_ENOMEM; PM_EDEVICE.
+ * FFT schedules: the batched passes have several compiled schedules (points
+ * per thread, i.e. radix sequence, and lines per work-group).  At creation
+ * the plan picks one: the environment variable PHASEMASK_SCHEDULE=<k>
+ * forces schedule k; else a choice cached for the same multiset of sizes on
+ * the same GPU architecture (in this process, or in the file named by
+ * PHASEMASK_TUNE_CACHE, one "key schedule" line per entry, appended to);
+ * else each schedule runs a few iterations on the plan's own buffers on
+ * `stream` (synchronised) and the fastest is kept.  PM_FLAG_NO_TUNE selects
+ * schedule 0 without timing.  PHASEMASK_LOG=1 prints the timings to stderr.
+ * Errors: PM_EINVAL for NULL arguments, count < 1 or an out-of-range
+ * PHASEMASK_SCHEDULE; PM_ENOMEM; PM_EDEVICE.
  * A batched handle works with phasemask_solve_batched, phasemask_set_stream,
  * phasemask_workspace_bytes and phasemask_destroy; other entry points
  * return PM_ESTATE for it.
@@ -164,13 +176,19 @@ pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights
  *                     returned mask (the last history entry of a one-mask
  *                     solve).
  * Results equal `count` separate phasemask_solve calls on the same inputs
- * (the phases bitwise; the errors up to the order of the FP64 sums).
+ * up to FP32 rounding; under schedule 0 (the one-mask radix schedules) the
+ * phases are bitwise equal and the errors equal up to the order of the FP64
+ * sums.
  * Errors: PM_EINVAL for NULL pointer arrays, n_iter < 0 or misaligned
  * arguments; PM_ESTATE for a one-mask handle; PM_EDEVICE.
  */
 pm_status phasemask_solve_batched(pm_handle h, const float* const* targets,
                                   const float* const* init_phases, int n_iter,
                                   float* const* out_phases, double* final_err);
+
+/* FFT schedule a batched plan runs (0 .. schedules-1), or -1 for a NULL or
+ * one-mask handle. */
+int phasemask_batch_schedule(pm_handle h);
 
 /*
  * Intensity loss and its gradient (differentiable phase optimisation beside

@@ -35,6 +35,7 @@ _SIGNATURES = {
                                                     ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_intensity_loss_bwd": (ctypes.c_int, [_c_handle, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "phasemask_batch_schedule": (ctypes.c_int, [_c_handle]),
     "phasemask_time_passes": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                              ctypes.POINTER(ctypes.c_float),
                                              ctypes.POINTER(ctypes.c_float)]),
@@ -44,6 +45,7 @@ _SIGNATURES = {
 }
 
 PM_FLAG_NO_GRAPH = 0x1
+PM_FLAG_NO_TUNE = 0x2
 
 STATUS = {0: "PM_OK", -1: "PM_EINVAL", -2: "PM_EUNSUPPORTED", -3: "PM_ENOMEM",
           -4: "PM_EDEVICE", -5: "PM_ESTATE"}
@@ -255,6 +257,10 @@ class BatchedPhaseMask:
         _check(lib.phasemask_solve_batched(self._h, tp.data_ptr(), pp.data_ptr(), int(n_iter),
                                            op.data_ptr(), ep or None), "phasemask_solve_batched")
         return outs, err
+
+    @property
+    def schedule(self) -> int:
+        return int(lib.phasemask_batch_schedule(self._h))
 
     @property
     def workspace_bytes(self) -> int:

@@ -21,6 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libphasemask.so")
 LENGTHS = (16, 32, 64, 128, 256, 512, 1024, 2048, 4096)
 ARCH = "gfx950"
+BATCH_SCHEDULES = 2  # = kBatchSchedules in csrc/pm_common.h
 
 # -packed-fp32-ops: keep hipcc from emitting packed FP32 instructions.
 HIPFLAGS = [
@@ -55,9 +56,10 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         steps.append([hipcc, *HIPFLAGS, f"-DPM_L={L}", "-c",
                       os.path.join(CSRC, "pm_pass.hip"), "-o", obj])
     for which in range(6):
-        steps.append([hipcc, *HIPFLAGS, f"-DPM_BATCH_WHICH={which}", "-c",
-                      os.path.join(CSRC, "pm_batch.hip"),
-                      "-o", os.path.join(BUILD, f"pm_batch_{which}.o")])
+        for sched in range(BATCH_SCHEDULES):
+            steps.append([hipcc, *HIPFLAGS, f"-DPM_BATCH_WHICH={which}", f"-DPM_BATCH_SCHED={sched}",
+                          "-c", os.path.join(CSRC, "pm_batch.hip"),
+                          "-o", os.path.join(BUILD, f"pm_batch_{which}_{sched}.o")])
     steps.append([hipcc, *HIPFLAGS, "-c", os.path.join(CSRC, "pm_aux.hip"),
                   "-o", os.path.join(BUILD, "pm_aux.o")])
     steps.append([hipcc, *HIPFLAGS, "-x", "hip", "-c", os.path.join(CSRC, "phasemask.cpp"),

@@ -10,6 +10,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <list>
 #include <new>
 #include <string>
@@ -102,6 +106,8 @@ struct pm_plan {
     int* mask_prep0 = nullptr;
     pm::BatchIo* bio = nullptr;
     float2* tw_batch = nullptr;
+    int sched = 0;                     // FFT schedule of the batched passes
+    size_t batch_ws_bytes = 0;
 };
 
 namespace {
@@ -281,13 +287,6 @@ pm_status launch_graph(pm_plan* h, int n_iter, bool hist) {
 
 // ----- batched solves ----------------------------------------------------------
 
-// Lines per work-group of the batched passes for a transform of length L
-// (kBatchThreads threads, points_per_thread(L) points each).
-int batch_lines(int L) {
-    const int P = L >= 256 ? 16 : (L >= 32 ? 8 : 4);
-    return pm::kBatchThreads / (L / P);
-}
-
 bool batch_len_ok(int n) {
     return n >= pm::kBatchMinLen && n <= pm::kBatchMaxLen && (n & (n - 1)) == 0;
 }
@@ -302,10 +301,41 @@ pm::BatchParams batch_params(pm_plan* h, const pm::BatchTask* tasks) {
     return p;
 }
 
+template <int SCHED>
+hipError_t batch_col_s(int mode, const pm::BatchParams& p, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    switch (mode) {
+        case pm::COL_ITER_NE: return pm::launch_batch_col<pm::COL_ITER_NE, SCHED>(p, grid, s, e0, e1);
+        case pm::COL_ERR: return pm::launch_batch_col<pm::COL_ERR, SCHED>(p, grid, s, e0, e1);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int SCHED>
+hipError_t batch_row_s(int mode, const pm::BatchParams& p, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    switch (mode) {
+        case pm::ROW_INIT: return pm::launch_batch_row<pm::ROW_INIT, SCHED>(p, grid, s, e0, e1);
+        case pm::ROW_ITER_NE: return pm::launch_batch_row<pm::ROW_ITER_NE, SCHED>(p, grid, s, e0, e1);
+        case pm::ROW_LAST_NE: return pm::launch_batch_row<pm::ROW_LAST_NE, SCHED>(p, grid, s, e0, e1);
+        case pm::ROW_LAST_FWD_NE: return pm::launch_batch_row<pm::ROW_LAST_FWD_NE, SCHED>(p, grid, s, e0, e1);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t batch_col(pm_plan* h, int mode, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+    const pm::BatchParams p = batch_params(h, h->col_tasks);
+    static_assert(pm::kBatchSchedules == 2, "one dispatch case per schedule");
+    return h->sched == 0 ? batch_col_s<0>(mode, p, h->n_col_tasks, s, e0, e1)
+                         : batch_col_s<1>(mode, p, h->n_col_tasks, s, e0, e1);
+}
+
+hipError_t batch_row(pm_plan* h, int mode, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+    const pm::BatchParams p = batch_params(h, h->row_tasks);
+    return h->sched == 0 ? batch_row_s<0>(mode, p, h->n_row_tasks, s, e0, e1)
+                         : batch_row_s<1>(mode, p, h->n_row_tasks, s, e0, e1);
+}
+
 // Whole batched solve after the pointer block is set.
 pm_status enqueue_batch(pm_plan* h, hipStream_t s, int n_iter, bool err) {
-    const pm::BatchParams pc = batch_params(h, h->col_tasks);
-    const pm::BatchParams pr = batch_params(h, h->row_tasks);
     if (n_iter == 0) {
         PM_TRY(pm::launch_batch_wrap(h->bio, h->masks, h->prep_tasks, h->n_prep_tasks, s), "batch wrap");
         if (!err) return PM_OK;
@@ -313,20 +343,159 @@ pm_status enqueue_batch(pm_plan* h, hipStream_t s, int n_iter, bool err) {
     PM_TRY(pm::launch_batch_norm(h->bio, h->prep_tasks, h->n_prep_tasks, h->part_m, s), "batch norm");
     PM_TRY(pm::launch_batch_tile(h->bio, h->masks, h->prep_tasks, h->n_prep_tasks, h->mask_prep0, h->part_m, s),
            "batch tile");
-    PM_TRY(pm::launch_batch_row<pm::ROW_INIT>(pr, h->n_row_tasks, s), "batch row init");
+    PM_TRY(batch_row(h, pm::ROW_INIT, s), "batch row init");
     for (int nu = 0; nu < n_iter; ++nu) {
-        PM_TRY(pm::launch_batch_col<pm::COL_ITER_NE>(pc, h->n_col_tasks, s), "batch column pass");
-        if (nu < n_iter - 1) {
-            PM_TRY(pm::launch_batch_row<pm::ROW_ITER_NE>(pr, h->n_row_tasks, s), "batch row pass");
-        } else if (err) {
-            PM_TRY(pm::launch_batch_row<pm::ROW_LAST_FWD_NE>(pr, h->n_row_tasks, s), "batch last row pass");
-        } else {
-            PM_TRY(pm::launch_batch_row<pm::ROW_LAST_NE>(pr, h->n_row_tasks, s), "batch last row pass");
-        }
+        PM_TRY(batch_col(h, pm::COL_ITER_NE, s), "batch column pass");
+        const int mode = nu < n_iter - 1 ? pm::ROW_ITER_NE : (err ? pm::ROW_LAST_FWD_NE : pm::ROW_LAST_NE);
+        PM_TRY(batch_row(h, mode, s), "batch row pass");
     }
     if (err) {
-        PM_TRY(pm::launch_batch_col<pm::COL_ERR>(pc, h->n_col_tasks, s), "batch column error");
+        PM_TRY(batch_col(h, pm::COL_ERR, s), "batch column error");
         PM_TRY(pm::launch_batch_finalize(h->bio, h->masks, h->count, h->part, s), "batch finalize");
+    }
+    return PM_OK;
+}
+
+// ----- batched schedule tuner --------------------------------------------------
+
+struct BatchLayout {
+    std::vector<pm::BatchMask> masks;
+    std::vector<pm::BatchTask> col, row;
+};
+
+// Task lists of one schedule; masks in `order` (largest first).
+BatchLayout batch_layout(int sched, int count, const int* heights, const int* widths,
+                         const std::vector<int>& order, const std::vector<float2*>& xs,
+                         const std::vector<float*>& ms) {
+    BatchLayout l;
+    l.masks.resize(count);
+    for (int i : order) {
+        const int H = heights[i], W = widths[i];
+        pm::BatchMask& mk = l.masks[i];
+        mk.H = H;
+        mk.W = W;
+        mk.X = xs[i];
+        mk.mhat = ms[i];
+        const int gc = pm::batch_lines(sched, H) / pm::kC;  // strips per column work-group
+        mk.col_wg0 = (int)l.col.size();
+        for (int s0 = 0; s0 < W / pm::kC; s0 += gc) l.col.push_back(pm::BatchTask{i, s0});
+        mk.col_wgs = (int)l.col.size() - mk.col_wg0;
+        const int gr = pm::batch_lines(sched, W);
+        for (int r0 = 0; r0 < H; r0 += gr) l.row.push_back(pm::BatchTask{i, r0});
+    }
+    return l;
+}
+
+hipError_t upload_layout(pm_plan* h, const BatchLayout& l) {
+    hipError_t e = hipMemcpy(h->masks, l.masks.data(), l.masks.size() * sizeof(pm::BatchMask), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(h->col_tasks, l.col.data(), l.col.size() * sizeof(pm::BatchTask), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(h->row_tasks, l.row.data(), l.row.size() * sizeof(pm::BatchTask), hipMemcpyHostToDevice);
+    h->n_col_tasks = (int)l.col.size();
+    h->n_row_tasks = (int)l.row.size();
+    return e;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+bool g_tune_file_read = false;
+
+std::string tune_key(int device, int count, const int* heights, const int* widths) {
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
+    std::vector<std::pair<int, int>> sz;
+    for (int i = 0; i < count; ++i) sz.emplace_back(heights[i], widths[i]);
+    std::sort(sz.begin(), sz.end());
+    std::ostringstream os;
+    os << arch.substr(0, arch.find(':')) << '|';
+    for (auto& p : sz) os << p.first << 'x' << p.second << ',';
+    return os.str();
+}
+
+// Average device time of `iters` batched iterations (column + row pass),
+// summed from the launches' own start/end events.
+hipError_t time_batch(pm_plan* h, int iters, double* ms_out) {
+    std::vector<hipEvent_t> ev(4 * (size_t)iters, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto& x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) {  // warm-up
+        e = batch_col(h, pm::COL_ITER_NE, h->stream);
+        if (e == hipSuccess) e = batch_row(h, pm::ROW_ITER_NE, h->stream);
+    }
+    for (int i = 0; i < iters && e == hipSuccess; ++i) {
+        e = batch_col(h, pm::COL_ITER_NE, h->stream, ev[4 * i], ev[4 * i + 1]);
+        if (e == hipSuccess) e = batch_row(h, pm::ROW_ITER_NE, h->stream, ev[4 * i + 2], ev[4 * i + 3]);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    double tot = 0.0;
+    for (int i = 0; i < 2 * iters && e == hipSuccess; ++i) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+        tot += ms;
+    }
+    for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
+    *ms_out = tot / iters;
+    return e;
+}
+
+// Picks the FFT schedule of a batched plan: PHASEMASK_SCHEDULE forces one;
+// otherwise a cached choice for the same sizes on the same architecture
+// (in-process, and the file named by PHASEMASK_TUNE_CACHE if set); otherwise
+// every schedule is timed on the plan's zeroed buffers and the fastest kept.
+pm_status tune_batch(pm_plan* h, const std::vector<BatchLayout>& layouts, const std::string& key) {
+    const char* force = std::getenv("PHASEMASK_SCHEDULE");
+    if (force != nullptr && force[0] != '\0') {
+        const int f = std::atoi(force);
+        if (f < 0 || f >= pm::kBatchSchedules) return fail(PM_EINVAL, "PHASEMASK_SCHEDULE out of range");
+        h->sched = f;
+        return PM_OK;
+    }
+    if (h->flags & PM_FLAG_NO_TUNE) {
+        h->sched = 0;
+        return PM_OK;
+    }
+    const char* path = std::getenv("PHASEMASK_TUNE_CACHE");
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (!g_tune_file_read && path != nullptr && path[0] != '\0') {
+            g_tune_file_read = true;
+            std::ifstream in(path);
+            std::string k;
+            int v;
+            while (in >> k >> v)
+                if (v >= 0 && v < pm::kBatchSchedules) g_tune_cache[k] = v;
+        }
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            h->sched = it->second;
+            return PM_OK;
+        }
+    }
+    PM_TRY(hipMemsetAsync(h->batch_ws, 0, h->batch_ws_bytes, h->stream), "hipMemsetAsync(tune)");
+    double best = 1e30;
+    int best_s = 0;
+    for (int sc = 0; sc < pm::kBatchSchedules; ++sc) {
+        h->sched = sc;
+        PM_TRY(upload_layout(h, layouts[sc]), "upload layout");
+        double ms = 0.0;
+        PM_TRY(time_batch(h, 5, &ms), "tune timing");
+        if (std::getenv("PHASEMASK_LOG") != nullptr)
+            std::fprintf(stderr, "phasemask tune %s schedule %d: %.1f us/iteration\n", key.c_str(), sc, ms * 1e3);
+        if (ms < best) {
+            best = ms;
+            best_s = sc;
+        }
+    }
+    h->sched = best_s;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best_s;
+    if (path != nullptr && path[0] != '\0') {
+        std::ofstream outf(path, std::ios::app);
+        outf << key << ' ' << best_s << '\n';
     }
     return PM_OK;
 }
@@ -491,7 +660,7 @@ pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights
     if (out == nullptr) return fail(PM_EINVAL, "out is NULL");
     *out = nullptr;
     if (count < 1 || heights == nullptr || widths == nullptr) return fail(PM_EINVAL, "need count >= 1 and sizes");
-    if ((flags & ~PM_FLAG_NO_GRAPH) != 0) return fail(PM_EINVAL, "unknown flag bits");
+    if ((flags & ~(PM_FLAG_NO_GRAPH | PM_FLAG_NO_TUNE)) != 0) return fail(PM_EINVAL, "unknown flag bits");
     for (int i = 0; i < count; ++i)
         if (!batch_len_ok(heights[i]) || !batch_len_ok(widths[i]))
             return fail(PM_EUNSUPPORTED, "batched sizes must be powers of two in [64, 1024]");
@@ -515,9 +684,6 @@ pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return (long)heights[a] * widths[a] > (long)heights[b] * widths[b];
     });
-    std::vector<pm::BatchMask> masks(count);
-    std::vector<pm::BatchTask> col, row, prep;
-    std::vector<int> prep0(count);
     size_t off = 0;
     std::vector<size_t> xoff(count), moff(count);
     for (int i = 0; i < count; ++i) {
@@ -527,32 +693,32 @@ pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights
         moff[i] = off;
         off += ((n * sizeof(float) + 255) / 256) * 256;
     }
-    for (int i : order) {
-        const int H = heights[i], W = widths[i];
-        pm::BatchMask& mk = masks[i];
-        mk.H = H;
-        mk.W = W;
-        const int gc = batch_lines(H) / pm::kC;  // strips per column work-group
-        mk.col_wg0 = (int)col.size();
-        for (int s0 = 0; s0 < W / pm::kC; s0 += gc) col.push_back(pm::BatchTask{i, s0});
-        mk.col_wgs = (int)col.size() - mk.col_wg0;
-        const int gr = batch_lines(W);
-        for (int r0 = 0; r0 < H; r0 += gr) row.push_back(pm::BatchTask{i, r0});
-        prep0[i] = (int)prep.size();
-        for (int p0 = 0; p0 < H * W; p0 += pm::kPrepPixels) prep.push_back(pm::BatchTask{i, p0});
-    }
-    h->n_col_tasks = (int)col.size();
-    h->n_row_tasks = (int)row.size();
-    h->n_prep_tasks = (int)prep.size();
     if ((e = hipMalloc(&h->batch_ws, off)) != hipSuccess) return bail(e, "hipMalloc(batch workspace)");
+    h->batch_ws_bytes = off;
+    std::vector<float2*> xs(count);
+    std::vector<float*> ms(count);
     for (int i = 0; i < count; ++i) {
-        masks[i].X = (float2*)((char*)h->batch_ws + xoff[i]);
-        masks[i].mhat = (float*)((char*)h->batch_ws + moff[i]);
+        xs[i] = (float2*)((char*)h->batch_ws + xoff[i]);
+        ms[i] = (float*)((char*)h->batch_ws + moff[i]);
     }
-    const size_t npart = (size_t)std::max(h->n_col_tasks, h->n_row_tasks);
+    std::vector<BatchLayout> layouts;
+    size_t max_col = 0, max_row = 0;
+    for (int sc = 0; sc < pm::kBatchSchedules; ++sc) {
+        layouts.push_back(batch_layout(sc, count, heights, widths, order, xs, ms));
+        max_col = std::max(max_col, layouts.back().col.size());
+        max_row = std::max(max_row, layouts.back().row.size());
+    }
+    std::vector<pm::BatchTask> prep;
+    std::vector<int> prep0(count);
+    for (int i : order) {
+        prep0[i] = (int)prep.size();
+        for (int p0 = 0; p0 < heights[i] * widths[i]; p0 += pm::kPrepPixels) prep.push_back(pm::BatchTask{i, p0});
+    }
+    h->n_prep_tasks = (int)prep.size();
+    const size_t npart = std::max(max_col, max_row);
     if ((e = hipMalloc(&h->masks, count * sizeof(pm::BatchMask))) != hipSuccess) return bail(e, "hipMalloc(masks)");
-    if ((e = hipMalloc(&h->col_tasks, col.size() * sizeof(pm::BatchTask))) != hipSuccess) return bail(e, "hipMalloc(tasks)");
-    if ((e = hipMalloc(&h->row_tasks, row.size() * sizeof(pm::BatchTask))) != hipSuccess) return bail(e, "hipMalloc(tasks)");
+    if ((e = hipMalloc(&h->col_tasks, max_col * sizeof(pm::BatchTask))) != hipSuccess) return bail(e, "hipMalloc(tasks)");
+    if ((e = hipMalloc(&h->row_tasks, max_row * sizeof(pm::BatchTask))) != hipSuccess) return bail(e, "hipMalloc(tasks)");
     if ((e = hipMalloc(&h->prep_tasks, prep.size() * sizeof(pm::BatchTask))) != hipSuccess) return bail(e, "hipMalloc(tasks)");
     if ((e = hipMalloc(&h->mask_prep0, count * sizeof(int))) != hipSuccess) return bail(e, "hipMalloc(prep index)");
     if ((e = hipMalloc(&h->part, npart * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(partials)");
@@ -562,19 +728,21 @@ pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights
     h->part_entries = 1;
     h->stride = (int)npart;
     const std::vector<float2> tw = twiddles(pm::kBatchMaxLen);
-    struct Up { void* dst; const void* src; size_t n; } ups[] = {
-        {h->masks, masks.data(), count * sizeof(pm::BatchMask)},
-        {h->col_tasks, col.data(), col.size() * sizeof(pm::BatchTask)},
-        {h->row_tasks, row.data(), row.size() * sizeof(pm::BatchTask)},
-        {h->prep_tasks, prep.data(), prep.size() * sizeof(pm::BatchTask)},
-        {h->mask_prep0, prep0.data(), count * sizeof(int)},
-        {h->tw_batch, tw.data(), tw.size() * sizeof(float2)}};
-    for (const Up& u : ups)
-        if ((e = hipMemcpy(u.dst, u.src, u.n, hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "hipMemcpy(plan)");
+    if ((e = hipMemcpy(h->prep_tasks, prep.data(), prep.size() * sizeof(pm::BatchTask), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(h->mask_prep0, prep0.data(), count * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(h->tw_batch, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(e, "hipMemcpy(plan)");
+    const std::string key = tune_key(h->device, count, heights, widths);
+    pm_status ts = tune_batch(h, layouts, key);
+    if (ts != PM_OK) {
+        free_plan(h);
+        return ts;
+    }
+    if ((e = upload_layout(h, layouts[h->sched])) != hipSuccess) return bail(e, "hipMemcpy(layout)");
     if ((e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess)
         return bail(e, "hipStreamCreate");
     h->ws_bytes = off + npart * sizeof(double) + prep.size() * (sizeof(double) + sizeof(pm::BatchTask)) +
-                  (col.size() + row.size()) * sizeof(pm::BatchTask) + count * (sizeof(pm::BatchMask) + sizeof(int)) +
+                  (max_col + max_row) * sizeof(pm::BatchTask) + count * (sizeof(pm::BatchMask) + sizeof(int)) +
                   sizeof(pm::BatchIo) + pm::kBatchMaxLen * sizeof(float2);
     *out = h;
     return PM_OK;
@@ -644,6 +812,8 @@ pm_status phasemask_intensity_loss_bwd(pm_handle h, int batch, const float* phas
     PM_TRY(kAdjRow[log2i(h->W) - 4](pm::ROW_GRAD, p, batch, h->stream), "gradient row pass");
     return PM_OK;
 }
+
+int phasemask_batch_schedule(pm_handle h) { return (h != nullptr && h->batched) ? h->sched : -1; }
 
 pm_status phasemask_time_passes(pm_handle h, const float* target_amplitude, const float* phase, int reps,
                                 float* col_ms, float* row_ms) {

@@ -1,34 +1,53 @@
 // pm_batch.hip -- batched row and column passes: one launch covers every
 // mask of a batch, each work-group taking one task (mask, first line) and
-// running the pass body for that mask's size.  Compiled once per pass mode
-// (PM_BATCH_WHICH = 0 .. 5), in parallel.
+// running the pass body for that mask's size under the FFT schedule SCHED.
+// Compiled once per (pass mode, schedule): PM_BATCH_WHICH = 0 .. 5 and
+// PM_BATCH_SCHED = 0 .. kBatchSchedules - 1, in parallel.
+#include <hip/hip_ext.h>
+
 #include "pm_kernels.hpp"
 
 #ifndef PM_BATCH_WHICH
 #error "compile with -DPM_BATCH_WHICH=<0..5>"
 #endif
+#ifndef PM_BATCH_SCHED
+#error "compile with -DPM_BATCH_SCHED=<schedule>"
+#endif
 
 namespace pm {
 
-// Lines per work-group for a transform of length L at kBatchThreads threads.
-template <int L>
+template <int SCHED, int L>
 struct BatchShape {
-    static constexpr int G = kBatchThreads / LineShape<L>::T;
+    static constexpr int P = batch_points(SCHED, L);
+    static constexpr int G = batch_lines(SCHED, L);
+    static constexpr int FLOATS2 = LdsPlan<L, G>::FLOATS2;
 };
 
+template <int SCHED>
 constexpr int batch_lds_floats2() {
+    const int f[5] = {BatchShape<SCHED, 64>::FLOATS2, BatchShape<SCHED, 128>::FLOATS2,
+                      BatchShape<SCHED, 256>::FLOATS2, BatchShape<SCHED, 512>::FLOATS2,
+                      BatchShape<SCHED, 1024>::FLOATS2};
     int m = 0;
-    const int f[5] = {LdsPlan<64, BatchShape<64>::G>::FLOATS2, LdsPlan<128, BatchShape<128>::G>::FLOATS2,
-                      LdsPlan<256, BatchShape<256>::G>::FLOATS2, LdsPlan<512, BatchShape<512>::G>::FLOATS2,
-                      LdsPlan<1024, BatchShape<1024>::G>::FLOATS2};
     for (int i = 0; i < 5; ++i) m = f[i] > m ? f[i] : m;
     return m;
 }
-constexpr int kBatchLds = batch_lds_floats2();
 
-template <int MODE>
+#define PM_COL_CASE(L)                                                                             \
+    case L:                                                                                        \
+        a.tw_step = kBatchMaxLen / L;                                                              \
+        col_body<L, BatchShape<SCHED, L>::P, BatchShape<SCHED, L>::G, MODE>(a, task.first, slot, lds, red); \
+        break;
+#define PM_ROW_CASE(L)                                                                             \
+    case L:                                                                                        \
+        a.tw_step = kBatchMaxLen / L;                                                              \
+        row_body<L, BatchShape<SCHED, L>::P, BatchShape<SCHED, L>::G, MODE>(a, task.first, pin, pout, slot, \
+                                                                           lds, red);              \
+        break;
+
+template <int MODE, int SCHED>
 __global__ void __launch_bounds__(kBatchThreads) k_col_batch(BatchParams p) {
-    __shared__ float2 lds[kBatchLds];
+    __shared__ float2 lds[batch_lds_floats2<SCHED>()];
     __shared__ double red[kBatchThreads / 64];
     const BatchTask task = p.tasks[blockIdx.x];
     const BatchMask mk = p.masks[task.mask];
@@ -40,18 +59,18 @@ __global__ void __launch_bounds__(kBatchThreads) k_col_batch(BatchParams p) {
     a.invN = 1.0 / ((double)mk.H * (double)mk.W);
     double* slot = p.part + blockIdx.x;
     switch (mk.H) {
-        case 64: a.tw_step = kBatchMaxLen / 64; col_body<64, BatchShape<64>::G, MODE>(a, task.first, slot, lds, red); break;
-        case 128: a.tw_step = kBatchMaxLen / 128; col_body<128, BatchShape<128>::G, MODE>(a, task.first, slot, lds, red); break;
-        case 256: a.tw_step = kBatchMaxLen / 256; col_body<256, BatchShape<256>::G, MODE>(a, task.first, slot, lds, red); break;
-        case 512: a.tw_step = kBatchMaxLen / 512; col_body<512, BatchShape<512>::G, MODE>(a, task.first, slot, lds, red); break;
-        case 1024: a.tw_step = 1; col_body<1024, BatchShape<1024>::G, MODE>(a, task.first, slot, lds, red); break;
+        PM_COL_CASE(64)
+        PM_COL_CASE(128)
+        PM_COL_CASE(256)
+        PM_COL_CASE(512)
+        PM_COL_CASE(1024)
         default: break;
     }
 }
 
-template <int MODE>
+template <int MODE, int SCHED>
 __global__ void __launch_bounds__(kBatchThreads) k_row_batch(BatchParams p) {
-    __shared__ float2 lds[kBatchLds];
+    __shared__ float2 lds[batch_lds_floats2<SCHED>()];
     __shared__ double red[kBatchThreads / 64];
     const BatchTask task = p.tasks[blockIdx.x];
     const BatchMask mk = p.masks[task.mask];
@@ -65,39 +84,52 @@ __global__ void __launch_bounds__(kBatchThreads) k_row_batch(BatchParams p) {
     if constexpr ((MODE & ROUT_PHASE) != 0) pout = p.io->phases_out[task.mask];
     double* slot = p.part + blockIdx.x;
     switch (mk.W) {
-        case 64: a.tw_step = kBatchMaxLen / 64; row_body<64, BatchShape<64>::G, MODE>(a, task.first, pin, pout, slot, lds, red); break;
-        case 128: a.tw_step = kBatchMaxLen / 128; row_body<128, BatchShape<128>::G, MODE>(a, task.first, pin, pout, slot, lds, red); break;
-        case 256: a.tw_step = kBatchMaxLen / 256; row_body<256, BatchShape<256>::G, MODE>(a, task.first, pin, pout, slot, lds, red); break;
-        case 512: a.tw_step = kBatchMaxLen / 512; row_body<512, BatchShape<512>::G, MODE>(a, task.first, pin, pout, slot, lds, red); break;
-        case 1024: a.tw_step = 1; row_body<1024, BatchShape<1024>::G, MODE>(a, task.first, pin, pout, slot, lds, red); break;
+        PM_ROW_CASE(64)
+        PM_ROW_CASE(128)
+        PM_ROW_CASE(256)
+        PM_ROW_CASE(512)
+        PM_ROW_CASE(1024)
         default: break;
     }
 }
 
-template <int MODE>
-hipError_t launch_batch_col(const BatchParams& p, int grid, hipStream_t s) {
-    k_col_batch<MODE><<<grid, kBatchThreads, 0, s>>>(p);
+template <typename K>
+hipError_t launch_k(K kern, const BatchParams& p, int grid, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (ev0 != nullptr || ev1 != nullptr) {
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBatchThreads), 0, s, ev0, ev1, 0, p);
+    } else {
+        kern<<<grid, kBatchThreads, 0, s>>>(p);
+    }
     return hipGetLastError();
 }
 
-template <int MODE>
-hipError_t launch_batch_row(const BatchParams& p, int grid, hipStream_t s) {
-    k_row_batch<MODE><<<grid, kBatchThreads, 0, s>>>(p);
-    return hipGetLastError();
+template <int MODE, int SCHED>
+hipError_t launch_batch_col(const BatchParams& p, int grid, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    return launch_k(k_col_batch<MODE, SCHED>, p, grid, s, ev0, ev1);
 }
+
+template <int MODE, int SCHED>
+hipError_t launch_batch_row(const BatchParams& p, int grid, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    return launch_k(k_row_batch<MODE, SCHED>, p, grid, s, ev0, ev1);
+}
+
+#define PM_INST_COL(MODE) \
+    template hipError_t launch_batch_col<MODE, PM_BATCH_SCHED>(const BatchParams&, int, hipStream_t, hipEvent_t, hipEvent_t);
+#define PM_INST_ROW(MODE) \
+    template hipError_t launch_batch_row<MODE, PM_BATCH_SCHED>(const BatchParams&, int, hipStream_t, hipEvent_t, hipEvent_t);
 
 #if PM_BATCH_WHICH == 0
-template hipError_t launch_batch_col<COL_ITER_NE>(const BatchParams&, int, hipStream_t);
+PM_INST_COL(COL_ITER_NE)
 #elif PM_BATCH_WHICH == 1
-template hipError_t launch_batch_col<COL_ERR>(const BatchParams&, int, hipStream_t);
+PM_INST_COL(COL_ERR)
 #elif PM_BATCH_WHICH == 2
-template hipError_t launch_batch_row<ROW_INIT>(const BatchParams&, int, hipStream_t);
+PM_INST_ROW(ROW_INIT)
 #elif PM_BATCH_WHICH == 3
-template hipError_t launch_batch_row<ROW_ITER_NE>(const BatchParams&, int, hipStream_t);
+PM_INST_ROW(ROW_ITER_NE)
 #elif PM_BATCH_WHICH == 4
-template hipError_t launch_batch_row<ROW_LAST_NE>(const BatchParams&, int, hipStream_t);
+PM_INST_ROW(ROW_LAST_NE)
 #elif PM_BATCH_WHICH == 5
-template hipError_t launch_batch_row<ROW_LAST_FWD_NE>(const BatchParams&, int, hipStream_t);
+PM_INST_ROW(ROW_LAST_FWD_NE)
 #endif
 
 }  // namespace pm

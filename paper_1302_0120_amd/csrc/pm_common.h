@@ -155,6 +155,20 @@ constexpr int kBatchMinLen = 64;
 constexpr int kBatchMaxLen = 1024;
 constexpr int kPrepPixels = 4096;  // pixels per task of the batched target preparation
 
+// FFT schedules of the batched passes.  A schedule fixes, per transform
+// length L, the points per thread P (hence the radix sequence P, P, ...,
+// remainder: 16-16-2 or 8-8-8 at L = 512) and, at kBatchThreads threads, the
+// lines per work-group G = kBatchThreads P / L (the tile).  The plan's tuner
+// times every schedule on the plan's own buffers and keeps the fastest.
+constexpr int kBatchSchedules = 2;
+__host__ __device__ constexpr int batch_points(int sched, int L) {
+    return sched == 0 ? (L >= 256 ? 16 : 8)
+                      : (L >= 1024 ? 16 : (L >= 256 ? 8 : (L == 128 ? 16 : 4)));
+}
+__host__ __device__ constexpr int batch_lines(int sched, int L) {
+    return kBatchThreads * batch_points(sched, L) / L;
+}
+
 struct BatchMask {
     int H, W;
     int col_wg0, col_wgs;  // this mask's column-pass work-groups (first, count)
@@ -182,12 +196,15 @@ struct BatchParams {
     double* part;                    // one partial per work-group (error passes)
 };
 
-// Batched passes; MODE is one of the column / row modes.  Explicit
-// instantiations live in pm_batch.hip.
-template <int MODE>
-hipError_t launch_batch_col(const BatchParams& p, int grid, hipStream_t s);
-template <int MODE>
-hipError_t launch_batch_row(const BatchParams& p, int grid, hipStream_t s);
+// Batched passes; MODE is one of the column / row modes, SCHED the FFT
+// schedule.  Explicit instantiations live in pm_batch.hip.  With non-null
+// events the launch records its own start and end on them.
+template <int MODE, int SCHED>
+hipError_t launch_batch_col(const BatchParams& p, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
+                            hipEvent_t ev1 = nullptr);
+template <int MODE, int SCHED>
+hipError_t launch_batch_row(const BatchParams& p, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
+                            hipEvent_t ev1 = nullptr);
 
 // Batched preparation kernels (pm_aux.hip).  Prep tasks cover kPrepPixels
 // pixels of one mask each; mask_prep0[i] is mask i's first prep task.

@@ -59,9 +59,9 @@ __device__ __forceinline__ void store_shared(float2* p, float2 v) {
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int L>
+template <int L, int PP = points_per_thread(L)>
 struct LineShape {
-    static constexpr int P = points_per_thread(L);  // points per thread
+    static constexpr int P = PP;                    // points per thread (radix schedule)
     static constexpr int T = L / P;                 // threads per line
     static constexpr int LP = lds_line_len(L);      // padded LDS line
 };
@@ -71,13 +71,12 @@ struct LineShape {
 // strip0 + sl, column c of that strip, rows j + T t.  For a fixed t a wave's
 // loads are 64 / kC consecutive rows of one strip: one contiguous run.
 // `lds` holds LdsPlan<H, G>::FLOATS2 elements, `red` NT / 64 doubles.
-template <int H, int G, int MODE>
+template <int H, int P, int G, int MODE>
 __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double* part_slot,
                                          float2* lds, double* red) {
-    constexpr int P = LineShape<H>::P;
-    constexpr int T = LineShape<H>::T;
+    constexpr int T = LineShape<H, P>::T;
     constexpr int NT = G * T;
-    constexpr int LP = LineShape<H>::LP;
+    constexpr int LP = LineShape<H, P>::LP;
     using LD = LdsPlan<H, G>;
     static_assert(G % kC == 0, "whole strips per work-group");
 
@@ -171,14 +170,13 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
 // c), c fastest: row row0 + rho, thread index within the row j = jhi kC + c.
 // For a fixed t the element (row, j + T t) lies in strip jhi + (T / kC) t at
 // column c, so a wave's loads are runs of G kC contiguous elements.
-template <int W, int G, int MODE>
+template <int W, int P, int G, int MODE>
 __device__ __forceinline__ void row_body(const RowParams& a, int row0, const float* phase_in,
                                          float* phase_out, double* part_slot, float2* lds,
                                          double* red) {
-    constexpr int P = LineShape<W>::P;
-    constexpr int T = LineShape<W>::T;
+    constexpr int T = LineShape<W, P>::T;
     constexpr int NT = G * T;
-    constexpr int LP = LineShape<W>::LP;
+    constexpr int LP = LineShape<W, P>::LP;
     static_assert(T % kC == 0, "row threads must cover whole strips");
     using LD = LdsPlan<W, G>;
 
@@ -272,7 +270,7 @@ k_col(ColParams a) {
     constexpr int NT = kC * LineShape<H>::T;
     __shared__ float2 lds[LdsPlan<H, kC>::FLOATS2];
     __shared__ double red[(NT + 63) / 64];
-    col_body<H, kC, MODE>(a, blockIdx.x, a.part + blockIdx.x, lds, red);
+    col_body<H, LineShape<H>::P, kC, MODE>(a, blockIdx.x, a.part + blockIdx.x, lds, red);
 }
 
 template <int W, int MODE>
@@ -285,7 +283,7 @@ k_row(RowParams a) {
     float* pout = nullptr;
     if constexpr ((MODE & RIN_PHASE) != 0) pin = a.io->phase_in;
     if constexpr ((MODE & ROUT_PHASE) != 0) pout = a.io->phase_out;
-    row_body<W, kGR, MODE>(a, blockIdx.x * kGR, pin, pout, a.part + blockIdx.x, lds, red);
+    row_body<W, LineShape<W>::P, kGR, MODE>(a, blockIdx.x * kGR, pin, pout, a.part + blockIdx.x, lds, red);
 }
 
 // Intensity-loss kernels over a batch of same-size phases, sample = blockIdx.y.
@@ -309,7 +307,7 @@ k_row_adj(AdjParams p) {
         a.gscale = (float)(4.0 * p.grad_loss[b] / (double)n);
         out = p.grad + b * n;
     }
-    row_body<W, kGR, MODE>(a, blockIdx.x * kGR, p.phase + b * n, out, nullptr, lds, red);
+    row_body<W, LineShape<W>::P, kGR, MODE>(a, blockIdx.x * kGR, p.phase + b * n, out, nullptr, lds, red);
 }
 
 template <int H>
@@ -327,7 +325,7 @@ k_col_adj(AdjParams p) {
     a.W = p.W;
     a.invN = 1.0 / (double)n;
     a.inten = p.inten + b * n;
-    col_body<H, kC, COL_LOSS>(a, blockIdx.x, p.part + b * p.nwg + blockIdx.x, lds, red);
+    col_body<H, LineShape<H>::P, kC, COL_LOSS>(a, blockIdx.x, p.part + b * p.nwg + blockIdx.x, lds, red);
 }
 
 }  // namespace pm

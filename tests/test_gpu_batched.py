@@ -39,11 +39,14 @@ def _problems(shapes, seed0=300):
     return out
 
 
-def test_batched_equals_one_mask_solves(pmb):
+def test_batched_equals_one_mask_solves(pmb, monkeypatch):
+    """Schedule 0 runs the one-mask radix schedules, so phases are bitwise equal."""
     probs = _problems(SHAPES)
     n_iter = 6
     print(f"batched vs one-mask, {len(SHAPES)} masks, n={n_iter}", flush=True)
+    monkeypatch.setenv("PHASEMASK_SCHEDULE", "0")
     bp = pmb.BatchedPhaseMask(SHAPES)
+    assert bp.schedule == 0
     targets = [_dev(m) for m, _ in probs]
     phases = [_dev(p) for _, p in probs]
     outs, err = bp.solve(targets, phases, n_iter)
@@ -135,3 +138,43 @@ def test_batched_handle_kind_errors(pmb):
     with pytest.raises(pmb.PhaseMaskError) as ei:
         pmb.BatchedPhaseMask([(64, 2048)])
     assert ei.value.status == -2
+
+
+@pytest.mark.parametrize("sched", [0, 1])
+def test_every_schedule_matches_oracle(pmb, monkeypatch, sched):
+    shapes = [(64, 256), (128, 128), (256, 512), (512, 256), (1024, 64)]
+    probs = _problems(shapes, 700)
+    monkeypatch.setenv("PHASEMASK_SCHEDULE", str(sched))
+    bp = pmb.BatchedPhaseMask(shapes)
+    assert bp.schedule == sched
+    targets = [_dev(m) for m, _ in probs]
+    phases = [_dev(p) for _, p in probs]
+    outs1, e1 = bp.solve(targets, phases, 1)
+    outs, err = bp.solve(targets, phases, 20)
+    for i, (m, p) in enumerate(probs):
+        ref1 = gs.gs_solve(m, p, 1)
+        u1 = np.exp(1j * outs1[i].cpu().numpy().astype(np.float64))
+        assert np.linalg.norm(u1 - ref1["u"]) / np.linalg.norm(ref1["u"]) <= 1e-5, (sched, i)
+        ref = gs.gs_solve(m, p, 20)["history"][-1]
+        assert abs(err[i].item() - ref) / ref <= 1e-3, (sched, i)
+
+
+def test_tuner_picks_and_caches(pmb, monkeypatch, tmp_path):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.delenv("PHASEMASK_SCHEDULE", raising=False)
+    monkeypatch.setenv("PHASEMASK_TUNE_CACHE", str(cache))
+    shapes = [(512, 512), (256, 256), (256, 256), (128, 1024)]
+    bp = pmb.BatchedPhaseMask(shapes)
+    assert bp.schedule in (0, 1)
+    # same sizes in another order: same key, same (cached) choice
+    bp2 = pmb.BatchedPhaseMask(list(reversed(shapes)))
+    assert bp2.schedule == bp.schedule
+    if cache.exists():  # written when this process tuned these sizes first
+        lines = cache.read_text().split()
+        assert str(bp.schedule) in lines
+    nt = pmb.BatchedPhaseMask(shapes, flags=pmb.PM_FLAG_NO_TUNE)
+    assert nt.schedule == 0
+    monkeypatch.setenv("PHASEMASK_SCHEDULE", "7")
+    with pytest.raises(pmb.PhaseMaskError) as ei:
+        pmb.BatchedPhaseMask(shapes)
+    assert ei.value.status == -1
