@@ -11,8 +11,8 @@ Notation (Sec. II of the paper)
 -------------------------------
 * ``u`` in C^N is the field on the SLM, N = n_x * n_y, stored row-major as a
   ``[n_y][n_x]`` array (rows = y, columns = x).
-* ``p`` >= 0 is the illumination amplitude on the SLM (Eq. 1).  The device
-  path is phase-only, p = 1; the functions here accept a general p.
+* ``p`` >= 0 is the illumination amplitude on the SLM (Eq. 1); p = 1 (a
+  phase-only SLM) unless given.
 * ``m`` >= 0 is the target amplitude of the optical stimulation pattern
   (Eq. 2), in natural DFT order (zero frequency at ``[0][0]``).
 * ``F`` is the 2-D discrete Fourier transform, taken unitary here (forward
@@ -54,6 +54,8 @@ __all__ = [
     "physical_error",
     "intensity_loss",
     "intensity_loss_grad",
+    "raar_solve",
+    "paper_initial_phase",
 ]
 
 DBL_MIN = np.finfo(np.float64).tiny
@@ -132,15 +134,15 @@ def mask_errors(m: np.ndarray, phi: np.ndarray) -> tuple[float, float]:
     return fourier_error(u, m), gap(P_M(u, mt))
 
 
-def gs_solve(m: np.ndarray, phi0: np.ndarray, n_iter: int) -> dict:
-    """Method of alternating projections, Eq. 6, with p = 1.
+def gs_solve(m: np.ndarray, phi0: np.ndarray, n_iter: int, p: np.ndarray | None = None) -> dict:
+    """Method of alternating projections, Eq. 6 (p = 1 unless given).
 
-    u^0 = exp(i phi0); for nu = 0 .. n_iter-1:
+    u^0 = p exp(i phi0) (a point of S, Eq. 1); for nu = 0 .. n_iter-1:
         U      = F u^nu                          (Eq. 2 / Eq. 4b)
-        E_F^nu = || |U| - m~ || / sqrt N          (error before projecting)
+        E_F^nu = || |U| - m~ || / ||p||           (error before projecting)
         V      = M_hat(U)                         (Eq. 5)
         w      = F^{-1} V  = P_M u^nu             (Eq. 4b)
-        G^nu   = || |w| - 1 || / sqrt N           (Eq. 7, prose reading)
+        G^nu   = || |w| - p || / ||p||            (Eq. 7, prose reading)
         u^{nu+1} = P_S w                          (Eq. 4a)
     and finally E_F^n of the returned mask.
 
@@ -154,18 +156,62 @@ def gs_solve(m: np.ndarray, phi0: np.ndarray, n_iter: int) -> dict:
     phi0 = np.asarray(phi0, dtype=np.float64)
     if m.shape != phi0.shape or m.ndim != 2:
         raise ValueError("target and phase must be 2-D arrays of one shape")
-    n = m.size
-    mt = matched_target(m)
-    u = np.exp(1j * phi0)
+    pp = np.ones_like(m) if p is None else np.asarray(p, dtype=np.float64)
+    p_norm = np.linalg.norm(pp)
+    mt = matched_target(m, pp)
+    u = pp * np.exp(1j * phi0)
     hist = []
     for _ in range(n_iter):
         U = F(u)
-        hist.append(float(np.linalg.norm(np.abs(U) - mt) / np.sqrt(n)))
+        hist.append(float(np.linalg.norm(np.abs(U) - mt) / p_norm))
         w = F_inv(M_hat(U, mt))
-        hist.append(float(np.linalg.norm(np.abs(w) - 1.0) / np.sqrt(n)))
-        u = P_S(w)
-    hist.append(float(np.linalg.norm(np.abs(F(u)) - mt) / np.sqrt(n)))
+        hist.append(float(np.linalg.norm(np.abs(w) - pp) / p_norm))
+        u = P_S(w, pp)
+    hist.append(float(np.linalg.norm(np.abs(F(u)) - mt) / p_norm))
     return {"u": u, "phi": np.angle(u), "history": np.array(hist)}
+
+
+def raar_solve(m: np.ndarray, phi0: np.ndarray, n_iter: int, beta: float,
+               p: np.ndarray | None = None) -> dict:
+    """Relaxed averaged alternating reflections, the alternative the paper
+    names for problems where alternating projections stagnate (Sec. IV.B).
+
+    With the reflectors R_S = 2 P_S - I and R_M = 2 P_M - I:
+        x^{nu+1} = beta/2 (R_S R_M + I) x^nu + (1 - beta) P_M x^nu
+                 = beta P_S(2 P_M x^nu - x^nu) + beta x^nu + (1 - 2 beta) P_M x^nu,
+    started from x^0 = p exp(i phi0).  The mask is the shadow P_S x^n.
+    History: [E_F(x^0), E_F(x^1), ..., E_F(x^{n-1}), E_F(P_S x^n)] with
+    E_F(x) = || |F x| - m~ || / ||p|| (length n_iter + 1).  beta = 1 gives
+    the Douglas-Rachford average of reflections.
+    """
+    if n_iter < 0:
+        raise ValueError("n_iter must be >= 0")
+    m = np.asarray(m, dtype=np.float64)
+    pp = np.ones_like(m) if p is None else np.asarray(p, dtype=np.float64)
+    p_norm = np.linalg.norm(pp)
+    mt = matched_target(m, pp)
+    x = pp * np.exp(1j * np.asarray(phi0, dtype=np.float64))
+    hist = []
+    for _ in range(n_iter):
+        U = F(x)
+        hist.append(float(np.linalg.norm(np.abs(U) - mt) / p_norm))
+        pm = F_inv(M_hat(U, mt))
+        x = beta * P_S(2.0 * pm - x, pp) + beta * x + (1.0 - 2.0 * beta) * pm
+    u = P_S(x, pp)
+    hist.append(float(np.linalg.norm(np.abs(F(u)) - mt) / p_norm))
+    return {"x": x, "u": u, "phi": np.angle(u), "history": np.array(hist)}
+
+
+def paper_initial_phase(m: np.ndarray, t_d: float = 3e-4) -> np.ndarray:
+    """The paper's initial mask (Sec. IV, first paragraph), read as: binarise
+    the target pattern (lit where the normalised target intensity m~^2 /
+    max m~^2 exceeds t_d, the dark tolerance of Eq. 8b), take the inverse
+    transform of that 1-bit pattern back to the SLM plane, and keep its phase
+    (the projection onto S of the back-propagated pattern).  Phase 0 where
+    the back-propagated field is exactly zero (tie-break of Eq. 4a)."""
+    it = np.asarray(m, dtype=np.float64) ** 2
+    b = (it / it.max() > t_d).astype(np.float64)
+    return np.angle(P_S(F_inv(b)))
 
 
 def physical_error(m: np.ndarray, u: np.ndarray, t_l: float = 0.1,

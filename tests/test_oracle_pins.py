@@ -340,3 +340,73 @@ def test_stored_history_regression():
     h = gs.gs_solve(m, phi0, 100)["history"]
     assert stored.shape == h.shape
     assert np.max(np.abs(h - stored)) <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# General illumination p (Eq. 1), RAAR, the paper's initial mask
+# --------------------------------------------------------------------------
+
+def test_general_illumination_distances_and_chain():
+    """With p != 1 the history still equals SLM-plane distances relative to
+    ||p||, the iterates keep modulus p, and the chain is monotone."""
+    m, phi = _spots(32, 32, 6)
+    rng = np.random.default_rng(61)
+    pp = rng.uniform(0.3, 1.5, m.shape)
+    res = gs.gs_solve(m, phi, 8, p=pp)
+    h = res["history"]
+    mt = gs.matched_target(m, pp)
+    pn = np.linalg.norm(pp)
+    assert abs(np.linalg.norm(mt) - pn) <= 1e-12 * pn
+    u = pp * np.exp(1j * phi.astype(np.float64))
+    for nu in range(8):
+        v = gs.P_M(u, mt)
+        un = gs.P_S(v, pp)
+        assert abs(h[2 * nu] - np.linalg.norm(u - v) / pn) <= 1e-12
+        assert abs(h[2 * nu + 1] - np.linalg.norm(v - un) / pn) <= 1e-12
+        u = un
+    assert np.max(np.abs(np.abs(res["u"]) - pp)) <= 1e-13
+    assert np.all(np.diff(h) <= 1e-12)
+    # p = 1 given explicitly reproduces the phase-only solve
+    r1 = gs.gs_solve(m, phi, 8, p=np.ones_like(pp))
+    r0 = gs.gs_solve(m, phi, 8)
+    assert np.max(np.abs(r1["history"] - r0["history"])) <= 1e-15
+
+
+def test_raar_reductions():
+    """beta = 1/2: x+ = P_S(2 P_M x - x)/2 + x/2 (the average of x and the
+    reflection step), checked step by step; at a solution of S cap M every
+    beta leaves x fixed; RAAR does not blow up and its shadow improves on a
+    consistent target from a nearby start."""
+    m, phi = _spots(16, 16, 7)
+    mt = gs.matched_target(m)
+    x = np.exp(1j * phi.astype(np.float64))
+    res = gs.raar_solve(m, phi, 3, 0.5)
+    for _ in range(3):
+        pm = gs.P_M(x, mt)
+        x = 0.5 * gs.P_S(2 * pm - x) + 0.5 * x
+    assert np.max(np.abs(x - res["x"])) <= 1e-12
+    assert res["history"].shape == (4,)
+    rng = np.random.default_rng(41)
+    phit = rng.uniform(0, 2 * np.pi, (32, 32))
+    mc = np.abs(gs.F(np.exp(1j * phit)))
+    for beta in (0.5, 0.9, 1.0):
+        r = gs.raar_solve(mc, phit, 5, beta)
+        assert r["history"].max() <= 1e-13
+    r = gs.raar_solve(mc, phit + rng.uniform(-0.3, 0.3, phit.shape), 60, 0.9)
+    assert r["history"][-1] < 0.5 * r["history"][0]
+
+
+def test_paper_initial_phase():
+    """A single lit pixel at frequency (a, b) back-propagates to the plane
+    wave exp(+2 pi i (a y/h + b x/w)): the initial mask is that wave's phase.
+    A target lit everywhere back-propagates to sqrt(N) delta_0: phase 0."""
+    h, w = 16, 32
+    a, b = 3, 5
+    m = np.zeros((h, w))
+    m[a, b] = 2.0
+    phi = gs.paper_initial_phase(m)
+    ys = np.arange(h)[:, None]
+    xs = np.arange(w)[None, :]
+    want = np.exp(2j * np.pi * (a * ys / h + b * xs / w))
+    assert np.max(np.abs(np.exp(1j * phi) - want)) <= 1e-12
+    assert np.max(np.abs(gs.paper_initial_phase(np.ones((h, w))))) == 0.0
