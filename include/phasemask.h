@@ -129,6 +129,39 @@ pm_status phasemask_error(pm_handle h, const float* target_amplitude,
                           const float* phase, double* errors);
 
 /*
+ * The paper's initial mask (Sec. IV, first paragraph), read as: binarise the
+ * target (lit where m^2 / max m^2 > t_dark, an IEEE double comparison),
+ * back-propagate the 1-bit pattern with the inverse transform and keep the
+ * phase (the projection onto S, Eq. 4a, with its zero tie-break).  The paper
+ * uses t_dark = 3e-4, its dark tolerance of Eq. 8b.
+ *   target_amplitude  as for phasemask_solve.
+ *   out_phase         float[height*width] receives the phase in (-pi, pi];
+ *                     must not overlap the target.
+ * Errors: PM_EINVAL for NULL, misaligned or overlapping arrays, or t_dark
+ * outside [0, 1); PM_EDEVICE.
+ */
+pm_status phasemask_initial_phase(pm_handle h, const float* target_amplitude,
+                                  double t_dark, float* out_phase);
+
+/*
+ * Physical error of the mask exp(i phase) against a target (Eq. 8a, 8b):
+ *   errors[0] = E_lit  = sum over lit pixels  (t_dark rel / t_lit - t_dark) [rel > t_lit]
+ *   errors[1] = E_dark = sum over dark pixels (I_r - t_dark) [I_r > t_dark]
+ * with I_t = m^2 / max m^2, I_r = |F u|^2 / max |F u|^2, rel = |I_t - I_r| / I_t
+ * and a pixel lit where I_t > t_dark (the paper calls both quantities
+ * intensities and leaves their scale and the lit/dark split unstated; this is
+ * the reading above).  The paper's tolerances are t_lit = 0.1, t_dark = 3e-4
+ * (Sec. II, the paragraph defining the physical error).  FP64 sums; the
+ * plan keeps a 4-byte-per-pixel scratch buffer after the first call.
+ *   errors            DEVICE double[2].
+ * Errors: PM_EINVAL for NULL or misaligned arrays, t_lit <= 0 or t_dark
+ * outside [0, 1); PM_ENOMEM; PM_EDEVICE.
+ */
+pm_status phasemask_physical_error(pm_handle h, const float* target_amplitude,
+                                   const float* phase, double t_lit, double t_dark,
+                                   double* errors);
+
+/*
  * Unnormalised complex 2-D DFT through the library's own FFT passes (the
  * transform inside P_M, Eq. 4b):
  *   inverse = 0:  out[k] = sum_x in[x] exp(-2 pi i (k_y y/height + k_x x/width))

@@ -36,6 +36,9 @@ _SIGNATURES = {
     "phasemask_intensity_loss_bwd": (ctypes.c_int, [_c_handle, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                                     ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_batch_schedule": (ctypes.c_int, [_c_handle]),
+    "phasemask_initial_phase": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
+    "phasemask_physical_error": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_void_p]),
     "phasemask_time_passes": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                              ctypes.POINTER(ctypes.c_float),
                                              ctypes.POINTER(ctypes.c_float)]),
@@ -140,6 +143,29 @@ class PhaseMask:
         ep = _dev_ptr(out, torch.float64, (2,), "errors")
         self._stream()
         _check(lib.phasemask_error(self._h, tp, pp, ep), "phasemask_error")
+        return out
+
+    def initial_phase(self, target: torch.Tensor, t_dark: float = 3e-4, out: torch.Tensor | None = None):
+        """The paper's initial mask: phase of the back-propagated 1-bit target."""
+        tp = _dev_ptr(target, torch.float32, self.shape, "target")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        op = _dev_ptr(out, torch.float32, self.shape, "out")
+        self._stream()
+        _check(lib.phasemask_initial_phase(self._h, tp, float(t_dark), op), "phasemask_initial_phase")
+        return out
+
+    def physical_error(self, target: torch.Tensor, phase: torch.Tensor, t_lit: float = 0.1,
+                       t_dark: float = 3e-4, out: torch.Tensor | None = None):
+        """(E_lit, E_dark) of Eq. 8 as a float64 device tensor of 2 entries."""
+        tp = _dev_ptr(target, torch.float32, self.shape, "target")
+        pp = _dev_ptr(phase, torch.float32, self.shape, "phase")
+        if out is None:
+            out = torch.empty(2, dtype=torch.float64, device=self.device)
+        ep = _dev_ptr(out, torch.float64, (2,), "errors")
+        self._stream()
+        _check(lib.phasemask_physical_error(self._h, tp, pp, float(t_lit), float(t_dark), ep),
+               "phasemask_physical_error")
         return out
 
     def fft2(self, x: torch.Tensor, inverse: bool = False, out: torch.Tensor | None = None):

@@ -87,6 +87,8 @@ struct pm_plan {
     float2* twW = nullptr;
     float2* twH = nullptr;
     double* part_m = nullptr;
+    float* part_mx = nullptr;          // per-work-group maxima of a target
+    float* pw = nullptr;               // |U|^2 / N scratch of the physical error, on first use
     double* part = nullptr;
     size_t part_entries = 0;           // capacity of `part` in history entries
     pm::PmIo* io = nullptr;
@@ -132,6 +134,8 @@ void free_plan(pm_plan* h) {
     (void)hipFree(h->twW);
     (void)hipFree(h->twH);
     (void)hipFree(h->part_m);
+    (void)hipFree(h->part_mx);
+    (void)hipFree(h->pw);
     (void)hipFree(h->part);
     (void)hipFree(h->io);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -556,6 +560,7 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
     if ((e = hipMalloc(&h->twW, width * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
     if ((e = hipMalloc(&h->twH, height * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
     if ((e = hipMalloc(&h->part_m, kNormGrid * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(norm)");
+    if ((e = hipMalloc(&h->part_mx, kNormGrid * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc(max)");
     if ((e = hipMalloc(&h->io, sizeof(pm::PmIo))) != hipSuccess) return bail(e, "hipMalloc(io)");
     h->ws_bytes = n * (sizeof(float2) + sizeof(float)) + (size_t)(width + height) * sizeof(float2) +
                   kNormGrid * sizeof(double) + sizeof(pm::PmIo);
@@ -810,6 +815,62 @@ pm_status phasemask_intensity_loss_bwd(pm_handle h, int batch, const float* phas
     p.W = h->W;
     p.nwg = h->nwg_col;
     PM_TRY(kAdjRow[log2i(h->W) - 4](pm::ROW_GRAD, p, batch, h->stream), "gradient row pass");
+    return PM_OK;
+}
+
+pm_status phasemask_initial_phase(pm_handle h, const float* target_amplitude, double t_dark, float* out_phase) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    if (!target_amplitude || !out_phase) return fail(PM_EINVAL, "null array argument");
+    if (misaligned(target_amplitude, 16) || misaligned(out_phase, 4)) return fail(PM_EINVAL, "misaligned array argument");
+    if (!(t_dark >= 0.0 && t_dark < 1.0)) return fail(PM_EINVAL, "t_dark must be in [0, 1)");
+    if (overlaps(out_phase, (size_t)h->N * sizeof(float), target_amplitude, (size_t)h->N * sizeof(float)))
+        return fail(PM_EINVAL, "out_phase overlaps the target");
+    hipStream_t s = h->stream;
+    pm::PmIo io{target_amplitude, nullptr, out_phase, nullptr};
+    PM_TRY(pm::launch_set_io(h->io, io, s), "set io");
+    PM_TRY(pm::launch_max_partial(target_amplitude, h->N, h->part_mx, kNormGrid, s), "target max");
+    pm::ColParams cp = col_params(h, nullptr);
+    cp.tnat = target_amplitude;
+    cp.tmax_part = h->part_mx;
+    cp.ntmax = kNormGrid;
+    cp.t_dark = t_dark;
+    const RowLauncher row = kRowLaunch[log2i(h->W) - 4];
+    const ColLauncher col = kColLaunch[log2i(h->H) - 4];
+    PM_TRY(col(pm::COL_INIT_BIT, cp, h->nwg_col, s, nullptr, nullptr), "1-bit inverse column pass");
+    PM_TRY(row(pm::ROW_LAST_NE, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "inverse row pass");
+    return PM_OK;
+}
+
+pm_status phasemask_physical_error(pm_handle h, const float* target_amplitude, const float* phase, double t_lit,
+                                   double t_dark, double* errors) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    if (!target_amplitude || !phase || !errors) return fail(PM_EINVAL, "null array argument");
+    if (misaligned(target_amplitude, 16) || misaligned(phase, 4) || misaligned(errors, 8))
+        return fail(PM_EINVAL, "misaligned array argument");
+    if (!(t_lit > 0.0) || !(t_dark >= 0.0 && t_dark < 1.0)) return fail(PM_EINVAL, "need t_lit > 0, 0 <= t_dark < 1");
+    const size_t nblk = ((size_t)h->N / 4 + 255) / 256;
+    st = ensure_partials(h, 1 + (2 * nblk + h->stride - 1) / h->stride);
+    if (st != PM_OK) return st;
+    if (h->pw == nullptr) {
+        hipError_t e = hipMalloc(&h->pw, (size_t)h->N * sizeof(float));
+        if (e != hipSuccess) return fail_hip(e, "hipMalloc(power)");
+        h->ws_bytes += (size_t)h->N * sizeof(float);
+    }
+    hipStream_t s = h->stream;
+    pm::PmIo io{target_amplitude, phase, nullptr, nullptr};
+    PM_TRY(pm::launch_set_io(h->io, io, s), "set io");
+    PM_TRY(pm::launch_max_partial(target_amplitude, h->N, h->part_mx, kNormGrid, s), "target max");
+    const RowLauncher row = kRowLaunch[log2i(h->W) - 4];
+    const ColLauncher col = kColLaunch[log2i(h->H) - 4];
+    PM_TRY(row(pm::ROW_INIT, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+    pm::ColParams cp = col_params(h, h->part);
+    cp.pw = h->pw;
+    PM_TRY(col(pm::COL_POW, cp, h->nwg_col, s, nullptr, nullptr), "power column pass");
+    PM_TRY(pm::launch_physical_error(h->pw, h->part, h->nwg_col, target_amplitude, h->part_mx, kNormGrid, h->H,
+                                     h->W, t_lit, t_dark, h->part + h->stride, errors, s),
+           "physical error");
     return PM_OK;
 }
 

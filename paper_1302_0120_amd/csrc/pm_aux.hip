@@ -226,6 +226,105 @@ hipError_t launch_sum_rows(const double* part, int nwg, double* out, int count, 
     return hipGetLastError();
 }
 
+// ----- physical error (Eq. 8) and target maxima -------------------------------
+
+__global__ void __launch_bounds__(kAuxThreads) k_max_partial(const float* x, int n, float* part) {
+    __shared__ float redf[kAuxThreads / 64];
+    const float4* x4 = reinterpret_cast<const float4*>(x);
+    float mx = 0.0f;
+    for (int i = blockIdx.x * kAuxThreads + threadIdx.x; i < n / 4; i += gridDim.x * kAuxThreads) {
+        const float4 q = x4[i];
+        mx = fmaxf(fmaxf(mx, fmaxf(q.x, q.y)), fmaxf(q.z, q.w));
+    }
+    mx = block_max<kAuxThreads>(mx, redf);
+    if (threadIdx.x == 0) part[blockIdx.x] = mx;
+}
+
+// E_lit = sum over lit pixels of (t_d rel / t_l - t_d) [rel > t_l], rel = |It - Ir| / It;
+// E_dark = sum over dark pixels of (Ir - t_d) [Ir > t_d]; It = m^2 / max m^2,
+// Ir = |U|^2 / max |U|^2, lit where It > t_d (Eq. 8a / 8b, reading in the
+// design notes).  One thread per 4 consecutive strip-tiled pixels.
+__global__ void __launch_bounds__(kAuxThreads)
+k_physical_error(const float* pw, const double* pw_max_part, int n_pw_max, const float* target,
+                 const float* tmax_part, int ntmax, int H, int W, double t_lit, double t_dark,
+                 double* scratch) {
+    static_assert(kC == 4, "one float4 per strip chunk");
+    __shared__ double red[kAuxThreads / 64];
+    __shared__ float redf[kAuxThreads / 64];
+    __shared__ double pmax_s;
+    double pm = 0.0;
+    for (int i = threadIdx.x; i < n_pw_max; i += kAuxThreads) pm = fmax(pm, pw_max_part[i]);
+    float tm = 0.0f;
+    for (int i = threadIdx.x; i < ntmax; i += kAuxThreads) tm = fmaxf(tm, tmax_part[i]);
+    tm = block_max<kAuxThreads>(tm, redf);
+    pm = (double)block_max<kAuxThreads>((float)pm, redf);  // the partial maxima are floats
+    if (threadIdx.x == 0) pmax_s = pm;
+    __syncthreads();
+    const double pmax = pmax_s;
+    const double mx2 = (double)tm * (double)tm;
+    const int i4 = blockIdx.x * kAuxThreads + threadIdx.x;  // float4 index, strip-tiled
+    double e_lit = 0.0, e_dark = 0.0;
+    if (i4 < H * W / 4) {
+        const int s = i4 / H;   // strip
+        const int y = i4 - s * H;
+        const float4 q = reinterpret_cast<const float4*>(pw)[i4];
+        const float4 m = reinterpret_cast<const float4*>(target + (size_t)y * W)[s];
+        const float qs[4] = {q.x, q.y, q.z, q.w};
+        const float ms[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double it = ((double)ms[k] * (double)ms[k]) / mx2;
+            const double ir = (double)qs[k] / pmax;
+            if (it > t_dark) {
+                const double rel = fabs(it - ir) / it;
+                if (rel - t_lit > 0.0) e_lit += t_dark * rel / t_lit - t_dark;
+            } else if (ir - t_dark > 0.0) {
+                e_dark += ir - t_dark;
+            }
+        }
+    }
+    const double a = block_sum<kAuxThreads>(e_lit, red);
+    __syncthreads();
+    const double b = block_sum<kAuxThreads>(e_dark, red);
+    if (threadIdx.x == 0) {
+        scratch[2 * blockIdx.x] = a;
+        scratch[2 * blockIdx.x + 1] = b;
+    }
+}
+
+__global__ void __launch_bounds__(kAuxThreads) k_pair_sum(const double* scratch, int n, double* out) {
+    __shared__ double red[kAuxThreads / 64];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < n; i += kAuxThreads) {
+        a += scratch[2 * i];
+        b += scratch[2 * i + 1];
+    }
+    const double ta = block_sum<kAuxThreads>(a, red);
+    __syncthreads();
+    const double tb = block_sum<kAuxThreads>(b, red);
+    if (threadIdx.x == 0) {
+        out[0] = ta;
+        out[1] = tb;
+    }
+}
+
+hipError_t launch_max_partial(const float* x, int n, float* part, int grid, hipStream_t s) {
+    k_max_partial<<<grid, kAuxThreads, 0, s>>>(x, n, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_physical_error(const float* pw, const double* pw_max_part, int n_pw_max, const float* target,
+                                 const float* tmax_part, int ntmax, int H, int W, double t_lit, double t_dark,
+                                 double* scratch, double* out, hipStream_t s) {
+    const int grid = (H * W / 4 + kAuxThreads - 1) / kAuxThreads;
+    k_physical_error<<<grid, kAuxThreads, 0, s>>>(pw, pw_max_part, n_pw_max, target, tmax_part, ntmax, H, W,
+                                                  t_lit, t_dark, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_pair_sum<<<1, kAuxThreads, 0, s>>>(scratch, grid, out);
+    return hipGetLastError();
+}
+
 // ----- one-mask helpers -------------------------------------------------------
 
 hipError_t launch_set_io(PmIo* io, const PmIo& val, hipStream_t s) {

@@ -63,6 +63,8 @@ enum : int {
     COUT_NAT = 128,
     C_NOERR = 256,    // M-hat without the Fourier-error partial sum
     C_LOSS = 512,     // intensity residual r = |U|^2/N - I, loss partials, U <- r U
+    C_BIT = 1024,     // load the 1-bit target pattern (lit where m^2 / max m^2 > t_dark)
+    C_POW = 2048,     // store |U|^2 / N (float, strip-tiled) and the work-group maximum
 };
 constexpr int COL_ITER = CIN_TILED | C_FWD | C_PROJ | C_INV | COUT_TILED;
 constexpr int COL_ERR = CIN_TILED | C_FWD | C_ERR;
@@ -70,6 +72,8 @@ constexpr int COL_FFT_FWD = CIN_TILED | C_FWD | COUT_NAT;
 constexpr int COL_FFT_INV = CIN_NAT | C_INV | COUT_TILED;
 constexpr int COL_ITER_NE = COL_ITER | C_NOERR;
 constexpr int COL_LOSS = CIN_TILED | C_FWD | C_LOSS | C_INV | COUT_TILED;
+constexpr int COL_INIT_BIT = C_BIT | C_INV | COUT_TILED;
+constexpr int COL_POW = CIN_TILED | C_FWD | C_POW;
 
 struct RowParams {
     float2* X;             // tiled iterate
@@ -94,6 +98,11 @@ struct ColParams {
     int W;
     double invN;           // 1 / (H W)
     const float* inten;    // C_LOSS: target intensity, natural layout [H][W]
+    const float* tnat;     // C_BIT: target amplitude, natural layout [H][W]
+    const float* tmax_part;// C_BIT: per-work-group maxima of the target
+    int ntmax;
+    double t_dark;         // C_BIT: lit threshold on the normalised intensity
+    float* pw;             // C_POW: |U|^2 / N, strip-tiled
 };
 
 // Intensity-loss passes over a batch of same-size phases (blockIdx.y = sample).
@@ -226,6 +235,14 @@ hipError_t launch_target_tile(const PmIo* io, int H, int W, const double* part, 
 hipError_t launch_finalize(const double* part, int stride, int nwg_col, int nwg_row, double invN,
                            const PmIo* io, int first_entry, int count, hipStream_t s);
 hipError_t launch_wrap_phase(const PmIo* io, int n, hipStream_t s);
+// Per-work-group maxima of a float array (n a multiple of 4).
+hipError_t launch_max_partial(const float* x, int n, float* part, int grid, hipStream_t s);
+// Physical error of Eq. 8 (E_lit, E_dark) from the strip-tiled power
+// |U|^2 / N, the natural-layout target and the partial maxima of both;
+// `scratch` holds 2 doubles per work-group of grid n / 1024.
+hipError_t launch_physical_error(const float* pw, const double* pw_max_part, int n_pw_max, const float* target,
+                                 const float* tmax_part, int ntmax, int H, int W, double t_lit, double t_dark,
+                                 double* scratch, double* out, hipStream_t s);
 // out[b] = sum of part[b * nwg .. b * nwg + nwg) in a fixed order, b < count.
 hipError_t launch_sum_rows(const double* part, int nwg, double* out, int count, hipStream_t s);
 

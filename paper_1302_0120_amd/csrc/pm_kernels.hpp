@@ -59,6 +59,25 @@ __device__ __forceinline__ void store_shared(float2* p, float2 v) {
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Work-group maximum of one float per thread, returned to every thread.
+// Max is exact, so the order does not matter.  All threads must call.
+template <int NT>
+__device__ __forceinline__ float block_max(float v, float* redf) {
+    constexpr int WS = NT < 64 ? NT : 64;
+    constexpr int NW = (NT + 63) / 64;
+#pragma unroll
+    for (int off = WS / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, WS));
+    if constexpr (NW > 1) {
+        if ((threadIdx.x & 63) == 0) redf[threadIdx.x >> 6] = v;
+        __syncthreads();
+        v = redf[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) v = fmaxf(v, redf[w]);
+        __syncthreads();
+    }
+    return v;
+}
+
 template <int L, int PP = points_per_thread(L)>
 struct LineShape {
     static constexpr int P = PP;                    // points per thread (radix schedule)
@@ -94,7 +113,19 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
         for (int t = 0; t < P; ++t) mt[t] = a.mhat[sb + (size_t)(j + T * t) * kC + c];
     }
     float2 v[P];
-    if constexpr ((MODE & CIN_NAT) != 0) {
+    if constexpr ((MODE & C_BIT) != 0) {
+        // 1-bit pattern: lit where m^2 / max(m^2) > t_dark, both in IEEE double
+        // (a correctly rounded division, as in any double evaluation of it).
+        float mx = 0.0f;
+        for (int i = tid; i < a.ntmax; i += NT) mx = fmaxf(mx, a.tmax_part[i]);
+        mx = block_max<NT>(mx, reinterpret_cast<float*>(red));
+        const double mx2 = (double)mx * (double)mx;
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            const double m = (double)a.tnat[(size_t)(j + T * t) * a.W + s * kC + c];
+            v[t] = make_float2((m * m) / mx2 > a.t_dark ? 1.0f : 0.0f, 0.0f);
+        }
+    } else if constexpr ((MODE & CIN_NAT) != 0) {
 #pragma unroll
         for (int t = 0; t < P; ++t) v[t] = a.nat_in[(size_t)(j + T * t) * a.W + s * kC + c];
     } else {
@@ -134,6 +165,19 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
             const double tot = block_sum<NT>(acc, red);
             if (tid == 0) *part_slot = tot;
         }
+    }
+
+    if constexpr ((MODE & C_POW) != 0) {
+        // |U_unitary|^2 = |U|^2 / N (exact power-of-two scaling).
+        float mx = 0.0f;
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            const float q = (v[t].x * v[t].x + v[t].y * v[t].y) * (float)a.invN;
+            a.pw[sb + (size_t)(j + T * t) * kC + c] = q;
+            mx = fmaxf(mx, q);
+        }
+        mx = block_max<NT>(mx, reinterpret_cast<float*>(red));
+        if (tid == 0) *part_slot = (double)mx;
     }
 
     if constexpr ((MODE & C_LOSS) != 0) {

@@ -55,6 +55,8 @@ hipError_t PM_CAT(launch_col_, PM_L)(int mode, const ColParams& p, int grid, hip
         case COL_FFT_FWD: return launch(k_col<PM_L, COL_FFT_FWD>, grid, block, s, ev0, ev1, p);
         case COL_FFT_INV: return launch(k_col<PM_L, COL_FFT_INV>, grid, block, s, ev0, ev1, p);
         case COL_ITER_NE: return launch(k_col<PM_L, COL_ITER_NE>, grid, block, s, ev0, ev1, p);
+        case COL_INIT_BIT: return launch(k_col<PM_L, COL_INIT_BIT>, grid, block, s, ev0, ev1, p);
+        case COL_POW: return launch(k_col<PM_L, COL_POW>, grid, block, s, ev0, ev1, p);
         default: return hipErrorInvalidValue;
     }
 }
