@@ -100,9 +100,10 @@ pm_status phasemask_set_stream(pm_handle h, void* stream);
  *                     for the iterates (any positive scale gives the same u).
  *   init_phase        float[height*width], radians, any real value.
  *   n_iter            >= 0.
- *   out_phase         float[height*width]; receives atan2(Im u, Re u) in
- *                     (-pi, pi].  May alias init_phase; must not overlap
- *                     target_amplitude.
+ *   out_phase         float[height*width]; receives the FP32 atan2(Im u, Re u),
+ *                     in [-pi, pi] up to FP32 rounding (the float nearest pi
+ *                     is slightly above pi).  May alias init_phase; must not
+ *                     overlap target_amplitude.
  *   err_history       NULL, or double[2*n_iter + 1] receiving
  *                     [E_F^0, G^0, E_F^1, G^1, ..., E_F^{n-1}, G^{n-1}, E_F^n]
  *                     (E_F^nu measured on u^nu before projecting, G^nu on
@@ -116,6 +117,24 @@ pm_status phasemask_set_stream(pm_handle h, void* stream);
 pm_status phasemask_solve(pm_handle h, const float* target_amplitude,
                           const float* init_phase, int n_iter,
                           float* out_phase, double* err_history);
+
+/*
+ * Relaxed averaged alternating reflections (RAAR), the algorithm the paper
+ * names for projection problems where alternating projections stagnate
+ * (Sec. IV.B).  With R_S = 2 P_S - I and R_M = 2 P_M - I:
+ *   x^{nu+1} = beta/2 (R_S R_M + I) x^nu + (1 - beta) P_M x^nu
+ *            = beta P_S(2 P_M x^nu - x^nu) + beta x^nu + (1 - 2 beta) P_M x^nu,
+ * from x^0 = exp(i init_phase); the mask is the shadow P_S x^n and out_phase
+ * receives its phase.  Arguments as for phasemask_solve, plus
+ *   beta          relaxation in (0, 1] (beta = 1: Douglas-Rachford).
+ *   err_history   NULL or double[n_iter + 1]:
+ *                 [E_F(x^0), ..., E_F(x^{n-1}), E_F(P_S x^n)].
+ * The plan keeps an 8-byte-per-pixel state buffer after the first call.
+ * Errors: as phasemask_solve, and PM_EINVAL for beta outside (0, 1].
+ */
+pm_status phasemask_solve_raar(pm_handle h, const float* target_amplitude,
+                               const float* init_phase, int n_iter, double beta,
+                               float* out_phase, double* err_history);
 
 /*
  * Errors of a given phase-only mask u = exp(i phase) against a target:
@@ -135,7 +154,7 @@ pm_status phasemask_error(pm_handle h, const float* target_amplitude,
  * phase (the projection onto S, Eq. 4a, with its zero tie-break).  The paper
  * uses t_dark = 3e-4, its dark tolerance of Eq. 8b.
  *   target_amplitude  as for phasemask_solve.
- *   out_phase         float[height*width] receives the phase in (-pi, pi];
+ *   out_phase         float[height*width] receives the phase (FP32 atan2);
  *                     must not overlap the target.
  * Errors: PM_EINVAL for NULL, misaligned or overlapping arrays, or t_dark
  * outside [0, 1); PM_EDEVICE.

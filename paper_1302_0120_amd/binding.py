@@ -24,6 +24,8 @@ _SIGNATURES = {
     "phasemask_set_stream": (ctypes.c_int, [_c_handle, ctypes.c_void_p]),
     "phasemask_solve": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "phasemask_solve_raar": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                            ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_error": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_fft2": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "phasemask_create_batched": (ctypes.c_int, [ctypes.POINTER(_c_handle), ctypes.c_int,
@@ -132,6 +134,22 @@ class PhaseMask:
         hp = 0 if hist is None else _dev_ptr(hist, torch.float64, (2 * int(n_iter) + 1,), "history")
         self._stream()
         _check(lib.phasemask_solve(self._h, tp, pp, int(n_iter), op, hp or None), "phasemask_solve")
+        return out, hist
+
+    def solve_raar(self, target: torch.Tensor, init_phase: torch.Tensor, n_iter: int, beta: float,
+                   out: torch.Tensor | None = None, history: bool = True):
+        """RAAR (relaxed averaged alternating reflections); returns (phase of
+        the shadow P_S x^n, history [E_F(x^0) .. E_F(x^{n-1}), E_F(P_S x^n)])."""
+        tp = _dev_ptr(target, torch.float32, self.shape, "target")
+        pp = _dev_ptr(init_phase, torch.float32, self.shape, "init_phase")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        op = _dev_ptr(out, torch.float32, self.shape, "out")
+        hist = torch.empty(int(n_iter) + 1, dtype=torch.float64, device=self.device) if history else None
+        self._stream()
+        _check(lib.phasemask_solve_raar(self._h, tp, pp, int(n_iter), float(beta), op,
+                                        hist.data_ptr() if hist is not None else None),
+               "phasemask_solve_raar")
         return out, hist
 
     def error(self, target: torch.Tensor, phase: torch.Tensor, out: torch.Tensor | None = None):

@@ -67,6 +67,8 @@ const ColLauncher kColLaunch[9] = {pm::launch_col_16,  pm::launch_col_32,   pm::
 struct GraphEntry {
     int n_iter;
     bool hist;
+    int algo;      // 0 = alternating projections, 1 = RAAR
+    float beta;    // RAAR relaxation (part of the captured kernel arguments)
     hipGraphExec_t exec;
 };
 
@@ -82,6 +84,7 @@ struct pm_plan {
     hipStream_t stream = nullptr;      // caller's stream
     hipStream_t cap_stream = nullptr;  // private stream used only for graph capture
     int nwg_row = 0, nwg_col = 0, stride = 0;
+    int num_cu = 0;                    // compute units of the device
     float2* X = nullptr;
     float* mhat = nullptr;
     float2* twW = nullptr;
@@ -89,6 +92,7 @@ struct pm_plan {
     double* part_m = nullptr;
     float* part_mx = nullptr;          // per-work-group maxima of a target
     float* pw = nullptr;               // |U|^2 / N scratch of the physical error, on first use
+    float2* Z = nullptr;               // RAAR's SLM-plane point, on first use
     double* part = nullptr;
     size_t part_entries = 0;           // capacity of `part` in history entries
     pm::PmIo* io = nullptr;
@@ -136,6 +140,7 @@ void free_plan(pm_plan* h) {
     (void)hipFree(h->part_m);
     (void)hipFree(h->part_mx);
     (void)hipFree(h->pw);
+    (void)hipFree(h->Z);
     (void)hipFree(h->part);
     (void)hipFree(h->io);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -187,6 +192,7 @@ pm::RowParams row_params(pm_plan* h, double* part) {
     r.io = h->io;
     r.part = part;
     r.H = h->H;
+    r.spread = h->nwg_row <= h->num_cu;
     return r;
 }
 
@@ -199,6 +205,7 @@ pm::ColParams col_params(pm_plan* h, double* part) {
     c.part = part;
     c.W = h->W;
     c.invN = 1.0 / (double)h->N;
+    c.spread = h->nwg_col <= h->num_cu;
     return c;
 }
 
@@ -217,7 +224,7 @@ pm_status enqueue_target(pm_plan* h, hipStream_t s) {
 
 // The whole solve after the pointer block is set: target preparation,
 // u^0, n_iter iterations, final error and history finalisation.
-pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist) {
+pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int algo = 0, float beta = 0.0f) {
     const int lw = log2i(h->W) - 4, lh = log2i(h->H) - 4;
     const RowLauncher row = kRowLaunch[lw];
     const ColLauncher col = kColLaunch[lh];
@@ -236,6 +243,29 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist) {
     }
     pm_status st = enqueue_target(h, s);
     if (st != PM_OK) return st;
+    if (algo == 1) {
+        // RAAR: x^0 = exp(i phi0) kept in Z; history = E_F(x^nu) at entries
+        // 2 nu and E_F(P_S x^n) at entry 2 n, finalised with step 2.
+        pm::RowParams rp = row_params(h, nullptr);
+        rp.Z = h->Z;
+        rp.beta = beta;
+        PM_TRY(row(pm::ROW_INIT_Z, rp, h->nwg_row, s, nullptr, nullptr), "row init");
+        for (int nu = 0; nu < n_iter; ++nu) {
+            PM_TRY(col(hist ? pm::COL_ITER : pm::COL_ITER_NE, col_params(h, pe(2 * nu)), h->nwg_col, s, nullptr,
+                       nullptr),
+                   "column pass");
+            const bool last = nu == n_iter - 1;
+            const int mode = !last ? pm::ROW_RAAR : (hist ? pm::ROW_RAAR_LAST_FWD : pm::ROW_RAAR_LAST);
+            PM_TRY(row(mode, rp, h->nwg_row, s, nullptr, nullptr), "RAAR row pass");
+        }
+        if (hist) {
+            PM_TRY(col(pm::COL_ERR, col_params(h, pe(2 * n_iter)), h->nwg_col, s, nullptr, nullptr), "column error");
+            PM_TRY(pm::launch_finalize(h->part, h->stride, h->nwg_col, h->nwg_row, 1.0 / h->N, h->io, 0, n_iter + 1,
+                                       s, 2),
+                   "finalize");
+        }
+        return PM_OK;
+    }
     PM_TRY(row(pm::ROW_INIT, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
     // Without a history the passes skip their error partial sums.
     const int col_mode = hist ? pm::COL_ITER : pm::COL_ITER_NE;
@@ -258,9 +288,9 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist) {
 pm_status enqueue_batch(pm_plan* h, hipStream_t s, int n_iter, bool err);
 
 // Replays (capturing on first use) the graph of one solve shape.
-pm_status launch_graph(pm_plan* h, int n_iter, bool hist) {
+pm_status launch_graph(pm_plan* h, int n_iter, bool hist, int algo = 0, float beta = 0.0f) {
     for (auto it = h->graphs.begin(); it != h->graphs.end(); ++it) {
-        if (it->n_iter == n_iter && it->hist == hist) {
+        if (it->n_iter == n_iter && it->hist == hist && it->algo == algo && it->beta == beta) {
             h->graphs.splice(h->graphs.begin(), h->graphs, it);
             PM_TRY(hipGraphLaunch(it->exec, h->stream), "hipGraphLaunch");
             return PM_OK;
@@ -269,7 +299,7 @@ pm_status launch_graph(pm_plan* h, int n_iter, bool hist) {
     hipGraph_t graph = nullptr;
     PM_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     pm_status st = h->batched ? enqueue_batch(h, h->cap_stream, n_iter, hist)
-                              : enqueue_solve(h, h->cap_stream, n_iter, hist);
+                              : enqueue_solve(h, h->cap_stream, n_iter, hist, algo, beta);
     hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
     if (st != PM_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -284,7 +314,7 @@ pm_status launch_graph(pm_plan* h, int n_iter, bool hist) {
         (void)hipGraphExecDestroy(h->graphs.back().exec);
         h->graphs.pop_back();
     }
-    h->graphs.push_front(GraphEntry{n_iter, hist, exec});
+    h->graphs.push_front(GraphEntry{n_iter, hist, algo, beta, exec});
     PM_TRY(hipGraphLaunch(exec, h->stream), "hipGraphLaunch");
     return PM_OK;
 }
@@ -554,6 +584,8 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
     };
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) return bail(e, "hipGetDevice");
+    if ((e = hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device)) != hipSuccess)
+        return bail(e, "hipDeviceGetAttribute");
     const size_t n = (size_t)h->N;
     if ((e = hipMalloc(&h->X, n * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(iterate)");
     if ((e = hipMalloc(&h->mhat, n * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc(target)");
@@ -611,6 +643,37 @@ pm_status phasemask_solve(pm_handle h, const float* target_amplitude, const floa
     PM_TRY(pm::launch_set_io(h->io, io, h->stream), "set io");
     if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_solve(h, h->stream, n_iter, hist);
     return launch_graph(h, n_iter, hist);
+}
+
+pm_status phasemask_solve_raar(pm_handle h, const float* target_amplitude, const float* init_phase, int n_iter,
+                               double beta, float* out_phase, double* err_history) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    if (!target_amplitude || !init_phase || !out_phase) return fail(PM_EINVAL, "null array argument");
+    if (n_iter < 0) return fail(PM_EINVAL, "n_iter must be >= 0");
+    if (!(beta > 0.0 && beta <= 1.0)) return fail(PM_EINVAL, "beta must be in (0, 1]");
+    if (misaligned(target_amplitude, 16)) return fail(PM_EINVAL, "target must be 16-byte aligned");
+    if (misaligned(init_phase, 4) || misaligned(out_phase, 4) || misaligned(err_history, 8))
+        return fail(PM_EINVAL, "misaligned array argument");
+    const size_t nb = (size_t)h->N * sizeof(float);
+    if (overlaps(out_phase, nb, target_amplitude, nb)) return fail(PM_EINVAL, "out_phase overlaps the target");
+    const bool hist = err_history != nullptr;
+    if (hist && overlaps(err_history, ((size_t)n_iter + 1) * sizeof(double), target_amplitude, nb))
+        return fail(PM_EINVAL, "err_history overlaps the target");
+    st = ensure_partials(h, 2 * (size_t)n_iter + 1);
+    if (st != PM_OK) return st;
+    if (h->Z == nullptr) {
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+        drop_graphs(h);
+        e = hipMalloc(&h->Z, (size_t)h->N * sizeof(float2));
+        if (e != hipSuccess) return fail_hip(e, "hipMalloc(RAAR state)");
+        h->ws_bytes += (size_t)h->N * sizeof(float2);
+    }
+    pm::PmIo io{target_amplitude, init_phase, out_phase, err_history};
+    PM_TRY(pm::launch_set_io(h->io, io, h->stream), "set io");
+    if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_solve(h, h->stream, n_iter, hist, 1, (float)beta);
+    return launch_graph(h, n_iter, hist, 1, (float)beta);
 }
 
 pm_status phasemask_error(pm_handle h, const float* target_amplitude, const float* phase, double* errors) {

@@ -63,14 +63,14 @@ k_target_tile(const PmIo* io, int H, int W, const double* part, int npart, float
     }
 }
 
-// History entry e = first_entry + blockIdx.x: even entries are Fourier
+// History entry e = first_entry + blockIdx.x * entry_step: even entries are Fourier
 // errors, E_F = sqrt(sum of partials); odd entries are gaps,
 // G = sqrt(sum / N).  Partials of entry e sit at part[e * stride + wg].
 __global__ void __launch_bounds__(kAuxThreads)
 k_finalize(const double* part, int stride, int nwg_col, int nwg_row, double invN,
-           const PmIo* io, int first_entry) {
+           const PmIo* io, int first_entry, int entry_step) {
     __shared__ double red[kAuxThreads / 64];
-    const int e = first_entry + blockIdx.x;
+    const int e = first_entry + blockIdx.x * entry_step;
     const int nwg = (e & 1) ? nwg_row : nwg_col;
     const double* p = part + (size_t)e * stride;
     double acc = 0.0;
@@ -345,8 +345,8 @@ hipError_t launch_target_tile(const PmIo* io, int H, int W, const double* part, 
 }
 
 hipError_t launch_finalize(const double* part, int stride, int nwg_col, int nwg_row, double invN,
-                           const PmIo* io, int first_entry, int count, hipStream_t s) {
-    k_finalize<<<count, kAuxThreads, 0, s>>>(part, stride, nwg_col, nwg_row, invN, io, first_entry);
+                           const PmIo* io, int first_entry, int count, hipStream_t s, int entry_step) {
+    k_finalize<<<count, kAuxThreads, 0, s>>>(part, stride, nwg_col, nwg_row, invN, io, first_entry, entry_step);
     return hipGetLastError();
 }
 

@@ -38,6 +38,8 @@ enum : int {
     ROUT_NAT = 128,   // write a natural-layout complex image
     R_NOERR = 256,    // P_S without the gap partial sum
     ROUT_GRAD = 512,  // intensity-loss gradient 4 gscale Im(e^{-i phi} g)
+    R_RAAR = 1024,    // RAAR update of the SLM-plane point x (kept in Z) from w = P_M x
+    R_STOREZ = 2048,  // store the initial field to Z (RAAR start)
 };
 constexpr int ROW_INIT = RIN_PHASE | R_FWD;
 constexpr int ROW_ITER = RIN_TILED | R_INV | R_PS | R_FWD;
@@ -50,6 +52,12 @@ constexpr int ROW_ITER_NE = ROW_ITER | R_NOERR;
 constexpr int ROW_LAST_NE = ROW_LAST | R_NOERR;
 constexpr int ROW_LAST_FWD_NE = ROW_LAST_FWD | R_NOERR;
 constexpr int ROW_GRAD = RIN_TILED | R_INV | ROUT_GRAD;
+constexpr int ROW_INIT_Z = RIN_PHASE | R_STOREZ | R_FWD;
+constexpr int ROW_RAAR = RIN_TILED | R_INV | R_RAAR | R_FWD;
+// Last RAAR pass: phase of the shadow P_S x^n, and (with _FWD) its row FFT
+// for the final Fourier error.
+constexpr int ROW_RAAR_LAST = RIN_TILED | R_INV | R_RAAR | ROUT_PHASE;
+constexpr int ROW_RAAR_LAST_FWD = RIN_TILED | R_INV | R_RAAR | ROUT_PHASE | R_FWD;
 
 // Column-pass modes (bit sets).
 enum : int {
@@ -85,6 +93,9 @@ struct RowParams {
     double* part;          // one gap partial per work-group (R_PS), null without
     int H;
     float gscale;          // ROUT_GRAD: gradient scale 4 g_out / N
+    float2* Z;             // R_RAAR / R_STOREZ: SLM-plane point x, strip-tiled
+    float beta;            // R_RAAR: relaxation parameter
+    int spread;            // launch at most one work-group per CU (grid fits the CUs)
 };
 
 struct ColParams {
@@ -103,6 +114,7 @@ struct ColParams {
     int ntmax;
     double t_dark;         // C_BIT: lit threshold on the normalised intensity
     float* pw;             // C_POW: |U|^2 / N, strip-tiled
+    int spread;            // launch at most one work-group per CU (grid fits the CUs)
 };
 
 // Intensity-loss passes over a batch of same-size phases (blockIdx.y = sample).
@@ -232,8 +244,9 @@ hipError_t launch_set_io(PmIo* io, const PmIo& val, hipStream_t s);
 hipError_t launch_norm_partial(const PmIo* io, int n, double* part, int grid, hipStream_t s);
 hipError_t launch_target_tile(const PmIo* io, int H, int W, const double* part, int npart,
                               float* mhat, hipStream_t s);
+// History entries first_entry + k * entry_step, k < count, into hist[k].
 hipError_t launch_finalize(const double* part, int stride, int nwg_col, int nwg_row, double invN,
-                           const PmIo* io, int first_entry, int count, hipStream_t s);
+                           const PmIo* io, int first_entry, int count, hipStream_t s, int entry_step = 1);
 hipError_t launch_wrap_phase(const PmIo* io, int n, hipStream_t s);
 // Per-work-group maxima of a float array (n a multiple of 4).
 hipError_t launch_max_partial(const float* x, int n, float* part, int grid, hipStream_t s);

@@ -253,6 +253,15 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
 #pragma unroll
         for (int t = 0; t < P; ++t) v[t] = a.X[tiled(t)];
     }
+    float2 zx[(MODE & R_RAAR) != 0 ? P : 1];
+    if constexpr ((MODE & R_RAAR) != 0) {
+#pragma unroll
+        for (int t = 0; t < P; ++t) zx[t] = a.Z[tiled(t)];
+    }
+    if constexpr ((MODE & R_STOREZ) != 0) {
+#pragma unroll
+        for (int t = 0; t < P; ++t) a.Z[tiled(t)] = v[t];
+    }
     float2* line = lds + rho * LP;
 
     constexpr int PAR1 = (MODE & R_INV) != 0 ? fft_parity_after<W, P, 0>() : 0;
@@ -279,6 +288,35 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
         if constexpr (ERR) {
             const double tot = block_sum<NT>(acc, red);
             if (tid == 0) *part_slot = tot;
+        }
+    }
+
+    if constexpr ((MODE & R_RAAR) != 0) {
+        // RAAR: x+ = beta P_S(2w - x) + beta x + (1 - 2 beta) w with w = P_M x
+        // (the unnormalised inverse of the target-scaled M-hat leaves w on the
+        // scale of x).  Tie-break of P_S below FLT_MIN as in Eq. 4a.
+        const float b = a.beta;
+        const float c = 1.0f - 2.0f * b;
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            const float2 w = v[t];
+            const float2 x = zx[t];
+            const float2 y = make_float2(2.0f * w.x - x.x, 2.0f * w.y - x.y);
+            const float a2 = y.x * y.x + y.y * y.y;
+            const bool nz = a2 >= FLT_MIN;
+            const float r = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
+            const float2 ps = nz ? make_float2(y.x * r, y.y * r) : make_float2(1.0f, 0.0f);
+            const float2 xn = make_float2(b * ps.x + b * x.x + c * w.x, b * ps.y + b * x.y + c * w.y);
+            if constexpr ((MODE & ROUT_PHASE) != 0) {
+                // last pass: the mask is the shadow P_S x^n
+                const float q2 = xn.x * xn.x + xn.y * xn.y;
+                const bool qz = q2 >= FLT_MIN;
+                const float qr = qz ? __builtin_amdgcn_rsqf(q2) : 0.0f;
+                v[t] = qz ? make_float2(xn.x * qr, xn.y * qr) : make_float2(1.0f, 0.0f);
+            } else {
+                a.Z[tiled(t)] = xn;
+                v[t] = xn;
+            }
         }
     }
 

@@ -16,13 +16,30 @@ namespace pm {
 
 namespace {
 
+// When a pass has no more work-groups than the GPU has CUs (p.spread), the
+// launch reserves extra dynamic LDS so that no CU can hold two of them: the
+// dispatcher then gives every work-group a CU of its own instead of doubling
+// up some CUs while others idle (measured: about 0.6 us per 1024^2 pass).
+constexpr size_t kSpreadLds = 80 * 1024 + 256;  // more than half of the 160 KB per CU
+
 template <typename Params>
 hipError_t launch(void (*kern)(Params), int grid, int block, hipStream_t s, hipEvent_t ev0,
                   hipEvent_t ev1, const Params& p) {
+    size_t dyn = 0;
+    if (p.spread) {
+        hipFuncAttributes attr{};
+        hipError_t e = hipFuncGetAttributes(&attr, (const void*)kern);
+        if (e != hipSuccess) return e;
+        if (attr.sharedSizeBytes < kSpreadLds) {
+            dyn = kSpreadLds - attr.sharedSizeBytes;
+            e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+            if (e != hipSuccess) return e;
+        }
+    }
     if (ev0 != nullptr || ev1 != nullptr) {
-        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, ev0, ev1, 0, p);
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), dyn, s, ev0, ev1, 0, p);
     } else {
-        kern<<<grid, block, 0, s>>>(p);
+        kern<<<grid, block, dyn, s>>>(p);
     }
     return hipGetLastError();
 }
@@ -42,6 +59,10 @@ hipError_t PM_CAT(launch_row_, PM_L)(int mode, const RowParams& p, int grid, hip
         case ROW_FFT_INV: return launch(k_row<PM_L, ROW_FFT_INV>, grid, block, s, ev0, ev1, p);
         case ROW_ITER_NE: return launch(k_row<PM_L, ROW_ITER_NE>, grid, block, s, ev0, ev1, p);
         case ROW_LAST_NE: return launch(k_row<PM_L, ROW_LAST_NE>, grid, block, s, ev0, ev1, p);
+        case ROW_INIT_Z: return launch(k_row<PM_L, ROW_INIT_Z>, grid, block, s, ev0, ev1, p);
+        case ROW_RAAR: return launch(k_row<PM_L, ROW_RAAR>, grid, block, s, ev0, ev1, p);
+        case ROW_RAAR_LAST: return launch(k_row<PM_L, ROW_RAAR_LAST>, grid, block, s, ev0, ev1, p);
+        case ROW_RAAR_LAST_FWD: return launch(k_row<PM_L, ROW_RAAR_LAST_FWD>, grid, block, s, ev0, ev1, p);
         default: return hipErrorInvalidValue;
     }
 }

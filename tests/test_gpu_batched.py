@@ -89,7 +89,7 @@ def test_batched_zero_iterations_and_no_error(pmb):
     outs, err = bp.solve(targets, phases, 0)
     for i, (m, p) in enumerate(probs):
         o = outs[i].cpu().numpy().astype(np.float64)
-        assert np.all(np.abs(o) <= math.pi)
+        assert np.all(np.abs(o) <= np.float32(math.pi))  # FP32 pi rounds up
         assert np.max(np.abs(np.exp(1j * o) - np.exp(1j * (3.0 * p.astype(np.float64))))) <= 2e-6
         ef = gs.mask_errors(m, (p * np.float32(3.0)))[0]
         assert abs(err[i].item() - ef) / ef <= 1e-5

@@ -56,7 +56,7 @@ def test_initial_phase_vs_oracle(pmb, n):
     wref = np.abs(gs.F_inv((it / it.max() > 3e-4).astype(np.float64)))
     err = np.linalg.norm((np.exp(1j * phi) - np.exp(1j * ref)) * wref) / np.linalg.norm(wref)
     assert err <= 1e-5, err
-    assert np.all(np.abs(phi) <= math.pi)
+    assert np.all(np.abs(phi) <= np.float32(math.pi))  # FP32 pi rounds up
 
 
 @pytest.mark.parametrize("n,iters", [(64, 0), (256, 0), (256, 20), (1024, 10)])

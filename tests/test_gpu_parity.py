@@ -206,7 +206,8 @@ def test_zero_iterations(pmb):
     out, hist = plan.solve(_dev(m), _dev(phi0), 0)
     o = out.cpu().numpy()
     assert hist.shape == (1,)
-    assert np.all(o <= math.pi) and np.all(o >= -math.pi)
+    pi32 = np.float32(math.pi)  # FP32 pi rounds up
+    assert np.all(o <= pi32) and np.all(o >= -pi32)
     assert np.max(np.abs(np.exp(1j * o.astype(np.float64)) - _field(phi0))) <= 1e-6
     ef = gs.mask_errors(m, phi0)[0]
     assert abs(hist.item() - ef) / ef <= 1e-5
