@@ -103,6 +103,89 @@ def bench_batched(torch, binding, synth, steps):
     }
 
 
+def bench_paper_slm(torch, binding, synth, steps=20):
+    """The paper's own timing case as context: an 800 x 600 SLM (600 rows of
+    800 pixels), 25 iterations, spot target; ms per solve with the target
+    resident, and with the target uploaded from pinned host memory first
+    (the paper's figure includes its upload).  Also 5 iterations, the
+    paper's usable-mask count."""
+    spec = synth.SPOTS_800x600
+    h, w, n_iter = spec.height, spec.width, spec.n_iter
+    m, phi0 = synth.spot_problem(spec)
+    dev = torch.device("cuda", 0)
+    host_m = torch.from_numpy(m).pin_memory()
+    md = host_m.to(dev)
+    pd = torch.from_numpy(phi0).to(dev)
+    plan = binding.PhaseMask(h, w, device=dev)
+    out = torch.empty((h, w), dtype=torch.float32, device=dev)
+    res = {"workload": "gs_spots_800x600_25it", "height": h, "width": w, "n_iter": n_iter,
+           "paper_ms_incl_upload": 45.0, "paper_gpu": "Tesla C2070 (FP32)"}
+
+    def timed(k, upload):
+        hist = torch.empty(2 * k + 1, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            plan.solve(md, pd, k, out=out, history=hist)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            if upload:
+                md.copy_(host_m, non_blocking=True)
+            plan.solve(md, pd, k, out=out, history=hist)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, float(hist[-1].item())
+
+    res["ms_per_mask"], res["final_fourier_error"] = timed(n_iter, False)
+    res["ms_per_mask_incl_upload"], _ = timed(n_iter, True)
+    res["ms_per_mask_5it_incl_upload"], _ = timed(5, True)
+    res["speedup_vs_paper"] = res["paper_ms_incl_upload"] / res["ms_per_mask_incl_upload"]
+    plan.close()
+    return res
+
+
+def bench_next_rows(torch, binding, synth, m, phi0, plan_steps=10, reps=100):
+    """The other device entry points on the same 1024 x 1024 workload: RAAR
+    (100 iterations), the paper's initial mask, the physical error of Eq. 8,
+    and a GS solve under a Gaussian illumination p (with the pass timings of
+    its row pass, which also reads p).  Algorithmic bytes per pixel: RAAR
+    iteration 20 (column) + 32 (row: iterate and the point x in and out);
+    illuminated GS iteration 20 + 20 (row also reads p)."""
+    h, w = m.shape
+    npx = h * w
+    n_iter = 100
+    dev = torch.device("cuda", 0)
+    md = torch.from_numpy(m).to(dev)
+    pd = torch.from_numpy(phi0).to(dev)
+    plan = binding.PhaseMask(h, w, device=dev)
+    out = torch.empty((h, w), dtype=torch.float32, device=dev)
+
+    def per_call(fn, k=plan_steps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / k
+
+    res = {"workload": "gs_spots_1024x1024", "n_iter": n_iter}
+    ms = per_call(lambda: plan.solve_raar(md, pd, n_iter, 0.9, out=out))
+    res["raar"] = {"beta": 0.9, "ms_per_mask": ms,
+                   "algorithmic_gbs": (20 + 32) * npx * n_iter / (ms * 1e-3) / 1e9}
+    res["initial_phase_ms"] = per_call(lambda: plan.initial_phase(md, out=out))
+    res["physical_error_ms"] = per_call(lambda: plan.physical_error(md, pd))
+    p = torch.from_numpy(synth.gaussian_illumination(h, w, waist=0.4)).to(dev)
+    plan.set_illumination(p)
+    ms = per_call(lambda: plan.solve(md, pd, n_iter, out=out))
+    col_ms, row_ms = plan.time_passes(md, pd, reps=reps)
+    res["illumination"] = {"profile": "gaussian waist 0.4", "ms_per_mask": ms,
+                           "passes_us": {"column": col_ms * 1e3, "row": row_ms * 1e3},
+                           "row_gbs": 20 * npx / (row_ms * 1e-3) / 1e9,
+                           "algorithmic_gbs": 40 * npx * n_iter / (ms * 1e-3) / 1e9}
+    plan.close()
+    return res
+
+
 def bench_adjoint(torch, binding, synth, lr, steps=200):
     """16 x 512^2 phases, 50-spot intensity targets I = m^2 scaled to sum N:
     200 Adam steps on the intensity loss (forward and adjoint kernels) versus
@@ -188,6 +271,10 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the Adam-versus-GS measurement")
+    ap.add_argument("--no-paper-slm", action="store_true",
+                    help="skip the 800x600 / 25-iteration context measurement")
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip RAAR / initial mask / physical error / illumination timings")
     ap.add_argument("--adam-lr", type=float, default=0.1,
                     help="chosen from {0.01, 0.03, 0.1} by the final Fourier error of the workload")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -274,6 +361,10 @@ def main():
         line["batched"] = bench_batched(torch, binding, synth, args.batched_steps)
     if not args.no_adjoint:
         line["adjoint"] = bench_adjoint(torch, binding, synth, args.adam_lr)
+    if not args.no_paper_slm:
+        line["paper_slm"] = bench_paper_slm(torch, binding, synth)
+    if not args.no_next_rows:
+        line["next_rows"] = bench_next_rows(torch, binding, synth, m, phi0)
     if not args.no_cpu_baseline:
         rate, cdt = cpu_baseline(m, phi0, args.cpu_iters)
         line["cpu_baseline"] = {

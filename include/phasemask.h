@@ -21,8 +21,11 @@
  *    forward kernel exp(-2 pi i (k_y y / height + k_x x / width)).
  *  * Complex arrays are interleaved pairs of float (re, im), 8 bytes per
  *    element.
- *  * Sizes: height and width must each be a power of two in [16, 4096];
- *    anything else returns PM_EUNSUPPORTED.
+ *  * Sizes: height and width must each be a power of two in [16, 4096], or
+ *    600, 800, 1080 or 1920 (the mixed-radix transforms of 800 x 600 and
+ *    1920 x 1080 SLM panels, in either orientation, also paired with any
+ *    supported length); anything else returns PM_EUNSUPPORTED.  The batched entry points take powers of two
+ *    only (see phasemask_create_batched).
  *  * All array arguments are DEVICE pointers owned by the caller, on the
  *    device that was current when the handle was created, unless a comment
  *    says otherwise.  The library never frees them.  Alignment: the target
@@ -59,7 +62,7 @@ typedef struct pm_plan* pm_handle;
 typedef enum {
     PM_OK = 0,
     PM_EINVAL = -1,        /* bad argument (null pointer, negative count, ...) */
-    PM_EUNSUPPORTED = -2,  /* size not a power of two in [16, 4096]           */
+    PM_EUNSUPPORTED = -2,  /* size outside {2^k: 16..4096} + {600, 800, 1080, 1920} */
     PM_ENOMEM = -3,        /* device or host allocation failed                */
     PM_EDEVICE = -4,       /* a HIP call or kernel launch failed              */
     PM_ESTATE = -5         /* handle destroyed or in an unusable state        */
@@ -90,6 +93,32 @@ pm_status phasemask_destroy(pm_handle h);
 
 /* Use `stream` (a hipStream_t, NULL = null stream) for subsequent calls. */
 pm_status phasemask_set_stream(pm_handle h, void* stream);
+
+/*
+ * Illumination amplitude p of Eq. 1: the set S becomes the fields whose
+ * pixel moduli equal p (not 1), so u^0 = p exp(i init_phase), P_S of Eq. 4a
+ * gives each pixel modulus p (a zero pixel takes p exp(i 0)), and the errors
+ * are relative to ||p|| with the target energy-matched to ||p||:
+ *     E_F = || |F u| - m ||p|| / ||m|| || / ||p||,
+ *     G   = || |P_M u| - p || / ||p||.
+ * Applies to phasemask_solve, phasemask_solve_raar, phasemask_error,
+ * phasemask_physical_error (whose field is u = p exp(i phase)) and
+ * phasemask_time_passes until changed; the output phase is that of the
+ * projected field before the factor p (also defined where p = 0).  Not
+ * applied by phasemask_initial_phase, phasemask_fft2 or the intensity-loss
+ * entry points.
+ *
+ *   illumination  float[height*width] DEVICE array, natural layout, p >= 0
+ *                 and not all zero (not checked), 16-byte aligned; or NULL
+ *                 to return to p = 1.  Copied on the handle's stream (with
+ *                 ||p||^2 summed in FP64), so the caller may reuse it once
+ *                 that stream has passed this call.
+ * The first call allocates 4 bytes per pixel.  Switching between p and
+ * p = 1 synchronises the stream and drops the handle's captured graphs.
+ * Errors: PM_EINVAL (misaligned), PM_ESTATE (batched handle), PM_ENOMEM,
+ * PM_EDEVICE.
+ */
+pm_status phasemask_set_illumination(pm_handle h, const float* illumination);
 
 /*
  * Run n_iter iterations of Eq. 6 starting from u^0 = exp(i init_phase) and

@@ -22,6 +22,7 @@ _SIGNATURES = {
                                         ctypes.c_uint, ctypes.c_void_p]),
     "phasemask_destroy": (ctypes.c_int, [_c_handle]),
     "phasemask_set_stream": (ctypes.c_int, [_c_handle, ctypes.c_void_p]),
+    "phasemask_set_illumination": (ctypes.c_int, [_c_handle, ctypes.c_void_p]),
     "phasemask_solve": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                        ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_solve_raar": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
@@ -117,6 +118,14 @@ class PhaseMask:
             raise PhaseMaskError(-5, "use after close")
         _check(lib.phasemask_set_stream(self._h, torch.cuda.current_stream(self.device).cuda_stream),
                "phasemask_set_stream")
+
+    def set_illumination(self, p: torch.Tensor | None):
+        """Illumination amplitude p of Eq. 1 for the later solves and error
+        evaluations (float32 [height, width], p >= 0), or None for p = 1."""
+        pp = None if p is None else _dev_ptr(p, torch.float32, self.shape, "illumination")
+        self._stream()
+        _check(lib.phasemask_set_illumination(self._h, pp), "phasemask_set_illumination")
+        self._illum = p  # the copy is stream-ordered; keep the source alive meanwhile
 
     def solve(self, target: torch.Tensor, init_phase: torch.Tensor, n_iter: int,
               out: torch.Tensor | None = None, history: bool | torch.Tensor = True):

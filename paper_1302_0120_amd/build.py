@@ -2,8 +2,8 @@
 
     python -m paper_1302_0120_amd.build          (or build() from Python)
 
-The row/column pass source is compiled once per transform length (16 ..
-4096) in parallel; objects go to ``_build/`` at the repository root and the
+The row/column pass source is compiled once per transform length (powers
+of two 16 .. 4096, and 600, 800, 1080, 1920) in parallel; objects go to ``_build/`` at the repository root and the
 shared library next to this file.
 """
 from __future__ import annotations
@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libphasemask.so")
-LENGTHS = (16, 32, 64, 128, 256, 512, 1024, 2048, 4096)
+LENGTHS = (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 600, 800, 1080, 1920)
 ARCH = "gfx950"
 BATCH_SCHEDULES = 2  # = kBatchSchedules in csrc/pm_common.h
 

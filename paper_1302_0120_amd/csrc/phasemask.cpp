@@ -44,25 +44,45 @@ int log2i(int n) {
     return l;
 }
 
+// Slot of a supported one-mask transform length in the launcher tables:
+// log2(L) - 4 for the powers of two 16 .. 4096, then 600, 800, 1080 and
+// 1920 (the mixed-radix plans); -1 when unsupported.
+int len_slot(int n) {
+    if (pow2_in_range(n)) return log2i(n) - 4;
+    if (n == 600) return 9;
+    if (n == 800) return 10;
+    if (n == 1080) return 11;
+    if (n == 1920) return 12;
+    return -1;
+}
+
 using AdjRowLauncher = hipError_t (*)(int, const pm::AdjParams&, int, hipStream_t);
 using AdjColLauncher = hipError_t (*)(const pm::AdjParams&, int, hipStream_t);
-const AdjRowLauncher kAdjRow[9] = {pm::launch_adj_row_16,  pm::launch_adj_row_32,   pm::launch_adj_row_64,
-                                   pm::launch_adj_row_128, pm::launch_adj_row_256,  pm::launch_adj_row_512,
-                                   pm::launch_adj_row_1024, pm::launch_adj_row_2048, pm::launch_adj_row_4096};
-const AdjColLauncher kAdjCol[9] = {pm::launch_adj_col_16,  pm::launch_adj_col_32,   pm::launch_adj_col_64,
-                                   pm::launch_adj_col_128, pm::launch_adj_col_256,  pm::launch_adj_col_512,
-                                   pm::launch_adj_col_1024, pm::launch_adj_col_2048, pm::launch_adj_col_4096};
+const AdjRowLauncher kAdjRow[13] = {pm::launch_adj_row_16,   pm::launch_adj_row_32,   pm::launch_adj_row_64,
+                                    pm::launch_adj_row_128,  pm::launch_adj_row_256,  pm::launch_adj_row_512,
+                                    pm::launch_adj_row_1024, pm::launch_adj_row_2048, pm::launch_adj_row_4096,
+                                    pm::launch_adj_row_600,  pm::launch_adj_row_800,
+    pm::launch_adj_row_1080, pm::launch_adj_row_1920};
+const AdjColLauncher kAdjCol[13] = {pm::launch_adj_col_16,   pm::launch_adj_col_32,   pm::launch_adj_col_64,
+                                    pm::launch_adj_col_128,  pm::launch_adj_col_256,  pm::launch_adj_col_512,
+                                    pm::launch_adj_col_1024, pm::launch_adj_col_2048, pm::launch_adj_col_4096,
+                                    pm::launch_adj_col_600,  pm::launch_adj_col_800,
+    pm::launch_adj_col_1080, pm::launch_adj_col_1920};
 
 using RowLauncher = hipError_t (*)(int, const pm::RowParams&, int, hipStream_t, hipEvent_t, hipEvent_t);
 using ColLauncher = hipError_t (*)(int, const pm::ColParams&, int, hipStream_t, hipEvent_t, hipEvent_t);
 
-// Indexed by log2(L) - 4, L = 16 .. 4096.
-const RowLauncher kRowLaunch[9] = {pm::launch_row_16,  pm::launch_row_32,   pm::launch_row_64,
-                                   pm::launch_row_128, pm::launch_row_256,  pm::launch_row_512,
-                                   pm::launch_row_1024, pm::launch_row_2048, pm::launch_row_4096};
-const ColLauncher kColLaunch[9] = {pm::launch_col_16,  pm::launch_col_32,   pm::launch_col_64,
-                                   pm::launch_col_128, pm::launch_col_256,  pm::launch_col_512,
-                                   pm::launch_col_1024, pm::launch_col_2048, pm::launch_col_4096};
+// Indexed by len_slot(L).
+const RowLauncher kRowLaunch[13] = {pm::launch_row_16,   pm::launch_row_32,   pm::launch_row_64,
+                                    pm::launch_row_128,  pm::launch_row_256,  pm::launch_row_512,
+                                    pm::launch_row_1024, pm::launch_row_2048, pm::launch_row_4096,
+                                    pm::launch_row_600,  pm::launch_row_800,
+    pm::launch_row_1080, pm::launch_row_1920};
+const ColLauncher kColLaunch[13] = {pm::launch_col_16,   pm::launch_col_32,   pm::launch_col_64,
+                                    pm::launch_col_128,  pm::launch_col_256,  pm::launch_col_512,
+                                    pm::launch_col_1024, pm::launch_col_2048, pm::launch_col_4096,
+                                    pm::launch_col_600,  pm::launch_col_800,
+    pm::launch_col_1080, pm::launch_col_1920};
 
 struct GraphEntry {
     int n_iter;
@@ -93,6 +113,9 @@ struct pm_plan {
     float* part_mx = nullptr;          // per-work-group maxima of a target
     float* pw = nullptr;               // |U|^2 / N scratch of the physical error, on first use
     float2* Z = nullptr;               // RAAR's SLM-plane point, on first use
+    float* illum = nullptr;            // illumination amplitude p, strip-tiled, on first use
+    double* pn2 = nullptr;             // ||p||^2 on the device
+    bool illum_on = false;             // solves use p (else p = 1)
     double* part = nullptr;
     size_t part_entries = 0;           // capacity of `part` in history entries
     pm::PmIo* io = nullptr;
@@ -141,6 +164,8 @@ void free_plan(pm_plan* h) {
     (void)hipFree(h->part_mx);
     (void)hipFree(h->pw);
     (void)hipFree(h->Z);
+    (void)hipFree(h->illum);
+    (void)hipFree(h->pn2);
     (void)hipFree(h->part);
     (void)hipFree(h->io);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -192,9 +217,16 @@ pm::RowParams row_params(pm_plan* h, double* part) {
     r.io = h->io;
     r.part = part;
     r.H = h->H;
+    r.illum = h->illum_on ? h->illum : nullptr;
     r.spread = h->nwg_row <= h->num_cu;
     return r;
 }
+
+// A solve-path row mode, with the illumination variant when one is set.
+int rmode(const pm_plan* h, int mode) { return h->illum_on ? (mode | pm::R_ILLUM) : mode; }
+
+// ||p||^2 on the device for the error scales, or null for p = 1.
+const double* pnorm2(const pm_plan* h) { return h->illum_on ? h->pn2 : nullptr; }
 
 pm::ColParams col_params(pm_plan* h, double* part) {
     pm::ColParams c{};
@@ -218,14 +250,14 @@ pm::ColParams col_params(pm_plan* h, double* part) {
 // Target normalisation + tiling (the rescaled m used by every column pass).
 pm_status enqueue_target(pm_plan* h, hipStream_t s) {
     PM_TRY(pm::launch_norm_partial(h->io, h->N, h->part_m, kNormGrid, s), "target norm");
-    PM_TRY(pm::launch_target_tile(h->io, h->H, h->W, h->part_m, kNormGrid, h->mhat, s), "target tile");
+    PM_TRY(pm::launch_target_tile(h->io, h->H, h->W, h->part_m, kNormGrid, h->mhat, s, pnorm2(h)), "target tile");
     return PM_OK;
 }
 
 // The whole solve after the pointer block is set: target preparation,
 // u^0, n_iter iterations, final error and history finalisation.
 pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int algo = 0, float beta = 0.0f) {
-    const int lw = log2i(h->W) - 4, lh = log2i(h->H) - 4;
+    const int lw = len_slot(h->W), lh = len_slot(h->H);
     const RowLauncher row = kRowLaunch[lw];
     const ColLauncher col = kColLaunch[lh];
     auto pe = [&](int e) { return h->part + (size_t)e * h->stride; };
@@ -235,9 +267,9 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int al
         if (!hist) return PM_OK;
         pm_status st = enqueue_target(h, s);
         if (st != PM_OK) return st;
-        PM_TRY(row(pm::ROW_INIT, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+        PM_TRY(row(rmode(h, pm::ROW_INIT), row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
         PM_TRY(col(pm::COL_ERR, col_params(h, pe(0)), h->nwg_col, s, nullptr, nullptr), "column error");
-        PM_TRY(pm::launch_finalize(h->part, h->stride, h->nwg_col, h->nwg_row, 1.0 / h->N, h->io, 0, 1, s),
+        PM_TRY(pm::launch_finalize(h->part, h->stride, h->nwg_col, h->nwg_row, 1.0 / h->N, h->io, 0, 1, s, 1, pnorm2(h)),
                "finalize");
         return PM_OK;
     }
@@ -249,24 +281,24 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int al
         pm::RowParams rp = row_params(h, nullptr);
         rp.Z = h->Z;
         rp.beta = beta;
-        PM_TRY(row(pm::ROW_INIT_Z, rp, h->nwg_row, s, nullptr, nullptr), "row init");
+        PM_TRY(row(rmode(h, pm::ROW_INIT_Z), rp, h->nwg_row, s, nullptr, nullptr), "row init");
         for (int nu = 0; nu < n_iter; ++nu) {
             PM_TRY(col(hist ? pm::COL_ITER : pm::COL_ITER_NE, col_params(h, pe(2 * nu)), h->nwg_col, s, nullptr,
                        nullptr),
                    "column pass");
             const bool last = nu == n_iter - 1;
             const int mode = !last ? pm::ROW_RAAR : (hist ? pm::ROW_RAAR_LAST_FWD : pm::ROW_RAAR_LAST);
-            PM_TRY(row(mode, rp, h->nwg_row, s, nullptr, nullptr), "RAAR row pass");
+            PM_TRY(row(rmode(h, mode), rp, h->nwg_row, s, nullptr, nullptr), "RAAR row pass");
         }
         if (hist) {
             PM_TRY(col(pm::COL_ERR, col_params(h, pe(2 * n_iter)), h->nwg_col, s, nullptr, nullptr), "column error");
             PM_TRY(pm::launch_finalize(h->part, h->stride, h->nwg_col, h->nwg_row, 1.0 / h->N, h->io, 0, n_iter + 1,
-                                       s, 2),
+                                       s, 2, pnorm2(h)),
                    "finalize");
         }
         return PM_OK;
     }
-    PM_TRY(row(pm::ROW_INIT, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+    PM_TRY(row(rmode(h, pm::ROW_INIT), row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
     // Without a history the passes skip their error partial sums.
     const int col_mode = hist ? pm::COL_ITER : pm::COL_ITER_NE;
     const int row_mode = hist ? pm::ROW_ITER : pm::ROW_ITER_NE;
@@ -274,12 +306,12 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int al
         PM_TRY(col(col_mode, col_params(h, pe(2 * nu)), h->nwg_col, s, nullptr, nullptr), "column pass");
         const bool last = nu == n_iter - 1;
         const int mode = !last ? row_mode : (hist ? pm::ROW_LAST_FWD : pm::ROW_LAST_NE);
-        PM_TRY(row(mode, row_params(h, pe(2 * nu + 1)), h->nwg_row, s, nullptr, nullptr), "row pass");
+        PM_TRY(row(rmode(h, mode), row_params(h, pe(2 * nu + 1)), h->nwg_row, s, nullptr, nullptr), "row pass");
     }
     if (hist) {
         PM_TRY(col(pm::COL_ERR, col_params(h, pe(2 * n_iter)), h->nwg_col, s, nullptr, nullptr), "column error");
         PM_TRY(pm::launch_finalize(h->part, h->stride, h->nwg_col, h->nwg_row, 1.0 / h->N, h->io, 0,
-                                   2 * n_iter + 1, s),
+                                   2 * n_iter + 1, s, 1, pnorm2(h)),
                "finalize");
     }
     return PM_OK;
@@ -562,8 +594,9 @@ const char* phasemask_last_error(void) { return g_last_error.c_str(); }
 pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags, void* stream) {
     if (out == nullptr) return fail(PM_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!pow2_in_range(height) || !pow2_in_range(width))
-        return fail(PM_EUNSUPPORTED, "height and width must be powers of two in [16, 4096]");
+    if (len_slot(height) < 0 || len_slot(width) < 0)
+        return fail(PM_EUNSUPPORTED,
+                    "height and width must each be a power of two in [16, 4096], 600, 800, 1080 or 1920");
     if ((flags & ~PM_FLAG_NO_GRAPH) != 0) return fail(PM_EINVAL, "unknown flag bits");
     pm_plan* h = new (std::nothrow) pm_plan;
     if (h == nullptr) return fail(PM_ENOMEM, "host allocation failed");
@@ -618,6 +651,39 @@ pm_status phasemask_set_stream(pm_handle h, void* stream) {
     pm_status st = check_handle(h, h != nullptr && h->batched);
     if (st != PM_OK) return st;
     h->stream = (hipStream_t)stream;
+    return PM_OK;
+}
+
+pm_status phasemask_set_illumination(pm_handle h, const float* illumination) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    if (illumination != nullptr && misaligned(illumination, 16))
+        return fail(PM_EINVAL, "illumination must be 16-byte aligned");
+    const bool on = illumination != nullptr;
+    if (on != h->illum_on) {
+        // Captured graphs hold the kernels of the other case.
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+        drop_graphs(h);
+    }
+    if (!on) {
+        h->illum_on = false;
+        return PM_OK;
+    }
+    if (h->illum == nullptr) {
+        hipError_t e = hipMalloc(&h->illum, (size_t)h->N * sizeof(float));
+        if (e != hipSuccess) return fail_hip(e, "hipMalloc(illumination)");
+        e = hipMalloc(&h->pn2, sizeof(double));
+        if (e != hipSuccess) {
+            (void)hipFree(h->illum);
+            h->illum = nullptr;
+            return fail_hip(e, "hipMalloc(illumination norm)");
+        }
+        h->ws_bytes += (size_t)h->N * sizeof(float) + sizeof(double);
+    }
+    PM_TRY(pm::launch_illum_prep(illumination, h->H, h->W, h->part_m, kNormGrid, h->illum, h->pn2, h->stream),
+           "illumination set-up");
+    h->illum_on = true;
     return PM_OK;
 }
 
@@ -689,12 +755,14 @@ pm_status phasemask_error(pm_handle h, const float* target_amplitude, const floa
     PM_TRY(pm::launch_set_io(h->io, io, s), "set io");
     st = enqueue_target(h, s);
     if (st != PM_OK) return st;
-    const RowLauncher row = kRowLaunch[log2i(h->W) - 4];
-    const ColLauncher col = kColLaunch[log2i(h->H) - 4];
-    PM_TRY(row(pm::ROW_INIT, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+    const RowLauncher row = kRowLaunch[len_slot(h->W)];
+    const ColLauncher col = kColLaunch[len_slot(h->H)];
+    PM_TRY(row(rmode(h, pm::ROW_INIT), row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
     PM_TRY(col(pm::COL_ITER, col_params(h, h->part), h->nwg_col, s, nullptr, nullptr), "column pass");
-    PM_TRY(row(pm::ROW_GAP, row_params(h, h->part + h->stride), h->nwg_row, s, nullptr, nullptr), "row gap");
-    PM_TRY(pm::launch_finalize(h->part, h->stride, h->nwg_col, h->nwg_row, 1.0 / h->N, h->io, 0, 2, s),
+    PM_TRY(row(rmode(h, pm::ROW_GAP), row_params(h, h->part + h->stride), h->nwg_row, s, nullptr, nullptr),
+           "row gap");
+    PM_TRY(pm::launch_finalize(h->part, h->stride, h->nwg_col, h->nwg_row, 1.0 / h->N, h->io, 0, 2, s, 1,
+                               pnorm2(h)),
            "finalize");
     return PM_OK;
 }
@@ -705,8 +773,8 @@ pm_status phasemask_fft2(pm_handle h, const void* in, void* out, int inverse) {
     if (!in || !out) return fail(PM_EINVAL, "null array argument");
     if (misaligned(in, 8) || misaligned(out, 8)) return fail(PM_EINVAL, "complex arrays must be 8-byte aligned");
     hipStream_t s = h->stream;
-    const RowLauncher row = kRowLaunch[log2i(h->W) - 4];
-    const ColLauncher col = kColLaunch[log2i(h->H) - 4];
+    const RowLauncher row = kRowLaunch[len_slot(h->W)];
+    const ColLauncher col = kColLaunch[len_slot(h->H)];
     pm::RowParams rp = row_params(h, nullptr);
     pm::ColParams cp = col_params(h, nullptr);
     if (!inverse) {
@@ -853,8 +921,8 @@ pm_status phasemask_intensity_loss_fwd(pm_handle h, int batch, const float* phas
     p.W = h->W;
     p.nwg = h->nwg_col;
     hipStream_t s = h->stream;
-    PM_TRY(kAdjRow[log2i(h->W) - 4](pm::ROW_INIT, p, batch, s), "loss row pass");
-    PM_TRY(kAdjCol[log2i(h->H) - 4](p, batch, s), "loss column pass");
+    PM_TRY(kAdjRow[len_slot(h->W)](pm::ROW_INIT, p, batch, s), "loss row pass");
+    PM_TRY(kAdjCol[len_slot(h->H)](p, batch, s), "loss column pass");
     PM_TRY(pm::launch_sum_rows(h->part, h->nwg_col, loss, batch, s), "loss sum");
     return PM_OK;
 }
@@ -877,7 +945,7 @@ pm_status phasemask_intensity_loss_bwd(pm_handle h, int batch, const float* phas
     p.H = h->H;
     p.W = h->W;
     p.nwg = h->nwg_col;
-    PM_TRY(kAdjRow[log2i(h->W) - 4](pm::ROW_GRAD, p, batch, h->stream), "gradient row pass");
+    PM_TRY(kAdjRow[len_slot(h->W)](pm::ROW_GRAD, p, batch, h->stream), "gradient row pass");
     return PM_OK;
 }
 
@@ -898,8 +966,8 @@ pm_status phasemask_initial_phase(pm_handle h, const float* target_amplitude, do
     cp.tmax_part = h->part_mx;
     cp.ntmax = kNormGrid;
     cp.t_dark = t_dark;
-    const RowLauncher row = kRowLaunch[log2i(h->W) - 4];
-    const ColLauncher col = kColLaunch[log2i(h->H) - 4];
+    const RowLauncher row = kRowLaunch[len_slot(h->W)];
+    const ColLauncher col = kColLaunch[len_slot(h->H)];
     PM_TRY(col(pm::COL_INIT_BIT, cp, h->nwg_col, s, nullptr, nullptr), "1-bit inverse column pass");
     PM_TRY(row(pm::ROW_LAST_NE, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "inverse row pass");
     return PM_OK;
@@ -925,9 +993,9 @@ pm_status phasemask_physical_error(pm_handle h, const float* target_amplitude, c
     pm::PmIo io{target_amplitude, phase, nullptr, nullptr};
     PM_TRY(pm::launch_set_io(h->io, io, s), "set io");
     PM_TRY(pm::launch_max_partial(target_amplitude, h->N, h->part_mx, kNormGrid, s), "target max");
-    const RowLauncher row = kRowLaunch[log2i(h->W) - 4];
-    const ColLauncher col = kColLaunch[log2i(h->H) - 4];
-    PM_TRY(row(pm::ROW_INIT, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+    const RowLauncher row = kRowLaunch[len_slot(h->W)];
+    const ColLauncher col = kColLaunch[len_slot(h->H)];
+    PM_TRY(row(rmode(h, pm::ROW_INIT), row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
     pm::ColParams cp = col_params(h, h->part);
     cp.pw = h->pw;
     PM_TRY(col(pm::COL_POW, cp, h->nwg_col, s, nullptr, nullptr), "power column pass");
@@ -954,9 +1022,9 @@ pm_status phasemask_time_passes(pm_handle h, const float* target_amplitude, cons
     PM_TRY(pm::launch_set_io(h->io, io, s), "set io");
     st = enqueue_target(h, s);
     if (st != PM_OK) return st;
-    const RowLauncher row = kRowLaunch[log2i(h->W) - 4];
-    const ColLauncher col = kColLaunch[log2i(h->H) - 4];
-    PM_TRY(row(pm::ROW_INIT, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+    const RowLauncher row = kRowLaunch[len_slot(h->W)];
+    const ColLauncher col = kColLaunch[len_slot(h->H)];
+    PM_TRY(row(rmode(h, pm::ROW_INIT), row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
     std::vector<hipEvent_t> ev(4 * (size_t)reps, nullptr);
     auto cleanup = [&]() {
         for (hipEvent_t e : ev)
@@ -973,7 +1041,7 @@ pm_status phasemask_time_passes(pm_handle h, const float* target_amplitude, cons
     for (int r = 0; r < reps && err == hipSuccess; ++r) {
         err = col(pm::COL_ITER, col_params(h, h->part), h->nwg_col, s, ev[4 * r], ev[4 * r + 1]);
         if (err == hipSuccess)
-            err = row(pm::ROW_ITER, row_params(h, h->part + h->stride), h->nwg_row, s, ev[4 * r + 2],
+            err = row(rmode(h, pm::ROW_ITER), row_params(h, h->part + h->stride), h->nwg_row, s, ev[4 * r + 2],
                       ev[4 * r + 3]);
     }
     if (err == hipSuccess) err = hipStreamSynchronize(s);

@@ -17,14 +17,13 @@ __global__ void k_set_io(PmIo* io, PmIo val) {
 
 constexpr int kAuxThreads = 256;
 
-// Partial sums of m^2 in FP64, one per work-group (grid-stride over float4).
-__global__ void __launch_bounds__(kAuxThreads) k_norm_partial(const PmIo* io, int n, double* part) {
-    __shared__ double red[kAuxThreads / 64];
-    const float4* m4 = reinterpret_cast<const float4*>(io->target);
+// Partial sums of x^2 in FP64, one per work-group (grid-stride over float4).
+__device__ __forceinline__ void sq_partial(const float* x, int n, double* part, double* red) {
+    const float4* x4 = reinterpret_cast<const float4*>(x);
     const int n4 = n / 4;
     double acc = 0.0;
     for (int i = blockIdx.x * kAuxThreads + threadIdx.x; i < n4; i += gridDim.x * kAuxThreads) {
-        const float4 q = m4[i];
+        const float4 q = x4[i];
         acc = fma((double)q.x, (double)q.x, acc);
         acc = fma((double)q.y, (double)q.y, acc);
         acc = fma((double)q.z, (double)q.z, acc);
@@ -34,18 +33,57 @@ __global__ void __launch_bounds__(kAuxThreads) k_norm_partial(const PmIo* io, in
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
+__global__ void __launch_bounds__(kAuxThreads) k_norm_partial(const PmIo* io, int n, double* part) {
+    __shared__ double red[red_slots(kAuxThreads)];
+    sq_partial(io->target, n, part, red);
+}
+
+__global__ void __launch_bounds__(kAuxThreads) k_sq_partial(const float* x, int n, double* part) {
+    __shared__ double red[red_slots(kAuxThreads)];
+    sq_partial(x, n, part, red);
+}
+
+// Natural [H][W] floats to the strip-tiled layout, one float4 per thread;
+// block 0 also sums the `npart` partials in a fixed order into *sum.
+__global__ void __launch_bounds__(kAuxThreads)
+k_tile_plain(const float* src, int H, int W, float* dst, const double* part, int npart, double* sum) {
+    static_assert(kC == 4, "one float4 per strip chunk");
+    const int w4 = W / 4;
+    const int i = blockIdx.x * kAuxThreads + threadIdx.x;
+    if (i < H * w4) {
+        const int y = i / w4;
+        const int q = i - y * w4;
+        reinterpret_cast<float4*>(dst)[(size_t)q * H + y] = reinterpret_cast<const float4*>(src)[i];
+    }
+    if (blockIdx.x == 0) {
+        __shared__ double red[red_slots(kAuxThreads)];
+        double acc = 0.0;
+        for (int k = threadIdx.x; k < npart; k += kAuxThreads) acc += part[k];
+        const double tot = block_sum<kAuxThreads>(acc, red);
+        if (threadIdx.x == 0) *sum = tot;
+    }
+}
+
 // mhat = m / ||m|| in the strip-tiled layout.  Every work-group sums the
 // partials itself in the same fixed order, so all see the same norm.
 // One thread per 4 consecutive pixels of a row (= one strip chunk, kC = 4).
 __global__ void __launch_bounds__(kAuxThreads)
-k_target_tile(const PmIo* io, int H, int W, const double* part, int npart, float* mhat) {
+k_target_tile(const PmIo* io, int H, int W, const double* part, int npart, float* mhat, const double* pn2) {
     static_assert(kC == 4, "one float4 per strip chunk");
-    __shared__ double red[kAuxThreads / 64];
+    __shared__ double red[red_slots(kAuxThreads)];
     __shared__ double inv_norm;
     double acc = 0.0;
     for (int i = threadIdx.x; i < npart; i += kAuxThreads) acc += part[i];
     const double tot = block_sum<kAuxThreads>(acc, red);
-    if (threadIdx.x == 0) inv_norm = tot > 0.0 ? 1.0 / sqrt(tot) : 0.0;
+    // p = 1: m / ||m||.  Illumination p: m ||p|| / (||m|| sqrt(N)), the
+    // energy-matched target on the scale of unnormalised transforms.
+    if (threadIdx.x == 0) {
+        if (pn2 == nullptr) {
+            inv_norm = tot > 0.0 ? 1.0 / sqrt(tot) : 0.0;
+        } else {
+            inv_norm = tot > 0.0 ? sqrt(pn2[0] / ((double)H * (double)W)) / sqrt(tot) : 0.0;
+        }
+    }
     __syncthreads();
     const double inv = inv_norm;
     const int w4 = W / 4;
@@ -66,10 +104,12 @@ k_target_tile(const PmIo* io, int H, int W, const double* part, int npart, float
 // History entry e = first_entry + blockIdx.x * entry_step: even entries are Fourier
 // errors, E_F = sqrt(sum of partials); odd entries are gaps,
 // G = sqrt(sum / N).  Partials of entry e sit at part[e * stride + wg].
+// With an illumination p (pn2 = ||p||^2 on the device) the errors are
+// relative to ||p||: E_F = sqrt(sum N / ||p||^2), G = sqrt(sum / ||p||^2).
 __global__ void __launch_bounds__(kAuxThreads)
 k_finalize(const double* part, int stride, int nwg_col, int nwg_row, double invN,
-           const PmIo* io, int first_entry, int entry_step) {
-    __shared__ double red[kAuxThreads / 64];
+           const PmIo* io, int first_entry, int entry_step, const double* pn2) {
+    __shared__ double red[red_slots(kAuxThreads)];
     const int e = first_entry + blockIdx.x * entry_step;
     const int nwg = (e & 1) ? nwg_row : nwg_col;
     const double* p = part + (size_t)e * stride;
@@ -78,7 +118,9 @@ k_finalize(const double* part, int stride, int nwg_col, int nwg_row, double invN
     const double tot = block_sum<kAuxThreads>(acc, red);
     if (threadIdx.x == 0) {
         double* hist = io->hist;
-        if (hist != nullptr) hist[blockIdx.x] = (e & 1) ? sqrt(tot * invN) : sqrt(tot);
+        const double ef2 = pn2 == nullptr ? 1.0 : 1.0 / (invN * pn2[0]);
+        const double g2 = pn2 == nullptr ? invN : 1.0 / pn2[0];
+        if (hist != nullptr) hist[blockIdx.x] = (e & 1) ? sqrt(tot * g2) : sqrt(tot * ef2);
     }
 }
 
@@ -106,7 +148,7 @@ __global__ void k_set_batch_io(BatchIo* io, BatchIo val) {
 __global__ void __launch_bounds__(kAuxThreads)
 k_batch_norm(const BatchIo* io, const BatchTask* tasks, double* part_m) {
     static_assert(kPrepPixels == kAuxThreads * 16, "4 float4 per thread");
-    __shared__ double red[kAuxThreads / 64];
+    __shared__ double red[red_slots(kAuxThreads)];
     const BatchTask task = tasks[blockIdx.x];
     const float4* m4 = reinterpret_cast<const float4*>(io->targets[task.mask] + task.first);
     double acc = 0.0;
@@ -127,7 +169,7 @@ k_batch_norm(const BatchIo* io, const BatchTask* tasks, double* part_m) {
 __global__ void __launch_bounds__(kAuxThreads)
 k_batch_tile(const BatchIo* io, const BatchMask* masks, const BatchTask* tasks, const int* mask_prep0,
              const double* part_m) {
-    __shared__ double red[kAuxThreads / 64];
+    __shared__ double red[red_slots(kAuxThreads)];
     __shared__ double inv_norm;
     const BatchTask task = tasks[blockIdx.x];
     const BatchMask mk = masks[task.mask];
@@ -173,7 +215,7 @@ k_batch_wrap(const BatchIo* io, const BatchTask* tasks) {
 // final_err[mask] = sqrt(sum of the mask's column-pass partials).
 __global__ void __launch_bounds__(kAuxThreads)
 k_batch_finalize(const BatchIo* io, const BatchMask* masks, const double* part) {
-    __shared__ double red[kAuxThreads / 64];
+    __shared__ double red[red_slots(kAuxThreads)];
     const BatchMask mk = masks[blockIdx.x];
     double acc = 0.0;
     for (int i = threadIdx.x; i < mk.col_wgs; i += kAuxThreads) acc += part[mk.col_wg0 + i];
@@ -213,7 +255,7 @@ hipError_t launch_batch_finalize(const BatchIo* io, const BatchMask* masks, int 
 
 // out[b] = sum of one row of partials, fixed order (one work-group per row).
 __global__ void __launch_bounds__(kAuxThreads) k_sum_rows(const double* part, int nwg, double* out) {
-    __shared__ double red[kAuxThreads / 64];
+    __shared__ double red[red_slots(kAuxThreads)];
     const double* p = part + (size_t)blockIdx.x * nwg;
     double acc = 0.0;
     for (int i = threadIdx.x; i < nwg; i += kAuxThreads) acc += p[i];
@@ -229,7 +271,7 @@ hipError_t launch_sum_rows(const double* part, int nwg, double* out, int count, 
 // ----- physical error (Eq. 8) and target maxima -------------------------------
 
 __global__ void __launch_bounds__(kAuxThreads) k_max_partial(const float* x, int n, float* part) {
-    __shared__ float redf[kAuxThreads / 64];
+    __shared__ float redf[red_slots(kAuxThreads)];
     const float4* x4 = reinterpret_cast<const float4*>(x);
     float mx = 0.0f;
     for (int i = blockIdx.x * kAuxThreads + threadIdx.x; i < n / 4; i += gridDim.x * kAuxThreads) {
@@ -249,8 +291,8 @@ k_physical_error(const float* pw, const double* pw_max_part, int n_pw_max, const
                  const float* tmax_part, int ntmax, int H, int W, double t_lit, double t_dark,
                  double* scratch) {
     static_assert(kC == 4, "one float4 per strip chunk");
-    __shared__ double red[kAuxThreads / 64];
-    __shared__ float redf[kAuxThreads / 64];
+    __shared__ double red[red_slots(kAuxThreads)];
+    __shared__ float redf[red_slots(kAuxThreads)];
     __shared__ double pmax_s;
     double pm = 0.0;
     for (int i = threadIdx.x; i < n_pw_max; i += kAuxThreads) pm = fmax(pm, pw_max_part[i]);
@@ -293,7 +335,7 @@ k_physical_error(const float* pw, const double* pw_max_part, int n_pw_max, const
 }
 
 __global__ void __launch_bounds__(kAuxThreads) k_pair_sum(const double* scratch, int n, double* out) {
-    __shared__ double red[kAuxThreads / 64];
+    __shared__ double red[red_slots(kAuxThreads)];
     double a = 0.0, b = 0.0;
     for (int i = threadIdx.x; i < n; i += kAuxThreads) {
         a += scratch[2 * i];
@@ -338,15 +380,27 @@ hipError_t launch_norm_partial(const PmIo* io, int n, double* part, int grid, hi
 }
 
 hipError_t launch_target_tile(const PmIo* io, int H, int W, const double* part, int npart,
-                              float* mhat, hipStream_t s) {
+                              float* mhat, hipStream_t s, const double* pn2) {
     const int grid = (H * (W / 4) + kAuxThreads - 1) / kAuxThreads;
-    k_target_tile<<<grid, kAuxThreads, 0, s>>>(io, H, W, part, npart, mhat);
+    k_target_tile<<<grid, kAuxThreads, 0, s>>>(io, H, W, part, npart, mhat, pn2);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const double* part, int stride, int nwg_col, int nwg_row, double invN,
-                           const PmIo* io, int first_entry, int count, hipStream_t s, int entry_step) {
-    k_finalize<<<count, kAuxThreads, 0, s>>>(part, stride, nwg_col, nwg_row, invN, io, first_entry, entry_step);
+                           const PmIo* io, int first_entry, int count, hipStream_t s, int entry_step,
+                           const double* pn2) {
+    k_finalize<<<count, kAuxThreads, 0, s>>>(part, stride, nwg_col, nwg_row, invN, io, first_entry, entry_step,
+                                             pn2);
+    return hipGetLastError();
+}
+
+hipError_t launch_illum_prep(const float* p, int H, int W, double* part, int grid, float* illum,
+                             double* pn2, hipStream_t s) {
+    k_sq_partial<<<grid, kAuxThreads, 0, s>>>(p, H * W, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int tgrid = (H * (W / 4) + kAuxThreads - 1) / kAuxThreads;
+    k_tile_plain<<<tgrid, kAuxThreads, 0, s>>>(p, H, W, illum, part, grid, pn2);
     return hipGetLastError();
 }
 

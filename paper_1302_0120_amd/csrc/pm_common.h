@@ -40,6 +40,7 @@ enum : int {
     ROUT_GRAD = 512,  // intensity-loss gradient 4 gscale Im(e^{-i phi} g)
     R_RAAR = 1024,    // RAAR update of the SLM-plane point x (kept in Z) from w = P_M x
     R_STOREZ = 2048,  // store the initial field to Z (RAAR start)
+    R_ILLUM = 4096,   // illumination amplitude p of Eq. 1 on S (else p = 1)
 };
 constexpr int ROW_INIT = RIN_PHASE | R_FWD;
 constexpr int ROW_ITER = RIN_TILED | R_INV | R_PS | R_FWD;
@@ -95,6 +96,7 @@ struct RowParams {
     float gscale;          // ROUT_GRAD: gradient scale 4 g_out / N
     float2* Z;             // R_RAAR / R_STOREZ: SLM-plane point x, strip-tiled
     float beta;            // R_RAAR: relaxation parameter
+    const float* illum;    // R_ILLUM: illumination amplitude p, strip-tiled (float per pixel)
     int spread;            // launch at most one work-group per CU (grid fits the CUs)
 };
 
@@ -130,7 +132,8 @@ struct AdjParams {
     int H, W, nwg;
 };
 
-// Launchers, one pair per supported transform length (16 .. 4096), defined
+// Launchers, one pair per supported transform length (powers of two 16 ..
+// 4096, and the mixed-radix lengths 600, 800, 1080 and 1920), defined
 // in the per-length kernel translation units.  `grid` is the number of
 // work-groups; the block size is fixed by the length.  With non-null
 // events the launch records the kernel's own start and end on them
@@ -152,6 +155,10 @@ PM_DECLARE_ADJ_LAUNCHERS(512)
 PM_DECLARE_ADJ_LAUNCHERS(1024)
 PM_DECLARE_ADJ_LAUNCHERS(2048)
 PM_DECLARE_ADJ_LAUNCHERS(4096)
+PM_DECLARE_ADJ_LAUNCHERS(600)
+PM_DECLARE_ADJ_LAUNCHERS(800)
+PM_DECLARE_ADJ_LAUNCHERS(1080)
+PM_DECLARE_ADJ_LAUNCHERS(1920)
 #undef PM_DECLARE_ADJ_LAUNCHERS
 
 PM_DECLARE_LAUNCHERS(16)
@@ -163,6 +170,10 @@ PM_DECLARE_LAUNCHERS(512)
 PM_DECLARE_LAUNCHERS(1024)
 PM_DECLARE_LAUNCHERS(2048)
 PM_DECLARE_LAUNCHERS(4096)
+PM_DECLARE_LAUNCHERS(600)
+PM_DECLARE_LAUNCHERS(800)
+PM_DECLARE_LAUNCHERS(1080)
+PM_DECLARE_LAUNCHERS(1920)
 #undef PM_DECLARE_LAUNCHERS
 
 // ---------------------------------------------------------------------------
@@ -242,11 +253,20 @@ hipError_t launch_batch_finalize(const BatchIo* io, const BatchMask* masks, int 
 // Small kernels (pm_aux.hip).
 hipError_t launch_set_io(PmIo* io, const PmIo& val, hipStream_t s);
 hipError_t launch_norm_partial(const PmIo* io, int n, double* part, int grid, hipStream_t s);
+// mhat = m / ||m||, or with an illumination (pn2 = device pointer to ||p||^2)
+// m ||p|| / (||m|| sqrt(N)), strip-tiled.
 hipError_t launch_target_tile(const PmIo* io, int H, int W, const double* part, int npart,
-                              float* mhat, hipStream_t s);
+                              float* mhat, hipStream_t s, const double* pn2 = nullptr);
 // History entries first_entry + k * entry_step, k < count, into hist[k].
+// pn2: ||p||^2 on the device with an illumination, else null (p = 1).
 hipError_t launch_finalize(const double* part, int stride, int nwg_col, int nwg_row, double invN,
-                           const PmIo* io, int first_entry, int count, hipStream_t s, int entry_step = 1);
+                           const PmIo* io, int first_entry, int count, hipStream_t s, int entry_step = 1,
+                           const double* pn2 = nullptr);
+// Illumination set-up: p (natural layout [H][W]) copied to the strip-tiled
+// `illum`, and ||p||^2 (FP64, fixed summation order) to *pn2; `part` holds
+// `grid` doubles of scratch.
+hipError_t launch_illum_prep(const float* p, int H, int W, double* part, int grid, float* illum,
+                             double* pn2, hipStream_t s);
 hipError_t launch_wrap_phase(const PmIo* io, int n, hipStream_t s);
 // Per-work-group maxima of a float array (n a multiple of 4).
 hipError_t launch_max_partial(const float* x, int n, float* part, int grid, hipStream_t s);

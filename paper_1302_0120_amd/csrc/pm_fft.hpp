@@ -15,10 +15,15 @@
 //     next inputs x[j + T t]; the last stage's outputs land exactly in the
 //     thread's own slots, so a line needs (#stages - 1) LDS exchanges and the
 //     first read / last write can go straight to or from global memory.
-//   * Radix sequence: P, P, ..., then the remaining factor (each divides P).
+//   * Radix sequence: P, P, ..., then the remaining factor (each divides P)
+//     for powers of two; fixed mixed-radix sequences (radices 4, 6, 8, 10,
+//     12, 30) for the non-power-of-two lengths 600, 800, 1080 and 1920,
+//     whose butterfly index b and sub-length NS are then not powers of two
+//     (b mod NS is a true modulo).
 //   * Twiddles come from a table tw[i] = exp(-2 pi i i / L) computed on the
 //     host in double precision and rounded once to float; each thread loads
-//     the ones it needs into registers at kernel start.
+//     the ones it needs into registers at kernel start (or, for the long
+//     mixed-radix plans, reads them from the table stage by stage).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -66,7 +71,8 @@ __device__ __forceinline__ float2 tw16(float2 a) {
     }
 }
 
-// In-register DFTs of R = 2, 4, 8, 16 points, natural order in and out.
+// In-register DFTs of R = 2, 3, 4, 5, 6, 8, 10, 12, 16, 30 points, natural
+// order in and out.
 // Each first forms sums and differences of input pairs, so equal inputs give
 // exact zeros off the zero frequency (the constant-field tie-break case).
 template <bool INV>
@@ -79,9 +85,142 @@ __device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2&
     x3 = csub(d02, d13);
 }
 
+// Radix-3 DFT from its definition with w = exp(-+2 pi i / 3):
+// X0 = x0 + (x1 + x2); X1,2 = x0 - (x1 + x2)/2 -+ i (sqrt(3)/2)(x1 - x2).
+template <bool INV>
+__device__ __forceinline__ void dft3(float2& x0, float2& x1, float2& x2) {
+    constexpr float S3 = 0.86602540378443865f;  // sin(2 pi / 3)
+    const float2 s = cadd(x1, x2);
+    const float2 d = csub(x1, x2);
+    const float2 t = make_float2(x0.x - 0.5f * s.x, x0.y - 0.5f * s.y);
+    const float2 r = rot90<INV>(make_float2(S3 * d.x, S3 * d.y));  // -+i (sqrt3/2) d
+    x0 = cadd(x0, s);
+    x1 = cadd(t, r);
+    x2 = csub(t, r);
+}
+
+// Radix-5 DFT from its definition with w = exp(-+2 pi i / 5), pairing
+// n with 5 - n (s = pair sums, d = pair differences):
+//   X_{1,4} = x0 + c1 s1 + c2 s2 -+ i (S1 d1 + S2 d2),
+//   X_{2,3} = x0 + c2 s1 + c1 s2 -+ i (S2 d1 - S1 d2),
+// c_k = cos(2 pi k / 5), S_k = sin(2 pi k / 5).  The cosine parts are formed
+// as x0 - (s1 + s2)/4 +- (sqrt5/4)(s1 - s2) (c1 + c2 = -1/2, c1 - c2 =
+// sqrt5/2), so equal inputs give exact zeros off the zero frequency.
+template <bool INV>
+__device__ __forceinline__ void dft5(float2& x0, float2& x1, float2& x2, float2& x3, float2& x4) {
+    constexpr float Q5 = 0.55901699437494742f;   // sqrt(5) / 4
+    constexpr float S1 = 0.95105651629515357f;   // sin(2 pi / 5)
+    constexpr float S2 = 0.58778525229247313f;   // sin(4 pi / 5)
+    const float2 s1 = cadd(x1, x4), d1 = csub(x1, x4);
+    const float2 s2 = cadd(x2, x3), d2 = csub(x2, x3);
+    const float2 t1 = cadd(s1, s2), t2 = csub(s1, s2);
+    const float2 a = make_float2(x0.x - 0.25f * t1.x, x0.y - 0.25f * t1.y);
+    const float2 m2 = make_float2(Q5 * t2.x, Q5 * t2.y);
+    const float2 a1 = cadd(a, m2), a2 = csub(a, m2);
+    const float2 b1 = rot90<INV>(make_float2(S1 * d1.x + S2 * d2.x, S1 * d1.y + S2 * d2.y));
+    const float2 b2 = rot90<INV>(make_float2(S2 * d1.x - S1 * d2.x, S2 * d1.y - S1 * d2.y));
+    x0 = cadd(x0, t1);
+    x1 = cadd(a1, b1);
+    x4 = csub(a1, b1);
+    x2 = cadd(a2, b2);
+    x3 = csub(a2, b2);
+}
+
+// cos and sin of 2 pi e / d for the internal twiddles of composite radices,
+// evaluated at compile time in double: the angle reduced to [-pi, pi], then
+// the Taylor series (30 terms; the largest term at pi is below 6, so the
+// cancellation error stays near 1e-15), rounded once to float.  Values
+// within 1e-12 of 0 are snapped to 0 (the quarter turns).
+__host__ __device__ constexpr double ct_angle(int e, int d) {
+    int r = ((e % d) + d) % d;
+    if (2 * r > d) r -= d;
+    return 6.283185307179586476925286766559 * (double)r / (double)d;
+}
+__host__ __device__ constexpr double ct_sin(double x) {
+    double term = x, sum = x;
+    for (int k = 1; k < 30; ++k) {
+        term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+        sum += term;
+    }
+    return (sum < 1e-12 && sum > -1e-12) ? 0.0 : sum;
+}
+__host__ __device__ constexpr double ct_cos(double x) {
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 30; ++k) {
+        term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+        sum += term;
+    }
+    return (sum < 1e-12 && sum > -1e-12) ? 0.0 : sum;
+}
+
+template <int D>
+struct TurnTable {
+    float c[D], s[D];
+    constexpr TurnTable() : c(), s() {
+        for (int e = 0; e < D; ++e) {
+            c[e] = (float)ct_cos(ct_angle(e, D));
+            s[e] = (float)ct_sin(ct_angle(e, D));
+        }
+    }
+};
+
+// R = R1 R2 by one Cooley-Tukey step: n = R2 n1 + n2, k = k1 + R1 k2.
+// DFT_R1 over n1 for each n2, twiddle exp(-+2 pi i n2 k1 / R), DFT_R2 over
+// n2 for each k1.  All indices are compile-time constants once the loops
+// are unrolled, so the twiddles are immediate constants.
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2 (&x)[R]);
+
+template <int R1, int R2, bool INV>
+__device__ __forceinline__ void dft_ct(float2 (&x)[R1 * R2]) {
+    constexpr int R = R1 * R2;
+    constexpr TurnTable<R> tt{};
+    float2 y[R];  // y[n2 R1 + k1]
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+        float2 col[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) col[n1] = x[R2 * n1 + n2];
+        dft<R1, INV>(col);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            const int e = (n2 * k1) % R;
+            if (e == 0) {
+                y[n2 * R1 + k1] = col[k1];
+            } else {
+                const float c = tt.c[e];
+                const float sn = INV ? tt.s[e] : -tt.s[e];
+                const float2 v = col[k1];
+                y[n2 * R1 + k1] = make_float2(v.x * c - v.y * sn, v.x * sn + v.y * c);
+            }
+        }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        float2 row[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) row[n2] = y[n2 * R1 + k1];
+        dft<R2, INV>(row);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) x[k1 + R1 * k2] = row[k2];
+    }
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void dft(float2 (&x)[R]) {
-    if constexpr (R == 2) {
+    if constexpr (R == 3) {
+        dft3<INV>(x[0], x[1], x[2]);
+    } else if constexpr (R == 5) {
+        dft5<INV>(x[0], x[1], x[2], x[3], x[4]);
+    } else if constexpr (R == 6) {
+        dft_ct<3, 2, INV>(x);
+    } else if constexpr (R == 10) {
+        dft_ct<5, 2, INV>(x);
+    } else if constexpr (R == 12) {
+        dft_ct<3, 4, INV>(x);
+    } else if constexpr (R == 30) {
+        dft_ct<10, 3, INV>(x);
+    } else if constexpr (R == 2) {
         const float2 t = csub(x[0], x[1]);
         x[0] = cadd(x[0], x[1]);
         x[1] = t;
@@ -129,7 +268,9 @@ __device__ __forceinline__ void dft(float2 (&x)[R]) {
 #pragma unroll
         for (int k = 0; k < 16; ++k) x[k] = y[k];
     } else {
-        static_assert(R == 2 || R == 4 || R == 8 || R == 16, "unsupported radix");
+        static_assert(R == 2 || R == 3 || R == 4 || R == 5 || R == 6 || R == 8 || R == 10 || R == 12 ||
+                          R == 16 || R == 30,
+                      "unsupported radix");
     }
 }
 
@@ -143,8 +284,16 @@ __device__ __forceinline__ constexpr int lds_pad(int i) { return i + (i >> 4); }
 #endif
 __host__ __device__ constexpr int lds_line_len(int L) { return L + L / 16 + PM_LDS_LINE_EXTRA; }
 
-// Radix of the stage that starts at sub-transform length NS.
+// Radix of the stage that starts at sub-transform length NS.  Powers of two
+// take P, P, ..., remainder.  The non-power-of-two lengths of common SLM
+// panels (800 x 600, 1920 x 1080) take fixed mixed-radix sequences whose
+// radices divide P: 800 = 8*10*10 (P = 40), 600 = 6*10*10 (P = 30),
+// 1080 = 30*6*6 (P = 30), 1920 = 12*10*4*4 (P = 60).
 __host__ __device__ constexpr int stage_radix(int L, int P, int NS) {
+    if (L == 800) return NS == 1 ? 8 : 10;
+    if (L == 600) return NS == 1 ? 6 : 10;
+    if (L == 1080) return NS == 1 ? 30 : 6;
+    if (L == 1920) return NS == 1 ? 12 : (NS == 12 ? 10 : 4);
     return (L / NS) >= P ? P : (L / NS);
 }
 
@@ -158,11 +307,20 @@ __host__ __device__ constexpr int twiddles_from(int L, int P, int NS) {
 
 // The thread's twiddle factors for a whole line transform, loaded once from
 // the table before any barrier (so their latency overlaps the data loads);
-// the inverse transform uses their conjugates.
+// the inverse transform uses their conjugates.  Plans that need more than
+// kMaxTwiddleRegs of them (the long mixed-radix plans, 54 and 72 factors)
+// would not fit the register file next to their data, so their stages read
+// the factors from the table (an L1-resident few KB) instead.
+constexpr int kMaxTwiddleRegs = 32;
+
 template <int L, int P>
 struct LineTwiddles {
-    static constexpr int COUNT = twiddles_from(L, P, 1) > 0 ? twiddles_from(L, P, 1) : 1;
+    static constexpr int NEED = twiddles_from(L, P, 1);
+    static constexpr bool PRELOAD = NEED <= kMaxTwiddleRegs;
+    static constexpr int COUNT = (PRELOAD && NEED > 0) ? NEED : 1;
     float2 w[COUNT];
+    const float2* table;
+    int step;
 };
 
 template <int L, int P, int NS, int OFF>
@@ -176,7 +334,7 @@ __device__ __forceinline__ void load_twiddles_from(LineTwiddles<L, P>& tw, int j
             constexpr int STRIDE = L / (NS * R);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                const int k = (j + T * m) & (NS - 1);
+                const int k = (j + T * m) % NS;
 #pragma unroll
                 for (int q = 1; q < R; ++q) tw.w[OFF + m * (R - 1) + (q - 1)] = table[q * k * STRIDE * step];
             }
@@ -192,7 +350,9 @@ __device__ __forceinline__ void load_twiddles_from(LineTwiddles<L, P>& tw, int j
 template <int L, int P>
 __device__ __forceinline__ void load_twiddles(LineTwiddles<L, P>& tw, int j, const float2* __restrict__ table,
                                               int step) {
-    load_twiddles_from<L, P, 1, 0>(tw, j, table, step);
+    tw.table = table;
+    tw.step = step;
+    if constexpr (LineTwiddles<L, P>::PRELOAD) load_twiddles_from<L, P, 1, 0>(tw, j, table, step);
 }
 
 // LDS exchange buffers per line: two (alternating, one barrier per
@@ -228,11 +388,16 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, i
 #pragma unroll
         for (int q = 0; q < R; ++q) x[q] = v[m + q * M];
         const int b = j + T * m;
-        const int k = b & (NS - 1);
+        const int k = b % NS;
         if constexpr (NS > 1) {
 #pragma unroll
             for (int q = 1; q < R; ++q) {
-                float2 w = tw.w[OFF + m * (R - 1) + (q - 1)];
+                float2 w;
+                if constexpr (LineTwiddles<L, P>::PRELOAD) {
+                    w = tw.w[OFF + m * (R - 1) + (q - 1)];
+                } else {
+                    w = tw.table[q * k * (L / (NS * R)) * tw.step];
+                }
                 if constexpr (INV) w.y = -w.y;
                 x[q] = cmul(x[q], w);
             }
@@ -277,7 +442,11 @@ __host__ __device__ constexpr int fft_parity_after() {
 
 // Points per thread for a line of L points.
 __host__ __device__ constexpr int points_per_thread(int L) {
-    return L >= 256 ? 16 : (L >= 32 ? 8 : 4);
+    return L == 800 ? 40
+         : L == 600 ? 30
+         : L == 1080 ? 30
+         : L == 1920 ? 60
+         : (L >= 256 ? 16 : (L >= 32 ? 8 : 4));
 }
 
 }  // namespace pm

@@ -23,21 +23,27 @@
 
 namespace pm {
 
+// Reduction groups of a work-group of NT threads: the largest power of two
+// that divides NT, at most one wave.  A group is a run of whole lanes, so
+// the in-group shuffles never read an inactive lane (a work-group of 80
+// threads is one full wave and a quarter wave: five groups of 16).
+__host__ __device__ constexpr int red_width(int NT) { return (NT & -NT) < 64 ? (NT & -NT) : 64; }
+__host__ __device__ constexpr int red_slots(int NT) { return NT / red_width(NT); }
+
 // Deterministic work-group sum of one double per thread: a fixed xor
-// butterfly inside each wave, then wave results added in wave order by
-// thread 0.  The result is valid in thread 0 only.  All threads must call.
+// butterfly inside each reduction group, then group results added in group
+// order by thread 0.  The result is valid in thread 0 only.  All threads
+// must call; `red` holds red_slots(NT) doubles.
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* red) {
-    constexpr int WS = NT < 64 ? NT : 64;
-    constexpr int NW = (NT + 63) / 64;
+    constexpr int WS = red_width(NT);
+    constexpr int NW = red_slots(NT);
 #pragma unroll
     for (int off = WS / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WS);
     if constexpr (NW == 1) {
         return v;
     } else {
-        const int lane = threadIdx.x & 63;
-        const int wave = threadIdx.x >> 6;
-        if (lane == 0) red[wave] = v;
+        if (threadIdx.x % WS == 0) red[threadIdx.x / WS] = v;
         __syncthreads();
         double s = 0.0;
         if (threadIdx.x == 0) {
@@ -60,15 +66,16 @@ __device__ __forceinline__ void store_shared(float2* p, float2 v) {
 }
 
 // Work-group maximum of one float per thread, returned to every thread.
-// Max is exact, so the order does not matter.  All threads must call.
+// Max is exact, so the order does not matter.  All threads must call;
+// `redf` holds red_slots(NT) floats.
 template <int NT>
 __device__ __forceinline__ float block_max(float v, float* redf) {
-    constexpr int WS = NT < 64 ? NT : 64;
-    constexpr int NW = (NT + 63) / 64;
+    constexpr int WS = red_width(NT);
+    constexpr int NW = red_slots(NT);
 #pragma unroll
     for (int off = WS / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, WS));
     if constexpr (NW > 1) {
-        if ((threadIdx.x & 63) == 0) redf[threadIdx.x >> 6] = v;
+        if (threadIdx.x % WS == 0) redf[threadIdx.x / WS] = v;
         __syncthreads();
         v = redf[0];
 #pragma unroll
@@ -89,7 +96,7 @@ struct LineShape {
 // `strip0` (G a multiple of kC).  Thread tid = (sl, j, c), c fastest: strip
 // strip0 + sl, column c of that strip, rows j + T t.  For a fixed t a wave's
 // loads are 64 / kC consecutive rows of one strip: one contiguous run.
-// `lds` holds LdsPlan<H, G>::FLOATS2 elements, `red` NT / 64 doubles.
+// `lds` holds LdsPlan<H, G>::FLOATS2 elements, `red` red_slots(G T) doubles.
 template <int H, int P, int G, int MODE>
 __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double* part_slot,
                                          float2* lds, double* red) {
@@ -238,13 +245,23 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
     LineTwiddles<W, P> tw;
     load_twiddles(tw, j, a.tw, a.tw_step);
     float2 v[P];
+    // Illumination amplitude p of Eq. 1 (S = fields of modulus p): the
+    // projections below take modulus p instead of 1.
+    constexpr bool ILLUM = (MODE & R_ILLUM) != 0;
+    static_assert(!ILLUM || (MODE & ROUT_PHASE) == 0 || (MODE & (R_PS | R_RAAR)) != 0,
+                  "with an illumination the phase is written by P_S or the RAAR update");
+    float pil[ILLUM ? P : 1];
+    if constexpr (ILLUM) {
+#pragma unroll
+        for (int t = 0; t < P; ++t) pil[t] = a.illum[tiled(t)];
+    }
 
     if constexpr ((MODE & RIN_PHASE) != 0) {
 #pragma unroll
         for (int t = 0; t < P; ++t) {
             float sn, cs;
             sincosf(phase_in[natural(t)], &sn, &cs);
-            v[t] = make_float2(cs, sn);
+            v[t] = ILLUM ? make_float2(pil[t] * cs, pil[t] * sn) : make_float2(cs, sn);
         }
     } else if constexpr ((MODE & RIN_NAT) != 0) {
 #pragma unroll
@@ -279,11 +296,18 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
             // Tie-break of Eq. 4a below FLT_MIN (phase 0), as in the column pass.
             const bool nz = a2 >= FLT_MIN;
             const float r = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
+            const float2 e = nz ? make_float2(w.x * r, w.y * r) : make_float2(1.0f, 0.0f);
             if constexpr (ERR) {
-                const double d = (double)(a2 * r) - 1.0;
+                const double d = (double)(a2 * r) - (ILLUM ? (double)pil[t] : 1.0);
                 acc = fma(d, d, acc);
             }
-            v[t] = nz ? make_float2(w.x * r, w.y * r) : make_float2(1.0f, 0.0f);
+            if constexpr (ILLUM) {
+                // the phase of the mask is that of e (also where p = 0)
+                if constexpr ((MODE & ROUT_PHASE) != 0) phase_out[natural(t)] = atan2f(e.y, e.x);
+                v[t] = make_float2(pil[t] * e.x, pil[t] * e.y);
+            } else {
+                v[t] = e;
+            }
         }
         if constexpr (ERR) {
             const double tot = block_sum<NT>(acc, red);
@@ -305,14 +329,21 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
             const float a2 = y.x * y.x + y.y * y.y;
             const bool nz = a2 >= FLT_MIN;
             const float r = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
-            const float2 ps = nz ? make_float2(y.x * r, y.y * r) : make_float2(1.0f, 0.0f);
+            float2 ps = nz ? make_float2(y.x * r, y.y * r) : make_float2(1.0f, 0.0f);
+            if constexpr (ILLUM) ps = make_float2(pil[t] * ps.x, pil[t] * ps.y);
             const float2 xn = make_float2(b * ps.x + b * x.x + c * w.x, b * ps.y + b * x.y + c * w.y);
             if constexpr ((MODE & ROUT_PHASE) != 0) {
                 // last pass: the mask is the shadow P_S x^n
                 const float q2 = xn.x * xn.x + xn.y * xn.y;
                 const bool qz = q2 >= FLT_MIN;
                 const float qr = qz ? __builtin_amdgcn_rsqf(q2) : 0.0f;
-                v[t] = qz ? make_float2(xn.x * qr, xn.y * qr) : make_float2(1.0f, 0.0f);
+                const float2 e = qz ? make_float2(xn.x * qr, xn.y * qr) : make_float2(1.0f, 0.0f);
+                if constexpr (ILLUM) {
+                    phase_out[natural(t)] = atan2f(e.y, e.x);
+                    v[t] = make_float2(pil[t] * e.x, pil[t] * e.y);
+                } else {
+                    v[t] = e;
+                }
             } else {
                 a.Z[tiled(t)] = xn;
                 v[t] = xn;
@@ -320,7 +351,7 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
         }
     }
 
-    if constexpr ((MODE & ROUT_PHASE) != 0) {
+    if constexpr ((MODE & ROUT_PHASE) != 0 && !ILLUM) {
 #pragma unroll
         for (int t = 0; t < P; ++t) phase_out[natural(t)] = atan2f(v[t].y, v[t].x);
     }
@@ -351,7 +382,7 @@ __global__ void __launch_bounds__(kC * LineShape<H>::T)
 k_col(ColParams a) {
     constexpr int NT = kC * LineShape<H>::T;
     __shared__ float2 lds[LdsPlan<H, kC>::FLOATS2];
-    __shared__ double red[(NT + 63) / 64];
+    __shared__ double red[red_slots(NT)];
     col_body<H, LineShape<H>::P, kC, MODE>(a, blockIdx.x, a.part + blockIdx.x, lds, red);
 }
 
@@ -360,7 +391,7 @@ __global__ void __launch_bounds__(kGR * LineShape<W>::T)
 k_row(RowParams a) {
     constexpr int NT = kGR * LineShape<W>::T;
     __shared__ float2 lds[LdsPlan<W, kGR>::FLOATS2];
-    __shared__ double red[(NT + 63) / 64];
+    __shared__ double red[red_slots(NT)];
     const float* pin = nullptr;
     float* pout = nullptr;
     if constexpr ((MODE & RIN_PHASE) != 0) pin = a.io->phase_in;
@@ -376,7 +407,7 @@ __global__ void __launch_bounds__(kGR * LineShape<W>::T)
 k_row_adj(AdjParams p) {
     constexpr int NT = kGR * LineShape<W>::T;
     __shared__ float2 lds[LdsPlan<W, kGR>::FLOATS2];
-    __shared__ double red[(NT + 63) / 64];
+    __shared__ double red[red_slots(NT)];
     const size_t n = (size_t)p.H * W;
     const size_t b = blockIdx.y;
     RowParams a{};
@@ -397,7 +428,7 @@ __global__ void __launch_bounds__(kC * LineShape<H>::T)
 k_col_adj(AdjParams p) {
     constexpr int NT = kC * LineShape<H>::T;
     __shared__ float2 lds[LdsPlan<H, kC>::FLOATS2];
-    __shared__ double red[(NT + 63) / 64];
+    __shared__ double red[red_slots(NT)];
     const size_t n = (size_t)H * p.W;
     const size_t b = blockIdx.y;
     ColParams a{};

@@ -46,26 +46,26 @@ hipError_t launch(void (*kern)(Params), int grid, int block, hipStream_t s, hipE
 
 }  // namespace
 
+// Row modes of the solves, each also built with R_ILLUM (illumination p).
+#define PM_ROW_SOLVE_MODES(X) \
+    X(ROW_INIT) X(ROW_ITER) X(ROW_LAST) X(ROW_LAST_FWD) X(ROW_GAP) X(ROW_ITER_NE) X(ROW_LAST_NE) \
+    X(ROW_INIT_Z) X(ROW_RAAR) X(ROW_RAAR_LAST) X(ROW_RAAR_LAST_FWD)
+#define PM_ROW_CASE(M)                                                                         \
+    case M: return launch(k_row<PM_L, M>, grid, block, s, ev0, ev1, p);                        \
+    case M | R_ILLUM: return launch(k_row<PM_L, M | R_ILLUM>, grid, block, s, ev0, ev1, p);
+
 hipError_t PM_CAT(launch_row_, PM_L)(int mode, const RowParams& p, int grid, hipStream_t s,
                                      hipEvent_t ev0, hipEvent_t ev1) {
     const int block = kGR * LineShape<PM_L>::T;
     switch (mode) {
-        case ROW_INIT: return launch(k_row<PM_L, ROW_INIT>, grid, block, s, ev0, ev1, p);
-        case ROW_ITER: return launch(k_row<PM_L, ROW_ITER>, grid, block, s, ev0, ev1, p);
-        case ROW_LAST: return launch(k_row<PM_L, ROW_LAST>, grid, block, s, ev0, ev1, p);
-        case ROW_LAST_FWD: return launch(k_row<PM_L, ROW_LAST_FWD>, grid, block, s, ev0, ev1, p);
-        case ROW_GAP: return launch(k_row<PM_L, ROW_GAP>, grid, block, s, ev0, ev1, p);
+        PM_ROW_SOLVE_MODES(PM_ROW_CASE)
         case ROW_FFT_FWD: return launch(k_row<PM_L, ROW_FFT_FWD>, grid, block, s, ev0, ev1, p);
         case ROW_FFT_INV: return launch(k_row<PM_L, ROW_FFT_INV>, grid, block, s, ev0, ev1, p);
-        case ROW_ITER_NE: return launch(k_row<PM_L, ROW_ITER_NE>, grid, block, s, ev0, ev1, p);
-        case ROW_LAST_NE: return launch(k_row<PM_L, ROW_LAST_NE>, grid, block, s, ev0, ev1, p);
-        case ROW_INIT_Z: return launch(k_row<PM_L, ROW_INIT_Z>, grid, block, s, ev0, ev1, p);
-        case ROW_RAAR: return launch(k_row<PM_L, ROW_RAAR>, grid, block, s, ev0, ev1, p);
-        case ROW_RAAR_LAST: return launch(k_row<PM_L, ROW_RAAR_LAST>, grid, block, s, ev0, ev1, p);
-        case ROW_RAAR_LAST_FWD: return launch(k_row<PM_L, ROW_RAAR_LAST_FWD>, grid, block, s, ev0, ev1, p);
         default: return hipErrorInvalidValue;
     }
 }
+#undef PM_ROW_CASE
+#undef PM_ROW_SOLVE_MODES
 
 hipError_t PM_CAT(launch_col_, PM_L)(int mode, const ColParams& p, int grid, hipStream_t s,
                                      hipEvent_t ev0, hipEvent_t ev1) {

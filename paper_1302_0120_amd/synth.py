@@ -1,4 +1,5 @@
-"""Seeded synthetic inputs: spot-pattern targets and random initial phases.
+"""Seeded synthetic inputs: spot-pattern targets and random initial phases,
+plus a Siemens-star target and a Gaussian illumination profile.
 
 The paper benchmarks on optical stimulation patterns (OSPs) made of bright
 spots on a dark background (Sec. IV, first paragraph) and notes random phases
@@ -35,9 +36,12 @@ __all__ = [
     "SPOTS_64",
     "SPOTS_512",
     "SPOTS_1024",
+    "SPOTS_800x600",
     "spot_problem",
     "batched_problems",
     "intensity_problems",
+    "siemens_star",
+    "gaussian_illumination",
 ]
 
 
@@ -101,6 +105,9 @@ SPOTS_64 = SpotSpec(64, 64, 5, 1.5, 1.0, 1.0, 100, 1)
 SPOTS_512 = SpotSpec(512, 512, 20, 2.0, 1.0, 1.0, 50, 2)
 # 1024 x 1024, 100 spots of sigma 2 px with amplitudes in [0.5, 1], 100 iterations.
 SPOTS_1024 = SpotSpec(1024, 1024, 100, 2.0, 0.5, 1.0, 100, 3)
+# The SLM panel of the paper's timing (800 x 600 pixels: 600 rows of 800),
+# 25 iterations; 20 spots of sigma 2 px with amplitudes in [0.5, 1].
+SPOTS_800x600 = SpotSpec(600, 800, 20, 2.0, 0.5, 1.0, 25, 6)
 
 
 def spot_problem(spec: SpotSpec, seed: int | None = None):
@@ -144,3 +151,42 @@ def intensity_problems(batch: int = 16, size: int = 512, n_spots: int = 50,
         ts.append((m.astype(np.float64) ** 2).astype(np.float32))
         ps.append(uniform_phase(size, size, rng))
     return np.stack(ts), np.stack(ps)
+
+
+def siemens_star(height: int, width: int, n_spokes: int = 36, r_outer: float = 0.35,
+                 r_inner: float = 0.03) -> np.ndarray:
+    """Binary Siemens-star target amplitude (fp32, natural DFT order), the
+    resolution pattern of the paper's second experiment (Sec. IV, Fig. 4).
+
+    In display coordinates (centre at ``(height // 2, width // 2)``) a pixel
+    is bright (1) when its polar angle t satisfies ``sin(n_spokes t) >= 0``
+    and its radius lies in ``[r_inner, r_outer] * min(height, width)``, else
+    dark (0).  Deterministic: no random draws.
+    """
+    if n_spokes < 1:
+        raise ValueError("need at least one spoke")
+    n = float(min(height, width))
+    yy = np.arange(height, dtype=np.float64)[:, None] - height // 2
+    xx = np.arange(width, dtype=np.float64)[None, :] - width // 2
+    r = np.hypot(yy, xx)
+    t = np.arctan2(yy, xx)
+    lit = (np.sin(n_spokes * t) >= 0.0) & (r >= r_inner * n) & (r <= r_outer * n)
+    return np.ascontiguousarray(np.fft.ifftshift(lit.astype(np.float32)))
+
+
+def gaussian_illumination(height: int, width: int, waist: float = 0.5,
+                          aperture: float | None = None) -> np.ndarray:
+    """Illumination amplitude p on the SLM (Eq. 1) of a Gaussian laser beam
+    centred on the panel: ``p = exp(-r^2 / (waist * min(height, width))^2)``
+    with r measured from ``(height / 2, width / 2)`` in pixels.  With
+    ``aperture`` set, p = 0 beyond radius ``aperture * min(height, width)``
+    (a circular stop).  fp32, SLM pixel order (no shift).
+    """
+    n = float(min(height, width))
+    yy = np.arange(height, dtype=np.float64)[:, None] + 0.5 - height / 2.0
+    xx = np.arange(width, dtype=np.float64)[None, :] + 0.5 - width / 2.0
+    r2 = yy * yy + xx * xx
+    p = np.exp(-r2 / (waist * n) ** 2)
+    if aperture is not None:
+        p[r2 > (aperture * n) ** 2] = 0.0
+    return np.ascontiguousarray(p.astype(np.float32))

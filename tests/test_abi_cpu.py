@@ -56,10 +56,12 @@ def test_host_side_argument_errors(lib):
     lib.phasemask_last_error.restype = ctypes.c_char_p
     h = ctypes.c_void_p(1234)
     assert lib.phasemask_create(None, 64, 64, 0, None) == -1
-    for hh, ww in [(48, 64), (64, 8), (8192, 64), (64, 0), (-64, 64), (64, 4097)]:
+    for hh, ww in [(48, 64), (64, 8), (8192, 64), (64, 0), (-64, 64), (64, 4097), (700, 800),
+                   (600, 1000), (720, 1280), (1080, 1000)]:
         assert lib.phasemask_create(ctypes.byref(h), hh, ww, 0, None) == -2
         assert h.value is None
-        assert b"power" in lib.phasemask_last_error()
+        msg = lib.phasemask_last_error()
+        assert b"power" in msg and b"600" in msg and b"800" in msg and b"1920" in msg
     assert lib.phasemask_create(ctypes.byref(h), 64, 64, 0x80, None) == -1
     assert lib.phasemask_destroy(None) == -1
     lib.phasemask_solve.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,

@@ -1,0 +1,150 @@
+"""GPU parity of the non-power-of-two transform lengths (600, 800, 1080 and
+1920: the mixed-radix plans 6*10*10, 8*10*10, 30*6*6 and 12*10*4*4) against
+the FP64 oracle, alone and mixed with power-of-two lengths on the other
+axis.  Tolerances are the
+power-of-two ones (see test_gpu_parity): each output of a 3-stage
+mixed-radix line takes fewer roundings than a 4-stage radix-16 line."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import gs
+from paper_1302_0120_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pmb():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1302_0120_amd import binding
+    return binding
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+SHAPES = [(600, 800), (800, 600), (600, 600), (800, 800), (600, 16), (16, 800), (64, 600),
+          (800, 1024), (4096, 600), (600, 4096), (1080, 1920), (1920, 1080), (1080, 64),
+          (32, 1920), (1080, 600)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fft2_mixed_radix(pmb, shape):
+    h, w = shape
+    print(f"fft2 {shape}", flush=True)
+    rng = np.random.default_rng(h * 11 + w)
+    x = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+    plan = pmb.PhaseMask(h, w)
+    xd = _dev(x)
+    fwd = plan.fft2(xd).cpu().numpy().astype(np.complex128)
+    inv = plan.fft2(xd, inverse=True).cpu().numpy().astype(np.complex128)
+    n = h * w
+    assert _rel_l2(fwd, gs.F(x) * math.sqrt(n)) <= 5e-6
+    assert _rel_l2(inv, gs.F_inv(x) * math.sqrt(n)) <= 5e-6
+
+
+def test_fft2_single_frequencies(pmb):
+    """A plane wave of frequency (a, b) transforms to N at (a, b) alone: one
+    check per radix-3, radix-5 and radix-2 factor of the index."""
+    h, w = 600, 800
+    ys = np.arange(h)[:, None]
+    xs = np.arange(w)[None, :]
+    plan = pmb.PhaseMask(h, w)
+    for a, b in [(0, 1), (1, 0), (3, 5), (200, 160), (125, 799), (599, 400)]:
+        x = np.exp(2j * math.pi * (a * ys / h + b * xs / w)).astype(np.complex64)
+        y = plan.fft2(_dev(x)).cpu().numpy().astype(np.complex128)
+        want = np.zeros((h, w))
+        want[a, b] = h * w
+        assert np.max(np.abs(y - want)) <= 2e-5 * h * w, (a, b)
+
+
+def test_constant_field_exact_zeros_mixed_radix(pmb):
+    """Radix-3, -5, -6 and -10 butterflies also give exact zeros off DC for
+    equal inputs (the zero tie-break of Eq. 5 relies on it)."""
+    for h, w in [(600, 800), (800, 600), (600, 64), (1080, 1920)]:
+        c = np.complex64(np.exp(0.7j))
+        x = torch.full((h, w), complex(c), dtype=torch.complex64, device="cuda")
+        y = pmb.PhaseMask(h, w).fft2(x).cpu().numpy()
+        assert abs(y[0, 0] - c * h * w) <= 1e-6 * h * w
+        y[0, 0] = 0
+        assert np.count_nonzero(y) == 0
+
+
+@pytest.mark.parametrize("shape", [(600, 800), (800, 600), (64, 800), (600, 128), (1080, 1920),
+                                   (1920, 256)])
+def test_one_iteration_mixed_radix(pmb, shape):
+    h, w = shape
+    print(f"one iteration {shape}", flush=True)
+    rng = np.random.default_rng(200 + h + w)
+    m = synth.spot_amplitude(h, w, 12, 2.0, 0.5, 1.0, rng)
+    phi0 = synth.uniform_phase(h, w, rng)
+    plan = pmb.PhaseMask(h, w)
+    phi1, hist = plan.solve(_dev(m), _dev(phi0), 1)
+    ref = gs.gs_solve(m, phi0, 1)
+    assert _rel_l2(np.exp(1j * phi1.cpu().numpy().astype(np.float64)), ref["u"]) <= 1e-5
+    hg = hist.cpu().numpy()
+    assert np.max(np.abs(hg - ref["history"]) / ref["history"]) <= 1e-5
+
+
+def test_paper_slm_workload(pmb):
+    """The 800 x 600 panel of the paper's timing, 25 iterations in one graph
+    launch: the final Fourier error within 1e-3 of the oracle, the first
+    entries within 1e-5, and the chain monotone."""
+    spec = synth.SPOTS_800x600
+    m, phi0 = synth.spot_problem(spec)
+    plan = pmb.PhaseMask(spec.height, spec.width)
+    phi, hist = plan.solve(_dev(m), _dev(phi0), spec.n_iter)
+    hg = hist.cpu().numpy()
+    hr = gs.gs_solve(m, phi0, spec.n_iter)["history"]
+    assert abs(hg[-1] - hr[-1]) / hr[-1] <= 1e-3, (hg[-1], hr[-1])
+    assert np.max(np.abs(hg[:3] - hr[:3]) / hr[:3]) <= 1e-5
+    assert np.all(np.diff(hg) <= 1e-6 * hg[:-1])
+    ef_out = plan.error(_dev(m), phi)[0].item()
+    assert abs(hg[-1] - ef_out) / ef_out <= 1e-5
+
+
+def test_paper_slm_other_entry_points(pmb):
+    """RAAR (one iteration exact), the paper's initial mask, the physical
+    error and the intensity-loss adjoint on the 800 x 600 panel."""
+    h, w = 600, 800
+    rng = np.random.default_rng(8600)
+    m = synth.spot_amplitude(h, w, 25, 2.0, 0.5, 1.0, rng)
+    phi0 = synth.uniform_phase(h, w, rng)
+    plan = pmb.PhaseMask(h, w)
+    md, pd = _dev(m), _dev(phi0)
+
+    ph, hist = plan.solve_raar(md, pd, 1, 0.8)
+    ref = gs.raar_solve(m, phi0, 1, 0.8)
+    assert _rel_l2(np.exp(1j * ph.cpu().numpy().astype(np.float64)), ref["u"]) <= 1e-5
+    assert np.max(np.abs(hist.cpu().numpy() - ref["history"]) / ref["history"]) <= 1e-5
+
+    pi = plan.initial_phase(md).cpu().numpy().astype(np.float64)
+    pref = gs.paper_initial_phase(m)
+    it = m.astype(np.float64) ** 2
+    wref = np.abs(gs.F_inv((it / it.max() > 3e-4).astype(np.float64)))
+    err = np.linalg.norm((np.exp(1j * pi) - np.exp(1j * pref)) * wref) / np.linalg.norm(wref)
+    assert err <= 1e-5, err
+
+    e = plan.physical_error(md, pd).cpu().numpy()
+    eref = gs.physical_error(m, np.exp(1j * phi0.astype(np.float64)))
+    for k in range(2):
+        assert abs(e[k] - eref[k]) <= 1e-4 * max(eref[k], 1e-6), (k, e[k], eref[k])
+
+    inten = (m.astype(np.float64) ** 2)
+    inten = (inten * (h * w / inten.sum())).astype(np.float32)
+    loss, saved = plan.intensity_loss_fwd(pd, _dev(inten))
+    g = plan.intensity_loss_bwd(pd, saved, torch.ones(1, dtype=torch.float64, device="cuda"))
+    lref = gs.intensity_loss(phi0, inten)
+    gref = gs.intensity_loss_grad(phi0, inten)
+    assert abs(loss.item() - lref) / lref <= 1e-5
+    assert _rel_l2(g.cpu().numpy().astype(np.float64), gref) <= 1e-4

@@ -98,6 +98,21 @@ def test_PS_is_nearest_point_brute_force():
     assert d0 < d.min()
 
 
+def test_PS_with_illumination_is_nearest_point_brute_force():
+    """With an illumination p (Eq. 1), S = {|z| = p}: no random point of S
+    is closer to u than P_S(u, p); a pixel with p = 0 maps to 0."""
+    rng = np.random.default_rng(12)
+    u = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    p = rng.uniform(0.2, 2.0, (4, 4))
+    p[2, 1] = 0.0
+    v = gs.P_S(u, p)
+    assert v[2, 1] == 0.0
+    d0 = np.linalg.norm(u - v)
+    thetas = rng.uniform(0, 2 * math.pi, (10000, 4, 4))
+    d = np.linalg.norm((u[None] - p[None] * np.exp(1j * thetas)).reshape(10000, -1), axis=1)
+    assert d0 < d.min()
+
+
 def test_PS_zero_tie_break():
     u = np.zeros((4, 4), complex)
     u[1, 2] = 3 - 4j

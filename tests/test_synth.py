@@ -42,3 +42,32 @@ def test_batched_problem_sizes():
         assert m.dtype == np.float32
     again = synth.batched_problems(count=8, sizes=(16, 32), max_spots=4)
     assert all(np.array_equal(a[0], b[0]) for a, b in zip(probs, again))
+
+
+def test_siemens_star_structure():
+    h, w = 128, 256
+    m = synth.siemens_star(h, w, n_spokes=12)
+    assert m.dtype == np.float32 and m.shape == (h, w)
+    assert set(np.unique(m)) <= {0.0, 1.0}
+    d = np.fft.fftshift(m)  # display coordinates
+    # the centre disc and the frame beyond r_outer are dark
+    assert d[h // 2, w // 2] == 0.0 and d[0, 0] == 0.0
+    # about half of the annulus is lit (12 bright sectors out of 24)
+    yy = np.arange(h)[:, None] - h // 2
+    xx = np.arange(w)[None, :] - w // 2
+    r = np.hypot(yy, xx)
+    ann = (r >= 0.03 * h) & (r <= 0.35 * h)
+    assert abs(d[ann].mean() - 0.5) < 0.05
+    # bright on the +x axis just past r_inner (angle 0: sin 0 = 0 >= 0)
+    assert d[h // 2, w // 2 + 20] == 1.0
+
+
+def test_gaussian_illumination_profile():
+    h, w = 64, 96
+    p = synth.gaussian_illumination(h, w, waist=0.4)
+    assert p.dtype == np.float32 and p.shape == (h, w)
+    assert np.all(p > 0) and p.max() <= 1.0
+    # symmetric about the panel centre (between pixels)
+    assert np.array_equal(p, p[::-1, :]) and np.array_equal(p, p[:, ::-1])
+    pa = synth.gaussian_illumination(h, w, waist=0.4, aperture=0.3)
+    assert np.count_nonzero(pa == 0) > 0 and np.all(pa[pa > 0] == p[pa > 0])
