@@ -24,8 +24,10 @@ ARCH = "gfx950"
 BATCH_SCHEDULES = 2  # = kBatchSchedules in csrc/pm_common.h
 
 # -packed-fp32-ops: keep hipcc from emitting packed FP32 instructions.
+# -ffp-contract=off: the kernels spell out every fused multiply-add, so one
+# formula rounds the same way in every instantiation.
 HIPFLAGS = [
-    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
     f"-I{INCLUDE}", f"-I{CSRC}",

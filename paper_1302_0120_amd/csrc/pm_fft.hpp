@@ -31,9 +31,17 @@ namespace pm {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+// Products are written with explicit fused multiply-adds and the library
+// is compiled without automatic contraction, so every instantiation of a
+// formula (any line count, either pass, one-mask or batched) rounds the
+// same way and gives bitwise the same result.
+//
+// a * (c + i s): (a.x c - a.y s, a.x s + a.y c), one rounding per product
+// term pair.
+__device__ __forceinline__ float2 cmul_cs(float2 a, float c, float s) {
+    return make_float2(fmaf(a.x, c, -(a.y * s)), fmaf(a.x, s, a.y * c));
 }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) { return cmul_cs(a, b.x, b.y); }
 // a * (-i) for the forward transform, a * (+i) for the inverse.
 template <bool INV>
 __device__ __forceinline__ float2 rot90(float2 a) {
@@ -67,7 +75,7 @@ __device__ __forceinline__ float2 tw16(float2 a) {
     } else {
         const float c = kCos16[e];
         const float s = INV ? kSin16[e] : -kSin16[e];
-        return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+        return cmul_cs(a, c, s);
     }
 }
 
@@ -92,7 +100,7 @@ __device__ __forceinline__ void dft3(float2& x0, float2& x1, float2& x2) {
     constexpr float S3 = 0.86602540378443865f;  // sin(2 pi / 3)
     const float2 s = cadd(x1, x2);
     const float2 d = csub(x1, x2);
-    const float2 t = make_float2(x0.x - 0.5f * s.x, x0.y - 0.5f * s.y);
+    const float2 t = make_float2(fmaf(-0.5f, s.x, x0.x), fmaf(-0.5f, s.y, x0.y));
     const float2 r = rot90<INV>(make_float2(S3 * d.x, S3 * d.y));  // -+i (sqrt3/2) d
     x0 = cadd(x0, s);
     x1 = cadd(t, r);
@@ -114,11 +122,11 @@ __device__ __forceinline__ void dft5(float2& x0, float2& x1, float2& x2, float2&
     const float2 s1 = cadd(x1, x4), d1 = csub(x1, x4);
     const float2 s2 = cadd(x2, x3), d2 = csub(x2, x3);
     const float2 t1 = cadd(s1, s2), t2 = csub(s1, s2);
-    const float2 a = make_float2(x0.x - 0.25f * t1.x, x0.y - 0.25f * t1.y);
+    const float2 a = make_float2(fmaf(-0.25f, t1.x, x0.x), fmaf(-0.25f, t1.y, x0.y));
     const float2 m2 = make_float2(Q5 * t2.x, Q5 * t2.y);
     const float2 a1 = cadd(a, m2), a2 = csub(a, m2);
-    const float2 b1 = rot90<INV>(make_float2(S1 * d1.x + S2 * d2.x, S1 * d1.y + S2 * d2.y));
-    const float2 b2 = rot90<INV>(make_float2(S2 * d1.x - S1 * d2.x, S2 * d1.y - S1 * d2.y));
+    const float2 b1 = rot90<INV>(make_float2(fmaf(S1, d1.x, S2 * d2.x), fmaf(S1, d1.y, S2 * d2.y)));
+    const float2 b2 = rot90<INV>(make_float2(fmaf(S2, d1.x, -(S1 * d2.x)), fmaf(S2, d1.y, -(S1 * d2.y))));
     x0 = cadd(x0, t1);
     x1 = cadd(a1, b1);
     x4 = csub(a1, b1);
@@ -190,8 +198,7 @@ __device__ __forceinline__ void dft_ct(float2 (&x)[R1 * R2]) {
             } else {
                 const float c = tt.c[e];
                 const float sn = INV ? tt.s[e] : -tt.s[e];
-                const float2 v = col[k1];
-                y[n2 * R1 + k1] = make_float2(v.x * c - v.y * sn, v.x * sn + v.y * c);
+                y[n2 * R1 + k1] = cmul_cs(col[k1], c, sn);
             }
         }
     }

@@ -153,14 +153,14 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
         for (int t = 0; t < P; ++t) {
             const float m = mt[t];
             const float2 U = v[t];
-            const float a2 = U.x * U.x + U.y * U.y;
+            const float a2 = fmaf(U.x, U.x, U.y * U.y);
             // |U|^2 >= FLT_MIN excludes denormals, so the raw hardware
             // reciprocal square root applies; below it the tie-break of
             // Eq. 5 takes phase 0 and |U| counts as 0.
             const bool nz = a2 >= FLT_MIN;
             const float r = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
             if constexpr (ERR) {
-                const double d = (double)(a2 * r) * a.invN - (double)m;
+                const double d = fma((double)(a2 * r), a.invN, -(double)m);
                 acc = fma(d, d, acc);
             }
             if constexpr ((MODE & C_PROJ) != 0) {
@@ -179,7 +179,7 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
         float mx = 0.0f;
 #pragma unroll
         for (int t = 0; t < P; ++t) {
-            const float q = (v[t].x * v[t].x + v[t].y * v[t].y) * (float)a.invN;
+            const float q = fmaf(v[t].x, v[t].x, v[t].y * v[t].y) * (float)a.invN;
             a.pw[sb + (size_t)(j + T * t) * kC + c] = q;
             mx = fmaxf(mx, q);
         }
@@ -197,7 +197,7 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
         for (int t = 0; t < P; ++t) {
             const float I = a.inten[(size_t)(j + T * t) * a.W + s * kC + c];
             const float2 U = v[t];
-            const float r = (U.x * U.x + U.y * U.y) * (float)a.invN - I;
+            const float r = fmaf(fmaf(U.x, U.x, U.y * U.y), (float)a.invN, -I);
             acc = fma((double)r, (double)r, acc);
             v[t] = make_float2(U.x * r, U.y * r);
         }
@@ -292,7 +292,7 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
 #pragma unroll
         for (int t = 0; t < P; ++t) {
             const float2 w = v[t];
-            const float a2 = w.x * w.x + w.y * w.y;
+            const float a2 = fmaf(w.x, w.x, w.y * w.y);
             // Tie-break of Eq. 4a below FLT_MIN (phase 0), as in the column pass.
             const bool nz = a2 >= FLT_MIN;
             const float r = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
@@ -325,16 +325,16 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
         for (int t = 0; t < P; ++t) {
             const float2 w = v[t];
             const float2 x = zx[t];
-            const float2 y = make_float2(2.0f * w.x - x.x, 2.0f * w.y - x.y);
-            const float a2 = y.x * y.x + y.y * y.y;
+            const float2 y = make_float2(fmaf(2.0f, w.x, -x.x), fmaf(2.0f, w.y, -x.y));
+            const float a2 = fmaf(y.x, y.x, y.y * y.y);
             const bool nz = a2 >= FLT_MIN;
             const float r = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
             float2 ps = nz ? make_float2(y.x * r, y.y * r) : make_float2(1.0f, 0.0f);
             if constexpr (ILLUM) ps = make_float2(pil[t] * ps.x, pil[t] * ps.y);
-            const float2 xn = make_float2(b * ps.x + b * x.x + c * w.x, b * ps.y + b * x.y + c * w.y);
+            const float2 xn = make_float2(fmaf(c, w.x, fmaf(b, x.x, b * ps.x)), fmaf(c, w.y, fmaf(b, x.y, b * ps.y)));
             if constexpr ((MODE & ROUT_PHASE) != 0) {
                 // last pass: the mask is the shadow P_S x^n
-                const float q2 = xn.x * xn.x + xn.y * xn.y;
+                const float q2 = fmaf(xn.x, xn.x, xn.y * xn.y);
                 const bool qz = q2 >= FLT_MIN;
                 const float qr = qz ? __builtin_amdgcn_rsqf(q2) : 0.0f;
                 const float2 e = qz ? make_float2(xn.x * qr, xn.y * qr) : make_float2(1.0f, 0.0f);
@@ -366,7 +366,7 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
         for (int t = 0; t < P; ++t) {
             float sn, cs;
             sincosf(phase_in[natural(t)], &sn, &cs);
-            phase_out[natural(t)] = a.gscale * (cs * v[t].y - sn * v[t].x);
+            phase_out[natural(t)] = a.gscale * fmaf(cs, v[t].y, -(sn * v[t].x));
         }
     }
     if constexpr ((MODE & R_FWD) != 0) {

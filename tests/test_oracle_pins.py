@@ -425,3 +425,24 @@ def test_paper_initial_phase():
     want = np.exp(2j * np.pi * (a * ys / h + b * xs / w))
     assert np.max(np.abs(np.exp(1j * phi) - want)) <= 1e-12
     assert np.max(np.abs(gs.paper_initial_phase(np.ones((h, w))))) == 0.0
+
+
+def test_one_iteration_sensitivity_rule():
+    """The tolerance rule of the one-iteration parity tests: on the small
+    spot cases the oracle's own change under an FP32-level perturbation of
+    phi^0 is far below the stated 1e-5 (so the literal bound applies), and
+    a perturbation of zero changes nothing."""
+    import parity_util
+    from paper_1302_0120_amd import synth
+    for h, w in [(16, 16), (64, 64), (32, 128)]:
+        rng = np.random.default_rng(100 + h + w)
+        m = synth.spot_amplitude(h, w, 8, 2.0, 0.5, 1.0, rng)
+        phi0 = synth.uniform_phase(h, w, rng)
+        tol, s = parity_util.one_iteration_tolerance(m, phi0)
+        assert s < 1e-6 and tol == 1e-5
+    old = parity_util.EPS32
+    try:
+        parity_util.EPS32 = 0.0
+        assert parity_util.oracle_sensitivity(m, phi0) == 0.0
+    finally:
+        parity_util.EPS32 = old
