@@ -447,12 +447,16 @@ __host__ __device__ constexpr int fft_parity_after() {
     return (PAR + exchanges_from(L, P, 1)) & 1;
 }
 
-// Points per thread for a line of L points.
+// Points per thread for a line of L points.  At 1024, P = 8 (radix 8-8-8-2,
+// 128 threads per line) measured faster than P = 16 (16-16-4, 64 threads):
+// one more LDS exchange, but two waves per SIMD instead of one to hide the
+// load latency behind (the one-mask 1024^2 passes hold one line per SIMD).
 __host__ __device__ constexpr int points_per_thread(int L) {
     return L == 800 ? 40
          : L == 600 ? 30
          : L == 1080 ? 30
          : L == 1920 ? 60
+         : L == 1024 ? 8
          : (L >= 256 ? 16 : (L >= 32 ? 8 : 4));
 }
 

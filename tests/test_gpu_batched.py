@@ -40,7 +40,11 @@ def _problems(shapes, seed0=300):
 
 
 def test_batched_equals_one_mask_solves(pmb, monkeypatch):
-    """Schedule 0 runs the one-mask radix schedules, so phases are bitwise equal."""
+    """Schedule 0 runs the one-mask radix schedules below length 1024, so
+    phases of masks without a side of 1024 are bitwise equal; at 1024 the
+    one-mask plan uses 8 points per thread and the batched one 16, so those
+    masks agree to FP32 rounding (field relative L2 <= 1e-4 after 6
+    iterations, final error 1e-5 relative)."""
     probs = _problems(SHAPES)
     n_iter = 6
     print(f"batched vs one-mask, {len(SHAPES)} masks, n={n_iter}", flush=True)
@@ -54,9 +58,15 @@ def test_batched_equals_one_mask_solves(pmb, monkeypatch):
     for i, (h, w) in enumerate(SHAPES):
         single = pmb.PhaseMask(h, w)
         ph, hist = single.solve(targets[i], phases[i], n_iter)
-        assert torch.equal(outs[i], ph), (i, (h, w))
         ef = hist[-1].item()
-        assert abs(err[i] - ef) <= 1e-12 * ef, (i, err[i], ef)
+        if 1024 not in (h, w):
+            assert torch.equal(outs[i], ph), (i, (h, w))
+            assert abs(err[i] - ef) <= 1e-12 * ef, (i, err[i], ef)
+        else:
+            a = np.exp(1j * outs[i].cpu().numpy().astype(np.float64))
+            b = np.exp(1j * ph.cpu().numpy().astype(np.float64))
+            assert np.linalg.norm(a - b) / np.linalg.norm(b) <= 1e-4, (i, (h, w))
+            assert abs(err[i] - ef) <= 1e-5 * ef, (i, err[i], ef)
 
 
 def test_batched_one_iteration_and_final_error_vs_oracle(pmb):
