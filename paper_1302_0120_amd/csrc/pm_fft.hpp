@@ -16,8 +16,8 @@
 //     thread's own slots, so a line needs (#stages - 1) LDS exchanges and the
 //     first read / last write can go straight to or from global memory.
 //   * Radix sequence: P, P, ..., then the remaining factor (each divides P)
-//     for powers of two; fixed mixed-radix sequences (radices 4, 6, 8, 10,
-//     12, 30) for the non-power-of-two lengths 600, 800, 1080 and 1920,
+//     for powers of two; fixed mixed-radix sequences (radices 4, 6, 10, 12,
+//     20, 30) for the non-power-of-two lengths 600, 800, 1080 and 1920,
 //     whose butterfly index b and sub-length NS are then not powers of two
 //     (b mod NS is a true modulo).
 //   * Twiddles come from a table tw[i] = exp(-2 pi i i / L) computed on the
@@ -79,8 +79,8 @@ __device__ __forceinline__ float2 tw16(float2 a) {
     }
 }
 
-// In-register DFTs of R = 2, 3, 4, 5, 6, 8, 10, 12, 16, 30 points, natural
-// order in and out.
+// In-register DFTs of R = 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 30 points,
+// natural order in and out.
 // Each first forms sums and differences of input pairs, so equal inputs give
 // exact zeros off the zero frequency (the constant-field tie-break case).
 template <bool INV>
@@ -225,6 +225,8 @@ __device__ __forceinline__ void dft(float2 (&x)[R]) {
         dft_ct<5, 2, INV>(x);
     } else if constexpr (R == 12) {
         dft_ct<3, 4, INV>(x);
+    } else if constexpr (R == 20) {
+        dft_ct<4, 5, INV>(x);
     } else if constexpr (R == 30) {
         dft_ct<10, 3, INV>(x);
     } else if constexpr (R == 2) {
@@ -276,7 +278,7 @@ __device__ __forceinline__ void dft(float2 (&x)[R]) {
         for (int k = 0; k < 16; ++k) x[k] = y[k];
     } else {
         static_assert(R == 2 || R == 3 || R == 4 || R == 5 || R == 6 || R == 8 || R == 10 || R == 12 ||
-                          R == 16 || R == 30,
+                          R == 16 || R == 20 || R == 30,
                       "unsupported radix");
     }
 }
@@ -294,10 +296,11 @@ __host__ __device__ constexpr int lds_line_len(int L) { return L + L / 16 + PM_L
 // Radix of the stage that starts at sub-transform length NS.  Powers of two
 // take P, P, ..., remainder.  The non-power-of-two lengths of common SLM
 // panels (800 x 600, 1920 x 1080) take fixed mixed-radix sequences whose
-// radices divide P: 800 = 8*10*10 (P = 40), 600 = 6*10*10 (P = 30),
-// 1080 = 30*6*6 (P = 30), 1920 = 12*10*4*4 (P = 60).
+// radices divide P: 800 = 20*10*4 (P = 20), 600 = 6*10*10 (P = 30),
+// 1080 = 30*6*6 (P = 30), 1920 = 12*10*4*4 (P = 60).  The largest radix
+// goes first, where no inter-stage twiddles are needed.
 __host__ __device__ constexpr int stage_radix(int L, int P, int NS) {
-    if (L == 800) return NS == 1 ? 8 : 10;
+    if (L == 800) return NS == 1 ? 20 : (NS == 20 ? 10 : 4);
     if (L == 600) return NS == 1 ? 6 : 10;
     if (L == 1080) return NS == 1 ? 30 : 6;
     if (L == 1920) return NS == 1 ? 12 : (NS == 12 ? 10 : 4);
@@ -315,10 +318,10 @@ __host__ __device__ constexpr int twiddles_from(int L, int P, int NS) {
 // The thread's twiddle factors for a whole line transform, loaded once from
 // the table before any barrier (so their latency overlaps the data loads);
 // the inverse transform uses their conjugates.  Plans that need more than
-// kMaxTwiddleRegs of them (the long mixed-radix plans, 54 and 72 factors)
+// kMaxTwiddleRegs of them (the long mixed-radix plans, 50 to 154 factors)
 // would not fit the register file next to their data, so their stages read
 // the factors from the table (an L1-resident few KB) instead.
-constexpr int kMaxTwiddleRegs = 32;
+constexpr int kMaxTwiddleRegs = 36;
 
 template <int L, int P>
 struct LineTwiddles {
@@ -452,7 +455,7 @@ __host__ __device__ constexpr int fft_parity_after() {
 // one more LDS exchange, but two waves per SIMD instead of one to hide the
 // load latency behind (the one-mask 1024^2 passes hold one line per SIMD).
 __host__ __device__ constexpr int points_per_thread(int L) {
-    return L == 800 ? 40
+    return L == 800 ? 20
          : L == 600 ? 30
          : L == 1080 ? 30
          : L == 1920 ? 60

@@ -1,5 +1,5 @@
 """GPU parity of the non-power-of-two transform lengths (600, 800, 1080 and
-1920: the mixed-radix plans 6*10*10, 8*10*10, 30*6*6 and 12*10*4*4) against
+1920: the mixed-radix plans 6*10*10, 20*10*4, 30*6*6 and 12*10*4*4) against
 the FP64 oracle, alone and mixed with power-of-two lengths on the other
 axis.  Tolerances are the
 power-of-two ones (see test_gpu_parity): each output of a 3-stage
