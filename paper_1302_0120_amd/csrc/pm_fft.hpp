@@ -318,10 +318,14 @@ __host__ __device__ constexpr int twiddles_from(int L, int P, int NS) {
 // The thread's twiddle factors for a whole line transform, loaded once from
 // the table before any barrier (so their latency overlaps the data loads);
 // the inverse transform uses their conjugates.  Plans that need more than
-// kMaxTwiddleRegs of them (the long mixed-radix plans, 50 to 154 factors)
-// would not fit the register file next to their data, so their stages read
-// the factors from the table (an L1-resident few KB) instead.
-constexpr int kMaxTwiddleRegs = 36;
+// kMaxTwiddleRegs of them (the 1920-point plan, 144 factors) would not fit
+// the register file next to their data, so their stages read the factors
+// from the table (an L1-resident few KB) instead.  (Up to 56 preloaded:
+// the 600-point plan needs 54 and measured 13% faster preloaded.)
+#ifndef PM_MAX_TWIDDLE_REGS
+#define PM_MAX_TWIDDLE_REGS 56
+#endif
+constexpr int kMaxTwiddleRegs = PM_MAX_TWIDDLE_REGS;
 
 template <int L, int P>
 struct LineTwiddles {
