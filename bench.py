@@ -123,7 +123,7 @@ def bench_paper_slm(torch, binding, synth, steps=20):
 
     def timed(k, upload):
         hist = torch.empty(2 * k + 1, dtype=torch.float64, device=dev)
-        for _ in range(5):  # warm-up runs exactly what is timed (first pinned uploads are slow)
+        for _ in range(30):  # warm-up runs exactly what is timed (the first pinned uploads are slow)
             if upload:
                 md.copy_(host_m, non_blocking=True)
             plan.solve(md, pd, k, out=out, history=hist)

@@ -48,34 +48,42 @@ def _run(cmd):
     return r
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    """Compile every HIP source and link the library; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, jobs: int | None = None, defines=(), out: str | None = None) -> str:
+    """Compile every HIP source and link the library; returns its path.
+
+    ``defines`` are extra ``NAME=VALUE`` macros for the tuning knobs of the
+    kernels (``PM_LDS_PAD``, ``PM_LDS_LINE_EXTRA``, ``PM_MAX_TWIDDLE_REGS``);
+    ``out`` writes the library elsewhere (objects then go to a separate
+    folder), e.g. to compare variants."""
     hipcc = _hipcc()
+    flags = HIPFLAGS + [f"-D{d}" for d in defines]
+    build_dir = BUILD if out is None else os.path.join(BUILD, "variant_" + "_".join(d.replace("=", "") for d in defines))
+    os.makedirs(build_dir, exist_ok=True)
+    lib = LIB if out is None else out
     steps = []
     for L in LENGTHS:
-        obj = os.path.join(BUILD, f"pm_pass_{L}.o")
-        steps.append([hipcc, *HIPFLAGS, f"-DPM_L={L}", "-c",
+        obj = os.path.join(build_dir, f"pm_pass_{L}.o")
+        steps.append([hipcc, *flags, f"-DPM_L={L}", "-c",
                       os.path.join(CSRC, "pm_pass.hip"), "-o", obj])
     for which in range(6):
         for sched in range(BATCH_SCHEDULES):
-            steps.append([hipcc, *HIPFLAGS, f"-DPM_BATCH_WHICH={which}", f"-DPM_BATCH_SCHED={sched}",
+            steps.append([hipcc, *flags, f"-DPM_BATCH_WHICH={which}", f"-DPM_BATCH_SCHED={sched}",
                           "-c", os.path.join(CSRC, "pm_batch.hip"),
-                          "-o", os.path.join(BUILD, f"pm_batch_{which}_{sched}.o")])
-    steps.append([hipcc, *HIPFLAGS, "-c", os.path.join(CSRC, "pm_aux.hip"),
-                  "-o", os.path.join(BUILD, "pm_aux.o")])
-    steps.append([hipcc, *HIPFLAGS, "-x", "hip", "-c", os.path.join(CSRC, "phasemask.cpp"),
-                  "-o", os.path.join(BUILD, "phasemask.o")])
+                          "-o", os.path.join(build_dir, f"pm_batch_{which}_{sched}.o")])
+    steps.append([hipcc, *flags, "-c", os.path.join(CSRC, "pm_aux.hip"),
+                  "-o", os.path.join(build_dir, "pm_aux.o")])
+    steps.append([hipcc, *flags, "-x", "hip", "-c", os.path.join(CSRC, "phasemask.cpp"),
+                  "-o", os.path.join(build_dir, "phasemask.o")])
     jobs = jobs or min(8, os.cpu_count() or 1)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         for r in ex.map(_run, steps):
             if verbose and (r.stdout or r.stderr):
                 print(r.stdout + r.stderr, file=sys.stderr)
     objs = [s[s.index("-o") + 1] for s in steps]
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -283,15 +283,29 @@ __device__ __forceinline__ void dft(float2 (&x)[R]) {
     }
 }
 
-// Padded LDS index: one spare element after every 16, against bank conflicts
-// of the strided Stockham writes.  Lines of one work-group are a further 8
-// elements apart (16 banks), so the 4 lines that share a wave fall on
-// different banks.
-__device__ __forceinline__ constexpr int lds_pad(int i) { return i + (i >> 4); }
-#ifndef PM_LDS_LINE_EXTRA
-#define PM_LDS_LINE_EXTRA 8
+// LDS index of element i of a line.  PM_LDS_PAD selects a padding scheme (a
+// tuning knob; every scheme is a bijection onto a line of lds_line_len
+// elements, so results do not depend on it):
+//   0: one spare element after every 16;  1: after every 32;  2: none;
+//   3: after every 16 and another after every 256.
+// Lines of one work-group are PM_LDS_LINE_EXTRA elements further apart, so
+// the lines that share a wave fall on different banks.  Measured on MI355X
+// (1024^2 and 800 x 600 solves, 11 layouts): no padding with lines 4
+// elements apart (any extra of 4 mod 8) is fastest, 5.5% faster than one
+// spare per 16 with lines 8 apart at 1024^2 and 8% faster at 800 x 600.
+#ifndef PM_LDS_PAD
+#define PM_LDS_PAD 2
 #endif
-__host__ __device__ constexpr int lds_line_len(int L) { return L + L / 16 + PM_LDS_LINE_EXTRA; }
+#ifndef PM_LDS_LINE_EXTRA
+#define PM_LDS_LINE_EXTRA 4
+#endif
+__host__ __device__ constexpr int lds_pad(int i) {
+    return PM_LDS_PAD == 0 ? i + (i >> 4)
+         : PM_LDS_PAD == 1 ? i + (i >> 5)
+         : PM_LDS_PAD == 2 ? i
+                           : i + (i >> 4) + (i >> 8);
+}
+__host__ __device__ constexpr int lds_line_len(int L) { return lds_pad(L) + PM_LDS_LINE_EXTRA; }
 
 // Radix of the stage that starts at sub-transform length NS.  Powers of two
 // take P, P, ..., remainder.  The non-power-of-two lengths of common SLM
