@@ -14,7 +14,10 @@ namespace pm {
 // owns kGR adjacent rows reads kGR*kC contiguous elements (128 bytes) per
 // strip.  The rescaled target uses the same layout.
 constexpr int kC = 4;    // columns per strip = columns per column work-group
-constexpr int kGR = 4;   // rows per row work-group
+#ifndef PM_KGR
+#define PM_KGR 4
+#endif
+constexpr int kGR = PM_KGR;  // rows per row work-group (a tuning knob)
 
 // Per-call pointers.  Kernels replayed from a captured graph read them from
 // this device-resident block, which a one-thread kernel rewrites before each
