@@ -190,3 +190,21 @@ def test_tuner_picks_and_caches(pmb, monkeypatch, tmp_path):
     with pytest.raises(pmb.PhaseMaskError) as ei:
         pmb.BatchedPhaseMask(shapes)
     assert ei.value.status == -1
+
+
+def test_cache_groups_do_not_change_results(pmb, monkeypatch):
+    """Masks iterated in cache-sized groups (here one group per mask) give
+    bitwise the results of one group with all masks."""
+    shapes = [(256, 256), (64, 512), (512, 128), (128, 128)]
+    probs = _problems(shapes, 900)
+    targets = [_dev(m) for m, _ in probs]
+    phases = [_dev(p) for _, p in probs]
+    monkeypatch.setenv("PHASEMASK_GROUP_MB", "0")
+    a, ea = pmb.BatchedPhaseMask(shapes).solve(targets, phases, 7)
+    monkeypatch.setenv("PHASEMASK_GROUP_MB", "1")
+    b, eb = pmb.BatchedPhaseMask(shapes).solve(targets, phases, 7)
+    assert all(torch.equal(x, y) for x, y in zip(a, b)) and torch.equal(ea, eb)
+    monkeypatch.setenv("PHASEMASK_GROUP_MB", "-3")
+    with pytest.raises(pmb.PhaseMaskError) as ei:
+        pmb.BatchedPhaseMask(shapes)
+    assert ei.value.status == -1
