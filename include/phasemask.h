@@ -127,6 +127,8 @@ pm_status phasemask_set_illumination(pm_handle h, const float* illumination);
  *   target_amplitude  float[height*width], m >= 0, finite, not all zero,
  *                     natural DFT order (Eq. 2).  Only its direction matters
  *                     for the iterates (any positive scale gives the same u).
+ *                     (An all-zero target, not checked, makes M = {0}: the
+ *                     result is the tie-break phase 0 and every error is 1.)
  *   init_phase        float[height*width], radians, any real value.
  *   n_iter            >= 0.
  *   out_phase         float[height*width]; receives the FP32 atan2(Im u, Re u),

@@ -70,6 +70,8 @@ def test_host_side_argument_errors(lib):
     assert lib.phasemask_error(None, None, None, None) == -1
     assert lib.phasemask_fft2(None, None, None, 0) == -1
     assert lib.phasemask_set_stream(None, None) == -1
+    lib.phasemask_set_illumination.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.phasemask_set_illumination(None, None) == -1
     lib.phasemask_workspace_bytes.restype = ctypes.c_size_t
     assert lib.phasemask_workspace_bytes(None) == 0
 

@@ -146,3 +146,25 @@ def test_zero_illumination_pixels_keep_a_defined_phase(pmb):
     ph, _ = plan.solve(_dev(m), _dev(phi0), 5)
     o = ph.cpu().numpy()
     assert np.all(np.isfinite(o)) and np.all(np.abs(o) <= np.float32(math.pi))
+
+
+def test_illumination_argument_errors_and_reuse(pmb):
+    """A misaligned illumination pointer is rejected before any work; the
+    plan stays usable, and a batched handle refuses illumination."""
+    h = w = 64
+    m, phi0, p = _problem(h, w, 23)
+    plan = pmb.PhaseMask(h, w)
+    buf = torch.zeros(h * w + 1, device="cuda")
+    st = pmb.lib.phasemask_set_illumination(plan._h, buf.data_ptr() + 4)
+    assert st == -1
+    ph0, _ = plan.solve(_dev(m), _dev(phi0), 3)
+    plan.set_illumination(_dev(p))
+    plan.set_illumination(_dev(p))          # a second copy replaces the first
+    ph1, h1 = plan.solve(_dev(m), _dev(phi0), 3)
+    ref = gs.gs_solve(m, phi0, 3, p=p)["history"]
+    assert np.max(np.abs(h1.cpu().numpy()[:3] - ref[:3]) / ref[:3]) <= 1e-5
+    plan.set_illumination(None)
+    ph2, _ = plan.solve(_dev(m), _dev(phi0), 3)
+    assert torch.equal(ph0, ph2)
+    bp = pmb.BatchedPhaseMask([(64, 64)])
+    assert pmb.lib.phasemask_set_illumination(bp._h, None) == -5

@@ -260,3 +260,17 @@ def test_device_side_argument_errors(pmb):
         plan.solve(m, m.clone(), 1, out=m, history=False)  # output overlaps target
     with pytest.raises(ValueError):
         plan.solve(m, torch.ones(32, 64, device="cuda"), 1)
+
+
+def test_all_zero_target_is_defined(pmb):
+    """An all-zero target (outside the documented domain) still gives a
+    defined result: M-hat is zero, so P_M u = 0 and P_S takes the tie-break
+    phase 0 everywhere; E_F = || |F u| || / ||p|| = 1 and G = 1."""
+    h, w = 64, 128
+    rng = np.random.default_rng(3)
+    phi0 = synth.uniform_phase(h, w, rng)
+    plan = pmb.PhaseMask(h, w)
+    ph, hist = plan.solve(torch.zeros(h, w, device="cuda"), _dev(phi0), 3)
+    assert torch.count_nonzero(ph).item() == 0
+    hg = hist.cpu().numpy()
+    assert np.all(np.abs(hg - 1.0) <= 1e-6), hg
