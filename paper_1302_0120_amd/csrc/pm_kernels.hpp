@@ -144,11 +144,16 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
     constexpr int PAR1 = (MODE & C_FWD) != 0 ? fft_parity_after<H, P, 0>() : 0;
     if constexpr ((MODE & C_FWD) != 0) fft_line<H, P, false, LD::NBUF, 0>(v, j, line, LD::STRIDE, tw);
 
+    // Per-thread partial of this pass's FP64 sum (Fourier error or loss);
+    // the work-group reduction runs at the very end, after the stores, so
+    // its barrier and the serial sum of thread 0 hold up nothing else.
+    double acc = 0.0;
+    float mx = 0.0f;  // C_POW: per-thread maximum
+
     if constexpr ((MODE & (C_PROJ | C_ERR)) != 0) {
         // U = unnormalised DFT of u, so |U|/N is the unitary modulus over
         // sqrt(N); mhat = m / ||m||.  E_F^2 = sum (|U|/N - mhat)^2.
         constexpr bool ERR = (MODE & C_NOERR) == 0;
-        double acc = 0.0;
 #pragma unroll
         for (int t = 0; t < P; ++t) {
             const float m = mt[t];
@@ -168,23 +173,16 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
                 v[t] = nz ? make_float2(U.x * q, U.y * q) : make_float2(m, 0.0f);
             }
         }
-        if constexpr (ERR) {
-            const double tot = block_sum<NT>(acc, red);
-            if (tid == 0) *part_slot = tot;
-        }
     }
 
     if constexpr ((MODE & C_POW) != 0) {
-        // |U_unitary|^2 = |U|^2 / N (exact power-of-two scaling).
-        float mx = 0.0f;
+        // |U_unitary|^2 = |U|^2 / N (for N a power of two, an exact scaling).
 #pragma unroll
         for (int t = 0; t < P; ++t) {
             const float q = fmaf(v[t].x, v[t].x, v[t].y * v[t].y) * (float)a.invN;
             a.pw[sb + (size_t)(j + T * t) * kC + c] = q;
             mx = fmaxf(mx, q);
         }
-        mx = block_max<NT>(mx, reinterpret_cast<float*>(red));
-        if (tid == 0) *part_slot = (double)mx;
     }
 
     if constexpr ((MODE & C_LOSS) != 0) {
@@ -192,7 +190,6 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
         // unnormalised U here gives |U_unitary|^2 = |U|^2 / N (exact scaling).
         // The residual-weighted field r U feeds the adjoint transform; its
         // 1/sqrt(N) factors are folded into the gradient scale.
-        double acc = 0.0;
 #pragma unroll
         for (int t = 0; t < P; ++t) {
             const float I = a.inten[(size_t)(j + T * t) * a.W + s * kC + c];
@@ -201,8 +198,6 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
             acc = fma((double)r, (double)r, acc);
             v[t] = make_float2(U.x * r, U.y * r);
         }
-        const double tot = block_sum<NT>(acc, red);
-        if (tid == 0) *part_slot = tot;
     }
 
     if constexpr ((MODE & C_INV) != 0) fft_line<H, P, true, LD::NBUF, PAR1>(v, j, line, LD::STRIDE, tw);
@@ -214,6 +209,16 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
     if constexpr ((MODE & COUT_NAT) != 0) {
 #pragma unroll
         for (int t = 0; t < P; ++t) a.nat_out[(size_t)(j + T * t) * a.W + s * kC + c] = v[t];
+    }
+
+    constexpr bool SUM = ((MODE & (C_PROJ | C_ERR)) != 0 && (MODE & C_NOERR) == 0) || (MODE & C_LOSS) != 0;
+    if constexpr (SUM) {
+        const double tot = block_sum<NT>(acc, red);
+        if (tid == 0) *part_slot = tot;
+    }
+    if constexpr ((MODE & C_POW) != 0) {
+        mx = block_max<NT>(mx, reinterpret_cast<float*>(red));
+        if (tid == 0) *part_slot = (double)mx;
     }
 }
 
@@ -284,11 +289,13 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
     constexpr int PAR1 = (MODE & R_INV) != 0 ? fft_parity_after<W, P, 0>() : 0;
     if constexpr ((MODE & R_INV) != 0) fft_line<W, P, true, LD::NBUF, 0>(v, j, line, LD::STRIDE, tw);
 
+    // Per-thread gap partial; reduced at the very end (see col_body).
+    double acc = 0.0;
+
     if constexpr ((MODE & R_PS) != 0) {
         // w = P_M u^nu with unit scale (the target was divided by ||m||, so
         // the unnormalised inverse leaves |w| on the scale of p = 1).
         constexpr bool ERR = (MODE & R_NOERR) == 0;
-        double acc = 0.0;
 #pragma unroll
         for (int t = 0; t < P; ++t) {
             const float2 w = v[t];
@@ -308,10 +315,6 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
             } else {
                 v[t] = e;
             }
-        }
-        if constexpr (ERR) {
-            const double tot = block_sum<NT>(acc, red);
-            if (tid == 0) *part_slot = tot;
         }
     }
 
@@ -373,6 +376,10 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
         fft_line<W, P, false, LD::NBUF, PAR1>(v, j, line, LD::STRIDE, tw);
 #pragma unroll
         for (int t = 0; t < P; ++t) store_shared(&a.X[tiled(t)], v[t]);
+    }
+    if constexpr ((MODE & R_PS) != 0 && (MODE & R_NOERR) == 0) {
+        const double tot = block_sum<NT>(acc, red);
+        if (tid == 0) *part_slot = tot;
     }
 }
 
