@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "pm_common.h"
+#include "pm_fft.hpp"
 
 namespace {
 
@@ -119,6 +120,7 @@ struct pm_plan {
     hipStream_t stream = nullptr;      // caller's stream
     hipStream_t cap_stream = nullptr;  // private stream used only for graph capture
     int nwg_row = 0, nwg_col = 0, stride = 0;
+    int slots_row = 0, slots_col = 0;  // FP64 partials per row / column pass (one per reduction group)
     int num_cu = 0;                    // compute units of the device
     float2* X = nullptr;
     float* mhat = nullptr;
@@ -286,7 +288,7 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int al
         if (st != PM_OK) return st;
         PM_TRY(row(rmode(h, pm::ROW_INIT), row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
         PM_TRY(col(pm::COL_ERR, col_params(h, pe(0)), h->nwg_col, s, nullptr, nullptr), "column error");
-        PM_TRY(pm::launch_finalize(h->part, h->stride, h->nwg_col, h->nwg_row, 1.0 / h->N, h->io, 0, 1, s, 1, pnorm2(h)),
+        PM_TRY(pm::launch_finalize(h->part, h->stride, h->slots_col, h->slots_row, 1.0 / h->N, h->io, 0, 1, s, 1, pnorm2(h)),
                "finalize");
         return PM_OK;
     }
@@ -309,7 +311,7 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int al
         }
         if (hist) {
             PM_TRY(col(pm::COL_ERR, col_params(h, pe(2 * n_iter)), h->nwg_col, s, nullptr, nullptr), "column error");
-            PM_TRY(pm::launch_finalize(h->part, h->stride, h->nwg_col, h->nwg_row, 1.0 / h->N, h->io, 0, n_iter + 1,
+            PM_TRY(pm::launch_finalize(h->part, h->stride, h->slots_col, h->slots_row, 1.0 / h->N, h->io, 0, n_iter + 1,
                                        s, 2, pnorm2(h)),
                    "finalize");
         }
@@ -327,7 +329,7 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int al
     }
     if (hist) {
         PM_TRY(col(pm::COL_ERR, col_params(h, pe(2 * n_iter)), h->nwg_col, s, nullptr, nullptr), "column error");
-        PM_TRY(pm::launch_finalize(h->part, h->stride, h->nwg_col, h->nwg_row, 1.0 / h->N, h->io, 0,
+        PM_TRY(pm::launch_finalize(h->part, h->stride, h->slots_col, h->slots_row, 1.0 / h->N, h->io, 0,
                                    2 * n_iter + 1, s, 1, pnorm2(h)),
                "finalize");
     }
@@ -660,7 +662,10 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
     h->stream = (hipStream_t)stream;
     h->nwg_row = height / pm::kGR;
     h->nwg_col = width / pm::kC;
-    h->stride = h->nwg_row > h->nwg_col ? h->nwg_row : h->nwg_col;
+    // Threads per work-group: lines x (length / points per thread).
+    h->slots_row = h->nwg_row * pm::red_slots(pm::kGR * (width / pm::points_per_thread(width)));
+    h->slots_col = h->nwg_col * pm::red_slots(pm::kC * (height / pm::points_per_thread(height)));
+    h->stride = h->slots_row > h->slots_col ? h->slots_row : h->slots_col;
     if (h->stride < kNormGrid) h->stride = kNormGrid;
 
     auto bail = [&](hipError_t e, const char* what) {
@@ -814,7 +819,7 @@ pm_status phasemask_error(pm_handle h, const float* target_amplitude, const floa
     PM_TRY(col(pm::COL_ITER, col_params(h, h->part), h->nwg_col, s, nullptr, nullptr), "column pass");
     PM_TRY(row(rmode(h, pm::ROW_GAP), row_params(h, h->part + h->stride), h->nwg_row, s, nullptr, nullptr),
            "row gap");
-    PM_TRY(pm::launch_finalize(h->part, h->stride, h->nwg_col, h->nwg_row, 1.0 / h->N, h->io, 0, 2, s, 1,
+    PM_TRY(pm::launch_finalize(h->part, h->stride, h->slots_col, h->slots_row, 1.0 / h->N, h->io, 0, 2, s, 1,
                                pnorm2(h)),
            "finalize");
     return PM_OK;
@@ -913,7 +918,7 @@ pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights
         for (int p0 = 0; p0 < heights[i] * widths[i]; p0 += pm::kPrepPixels) prep.push_back(pm::BatchTask{i, p0});
     }
     h->n_prep_tasks = (int)prep.size();
-    const size_t npart = std::max(max_col, max_row);
+    const size_t npart = std::max(max_col, max_row) * pm::red_slots(pm::kBatchThreads);
     if ((e = hipMalloc(&h->masks, count * sizeof(pm::BatchMask))) != hipSuccess) return bail(e, "hipMalloc(masks)");
     if ((e = hipMalloc(&h->col_tasks, max_col * sizeof(pm::BatchTask))) != hipSuccess) return bail(e, "hipMalloc(tasks)");
     if ((e = hipMalloc(&h->row_tasks, max_row * sizeof(pm::BatchTask))) != hipSuccess) return bail(e, "hipMalloc(tasks)");
@@ -981,11 +986,11 @@ pm_status phasemask_intensity_loss_fwd(pm_handle h, int batch, const float* phas
     p.twH = h->twH;
     p.H = h->H;
     p.W = h->W;
-    p.nwg = h->nwg_col;
+    p.nwg = h->slots_col;
     hipStream_t s = h->stream;
     PM_TRY(kAdjRow[len_slot(h->W)](pm::ROW_INIT, p, batch, s), "loss row pass");
     PM_TRY(kAdjCol[len_slot(h->H)](p, batch, s), "loss column pass");
-    PM_TRY(pm::launch_sum_rows(h->part, h->nwg_col, loss, batch, s), "loss sum");
+    PM_TRY(pm::launch_sum_rows(h->part, h->slots_col, loss, batch, s), "loss sum");
     return PM_OK;
 }
 
@@ -1006,7 +1011,7 @@ pm_status phasemask_intensity_loss_bwd(pm_handle h, int batch, const float* phas
     p.twH = h->twH;
     p.H = h->H;
     p.W = h->W;
-    p.nwg = h->nwg_col;
+    p.nwg = h->slots_col;
     PM_TRY(kAdjRow[len_slot(h->W)](pm::ROW_GRAD, p, batch, h->stream), "gradient row pass");
     return PM_OK;
 }
@@ -1061,7 +1066,7 @@ pm_status phasemask_physical_error(pm_handle h, const float* target_amplitude, c
     pm::ColParams cp = col_params(h, h->part);
     cp.pw = h->pw;
     PM_TRY(col(pm::COL_POW, cp, h->nwg_col, s, nullptr, nullptr), "power column pass");
-    PM_TRY(pm::launch_physical_error(h->pw, h->part, h->nwg_col, target_amplitude, h->part_mx, kNormGrid, h->H,
+    PM_TRY(pm::launch_physical_error(h->pw, h->part, h->slots_col, target_amplitude, h->part_mx, kNormGrid, h->H,
                                      h->W, t_lit, t_dark, h->part + h->stride, errors, s),
            "physical error");
     return PM_OK;

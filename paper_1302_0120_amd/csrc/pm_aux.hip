@@ -103,15 +103,16 @@ k_target_tile(const PmIo* io, int H, int W, const double* part, int npart, float
 
 // History entry e = first_entry + blockIdx.x * entry_step: even entries are Fourier
 // errors, E_F = sqrt(sum of partials); odd entries are gaps,
-// G = sqrt(sum / N).  Partials of entry e sit at part[e * stride + wg].
+// G = sqrt(sum / N).  The n_col (n_row) partials of entry e sit at
+// part[e * stride + i].
 // With an illumination p (pn2 = ||p||^2 on the device) the errors are
 // relative to ||p||: E_F = sqrt(sum N / ||p||^2), G = sqrt(sum / ||p||^2).
 __global__ void __launch_bounds__(kAuxThreads)
-k_finalize(const double* part, int stride, int nwg_col, int nwg_row, double invN,
+k_finalize(const double* part, int stride, int n_col, int n_row, double invN,
            const PmIo* io, int first_entry, int entry_step, const double* pn2) {
     __shared__ double red[red_slots(kAuxThreads)];
     const int e = first_entry + blockIdx.x * entry_step;
-    const int nwg = (e & 1) ? nwg_row : nwg_col;
+    const int nwg = (e & 1) ? n_row : n_col;
     const double* p = part + (size_t)e * stride;
     double acc = 0.0;
     for (int i = threadIdx.x; i < nwg; i += kAuxThreads) acc += p[i];
@@ -218,7 +219,8 @@ k_batch_finalize(const BatchIo* io, const BatchMask* masks, const double* part) 
     __shared__ double red[red_slots(kAuxThreads)];
     const BatchMask mk = masks[blockIdx.x];
     double acc = 0.0;
-    for (int i = threadIdx.x; i < mk.col_wgs; i += kAuxThreads) acc += part[mk.col_wg0 + i];
+    constexpr int NS = red_slots(kBatchThreads);  // partials per column work-group
+    for (int i = threadIdx.x; i < mk.col_wgs * NS; i += kAuxThreads) acc += part[mk.col_wg0 * NS + i];
     const double tot = block_sum<kAuxThreads>(acc, red);
     if (threadIdx.x == 0 && io->final_err != nullptr) io->final_err[blockIdx.x] = sqrt(tot);
 }
@@ -386,10 +388,10 @@ hipError_t launch_target_tile(const PmIo* io, int H, int W, const double* part, 
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double* part, int stride, int nwg_col, int nwg_row, double invN,
+hipError_t launch_finalize(const double* part, int stride, int n_col, int n_row, double invN,
                            const PmIo* io, int first_entry, int count, hipStream_t s, int entry_step,
                            const double* pn2) {
-    k_finalize<<<count, kAuxThreads, 0, s>>>(part, stride, nwg_col, nwg_row, invN, io, first_entry, entry_step,
+    k_finalize<<<count, kAuxThreads, 0, s>>>(part, stride, n_col, n_row, invN, io, first_entry, entry_step,
                                              pn2);
     return hipGetLastError();
 }

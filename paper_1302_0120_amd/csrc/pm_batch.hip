@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_col_batch(BatchParams p) {
     a.tw = p.tw;
     a.W = mk.W;
     a.invN = 1.0 / ((double)mk.H * (double)mk.W);
-    double* slot = p.part + blockIdx.x;
+    double* slot = p.part + blockIdx.x * red_slots(kBatchThreads);
     switch (mk.H) {
         PM_COL_CASE(64)
         PM_COL_CASE(128)
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_row_batch(BatchParams p) {
     float* pout = nullptr;
     if constexpr ((MODE & RIN_PHASE) != 0) pin = p.io->phases_in[task.mask];
     if constexpr ((MODE & ROUT_PHASE) != 0) pout = p.io->phases_out[task.mask];
-    double* slot = p.part + blockIdx.x;
+    double* slot = p.part + blockIdx.x * red_slots(kBatchThreads);
     switch (mk.W) {
         PM_ROW_CASE(64)
         PM_ROW_CASE(128)

@@ -13,6 +13,15 @@ namespace pm {
 // A column pass reads one strip as one contiguous block; a row pass that
 // owns kGR adjacent rows reads kGR*kC contiguous elements (128 bytes) per
 // strip.  The rescaled target uses the same layout.
+// Reduction groups of a work-group of NT threads: the largest power of two
+// that divides NT, at most one wave.  A group is a run of whole lanes, so
+// in-group shuffles never read an inactive lane (a work-group of 80 threads
+// is one full wave and a quarter wave: five groups of 16).  The passes write
+// one FP64 partial per group (red_slots(NT) per work-group), so no
+// work-group barrier is needed for their sums.
+__host__ __device__ constexpr int red_width(int NT) { return (NT & -NT) < 64 ? (NT & -NT) : 64; }
+__host__ __device__ constexpr int red_slots(int NT) { return NT / red_width(NT); }
+
 constexpr int kC = 4;    // columns per strip = columns per column work-group
 #ifndef PM_KGR
 #define PM_KGR 4
@@ -129,7 +138,7 @@ struct AdjParams {
     const float* inten;         // [batch][H][W] target intensity
     float* grad;                // [batch][H][W] gradient (backward)
     const double* grad_loss;    // [batch] upstream gradient of each sample's loss (backward)
-    double* part;               // [batch][nwg] loss partials (forward)
+    double* part;               // [batch][nwg] loss partials (forward), nwg slots per sample
     const float2* twW;
     const float2* twH;
     int H, W, nwg;
@@ -262,7 +271,7 @@ hipError_t launch_target_tile(const PmIo* io, int H, int W, const double* part, 
                               float* mhat, hipStream_t s, const double* pn2 = nullptr);
 // History entries first_entry + k * entry_step, k < count, into hist[k].
 // pn2: ||p||^2 on the device with an illumination, else null (p = 1).
-hipError_t launch_finalize(const double* part, int stride, int nwg_col, int nwg_row, double invN,
+hipError_t launch_finalize(const double* part, int stride, int n_col, int n_row, double invN,
                            const PmIo* io, int first_entry, int count, hipStream_t s, int entry_step = 1,
                            const double* pn2 = nullptr);
 // Illumination set-up: p (natural layout [H][W]) copied to the strip-tiled

@@ -23,13 +23,6 @@
 
 namespace pm {
 
-// Reduction groups of a work-group of NT threads: the largest power of two
-// that divides NT, at most one wave.  A group is a run of whole lanes, so
-// the in-group shuffles never read an inactive lane (a work-group of 80
-// threads is one full wave and a quarter wave: five groups of 16).
-__host__ __device__ constexpr int red_width(int NT) { return (NT & -NT) < 64 ? (NT & -NT) : 64; }
-__host__ __device__ constexpr int red_slots(int NT) { return NT / red_width(NT); }
-
 // Deterministic work-group sum of one double per thread: a fixed xor
 // butterfly inside each reduction group, then group results added in group
 // order by thread 0.  The result is valid in thread 0 only.  All threads
@@ -52,6 +45,26 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
         }
         return s;
     }
+}
+
+// One FP64 partial per reduction group (see red_width): a fixed xor
+// butterfly inside the group, then the group's first lane writes its sum to
+// slot[group].  No barrier; all threads must call.
+template <int NT>
+__device__ __forceinline__ void group_sum_store(double v, double* slot) {
+    constexpr int WS = red_width(NT);
+#pragma unroll
+    for (int off = WS / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WS);
+    if (threadIdx.x % WS == 0) slot[threadIdx.x / WS] = v;
+}
+
+// The same for a maximum (stored as a double).
+template <int NT>
+__device__ __forceinline__ void group_max_store(float v, double* slot) {
+    constexpr int WS = red_width(NT);
+#pragma unroll
+    for (int off = WS / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, WS));
+    if (threadIdx.x % WS == 0) slot[threadIdx.x / WS] = (double)v;
 }
 
 // Store of one iterate element that the next pass reads on other XCDs: a
@@ -96,7 +109,8 @@ struct LineShape {
 // `strip0` (G a multiple of kC).  Thread tid = (sl, j, c), c fastest: strip
 // strip0 + sl, column c of that strip, rows j + T t.  For a fixed t a wave's
 // loads are 64 / kC consecutive rows of one strip: one contiguous run.
-// `lds` holds LdsPlan<H, G>::FLOATS2 elements, `red` red_slots(G T) doubles.
+// `lds` holds LdsPlan<H, G>::FLOATS2 elements, `red` red_slots(G T) doubles;
+// the FP64 partials go to part_slot[0 .. red_slots(G T)).
 template <int H, int P, int G, int MODE>
 __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double* part_slot,
                                          float2* lds, double* red) {
@@ -145,8 +159,8 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
     if constexpr ((MODE & C_FWD) != 0) fft_line<H, P, false, LD::NBUF, 0>(v, j, line, LD::STRIDE, tw);
 
     // Per-thread partial of this pass's FP64 sum (Fourier error or loss);
-    // the work-group reduction runs at the very end, after the stores, so
-    // its barrier and the serial sum of thread 0 hold up nothing else.
+    // reduced at the very end, after the stores, into one partial per
+    // reduction group (part_slot[0 .. red_slots(NT))).
     double acc = 0.0;
     float mx = 0.0f;  // C_POW: per-thread maximum
 
@@ -212,14 +226,8 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
     }
 
     constexpr bool SUM = ((MODE & (C_PROJ | C_ERR)) != 0 && (MODE & C_NOERR) == 0) || (MODE & C_LOSS) != 0;
-    if constexpr (SUM) {
-        const double tot = block_sum<NT>(acc, red);
-        if (tid == 0) *part_slot = tot;
-    }
-    if constexpr ((MODE & C_POW) != 0) {
-        mx = block_max<NT>(mx, reinterpret_cast<float*>(red));
-        if (tid == 0) *part_slot = (double)mx;
-    }
+    if constexpr (SUM) group_sum_store<NT>(acc, part_slot);
+    if constexpr ((MODE & C_POW) != 0) group_max_store<NT>(mx, part_slot);
 }
 
 // Row pass over G adjacent rows starting at `row0`.  Thread tid = (jhi, rho,
@@ -377,10 +385,7 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
 #pragma unroll
         for (int t = 0; t < P; ++t) store_shared(&a.X[tiled(t)], v[t]);
     }
-    if constexpr ((MODE & R_PS) != 0 && (MODE & R_NOERR) == 0) {
-        const double tot = block_sum<NT>(acc, red);
-        if (tid == 0) *part_slot = tot;
-    }
+    if constexpr ((MODE & R_PS) != 0 && (MODE & R_NOERR) == 0) group_sum_store<NT>(acc, part_slot);
 }
 
 // One-mask kernels: kC columns (one strip) or kGR rows per work-group.
@@ -390,7 +395,7 @@ k_col(ColParams a) {
     constexpr int NT = kC * LineShape<H>::T;
     __shared__ float2 lds[LdsPlan<H, kC>::FLOATS2];
     __shared__ double red[red_slots(NT)];
-    col_body<H, LineShape<H>::P, kC, MODE>(a, blockIdx.x, a.part + blockIdx.x, lds, red);
+    col_body<H, LineShape<H>::P, kC, MODE>(a, blockIdx.x, a.part + blockIdx.x * red_slots(NT), lds, red);
 }
 
 template <int W, int MODE>
@@ -403,7 +408,8 @@ k_row(RowParams a) {
     float* pout = nullptr;
     if constexpr ((MODE & RIN_PHASE) != 0) pin = a.io->phase_in;
     if constexpr ((MODE & ROUT_PHASE) != 0) pout = a.io->phase_out;
-    row_body<W, LineShape<W>::P, kGR, MODE>(a, blockIdx.x * kGR, pin, pout, a.part + blockIdx.x, lds, red);
+    row_body<W, LineShape<W>::P, kGR, MODE>(a, blockIdx.x * kGR, pin, pout, a.part + blockIdx.x * red_slots(NT), lds,
+                                            red);
 }
 
 // Intensity-loss kernels over a batch of same-size phases, sample = blockIdx.y.
@@ -445,7 +451,8 @@ k_col_adj(AdjParams p) {
     a.W = p.W;
     a.invN = 1.0 / (double)n;
     a.inten = p.inten + b * n;
-    col_body<H, LineShape<H>::P, kC, COL_LOSS>(a, blockIdx.x, p.part + b * p.nwg + blockIdx.x, lds, red);
+    col_body<H, LineShape<H>::P, kC, COL_LOSS>(a, blockIdx.x, p.part + b * p.nwg + blockIdx.x * red_slots(NT), lds,
+                                               red);
 }
 
 }  // namespace pm
