@@ -660,10 +660,10 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
     h->N = height * width;
     h->flags = flags;
     h->stream = (hipStream_t)stream;
-    h->nwg_row = height / pm::kGR;
+    h->nwg_row = height / pm::row_lines(width);
     h->nwg_col = width / pm::kC;
     // Threads per work-group: lines x (length / points per thread).
-    h->slots_row = h->nwg_row * pm::red_slots(pm::kGR * (width / pm::points_per_thread(width)));
+    h->slots_row = h->nwg_row * pm::red_slots(pm::row_lines(width) * (width / pm::points_per_thread(width)));
     h->slots_col = h->nwg_col * pm::red_slots(pm::kC * (height / pm::points_per_thread(height)));
     h->stride = h->slots_row > h->slots_col ? h->slots_row : h->slots_col;
     if (h->stride < kNormGrid) h->stride = kNormGrid;

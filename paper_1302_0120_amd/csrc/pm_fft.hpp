@@ -481,4 +481,10 @@ __host__ __device__ constexpr int points_per_thread(int L) {
          : (L >= 256 ? 16 : (L >= 32 ? 8 : 4));
 }
 
+// Rows per work-group of the one-mask row pass for rows of W points.
+#ifndef PM_ROWS_800
+#define PM_ROWS_800 4
+#endif
+__host__ __device__ constexpr int row_lines(int W) { return W == 800 ? PM_ROWS_800 : kGR; }
+
 }  // namespace pm

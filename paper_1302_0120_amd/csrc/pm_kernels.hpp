@@ -388,7 +388,7 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
     if constexpr ((MODE & R_PS) != 0 && (MODE & R_NOERR) == 0) group_sum_store<NT>(acc, part_slot);
 }
 
-// One-mask kernels: kC columns (one strip) or kGR rows per work-group.
+// One-mask kernels: kC columns (one strip) or row_lines(W) rows per work-group.
 template <int H, int MODE>
 __global__ void __launch_bounds__(kC * LineShape<H>::T)
 k_col(ColParams a) {
@@ -399,16 +399,16 @@ k_col(ColParams a) {
 }
 
 template <int W, int MODE>
-__global__ void __launch_bounds__(kGR * LineShape<W>::T)
+__global__ void __launch_bounds__(row_lines(W) * LineShape<W>::T)
 k_row(RowParams a) {
-    constexpr int NT = kGR * LineShape<W>::T;
-    __shared__ float2 lds[LdsPlan<W, kGR>::FLOATS2];
+    constexpr int NT = row_lines(W) * LineShape<W>::T;
+    __shared__ float2 lds[LdsPlan<W, row_lines(W)>::FLOATS2];
     __shared__ double red[red_slots(NT)];
     const float* pin = nullptr;
     float* pout = nullptr;
     if constexpr ((MODE & RIN_PHASE) != 0) pin = a.io->phase_in;
     if constexpr ((MODE & ROUT_PHASE) != 0) pout = a.io->phase_out;
-    row_body<W, LineShape<W>::P, kGR, MODE>(a, blockIdx.x * kGR, pin, pout, a.part + blockIdx.x * red_slots(NT), lds,
+    row_body<W, LineShape<W>::P, row_lines(W), MODE>(a, blockIdx.x * row_lines(W), pin, pout, a.part + blockIdx.x * red_slots(NT), lds,
                                             red);
 }
 
@@ -416,10 +416,10 @@ k_row(RowParams a) {
 // Forward: ROW_INIT (exp(i phi), row FFT) then the column kernel (COL_LOSS).
 // Backward: ROW_GRAD.
 template <int W, int MODE>
-__global__ void __launch_bounds__(kGR * LineShape<W>::T)
+__global__ void __launch_bounds__(row_lines(W) * LineShape<W>::T)
 k_row_adj(AdjParams p) {
-    constexpr int NT = kGR * LineShape<W>::T;
-    __shared__ float2 lds[LdsPlan<W, kGR>::FLOATS2];
+    constexpr int NT = row_lines(W) * LineShape<W>::T;
+    __shared__ float2 lds[LdsPlan<W, row_lines(W)>::FLOATS2];
     __shared__ double red[red_slots(NT)];
     const size_t n = (size_t)p.H * W;
     const size_t b = blockIdx.y;
@@ -433,7 +433,7 @@ k_row_adj(AdjParams p) {
         a.gscale = (float)(4.0 * p.grad_loss[b] / (double)n);
         out = p.grad + b * n;
     }
-    row_body<W, LineShape<W>::P, kGR, MODE>(a, blockIdx.x * kGR, p.phase + b * n, out, nullptr, lds, red);
+    row_body<W, LineShape<W>::P, row_lines(W), MODE>(a, blockIdx.x * row_lines(W), p.phase + b * n, out, nullptr, lds, red);
 }
 
 template <int H>

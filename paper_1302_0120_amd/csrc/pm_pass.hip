@@ -56,7 +56,7 @@ hipError_t launch(void (*kern)(Params), int grid, int block, hipStream_t s, hipE
 
 hipError_t PM_CAT(launch_row_, PM_L)(int mode, const RowParams& p, int grid, hipStream_t s,
                                      hipEvent_t ev0, hipEvent_t ev1) {
-    const int block = kGR * LineShape<PM_L>::T;
+    const int block = row_lines(PM_L) * LineShape<PM_L>::T;
     switch (mode) {
         PM_ROW_SOLVE_MODES(PM_ROW_CASE)
         case ROW_FFT_FWD: return launch(k_row<PM_L, ROW_FFT_FWD>, grid, block, s, ev0, ev1, p);
@@ -83,7 +83,7 @@ hipError_t PM_CAT(launch_col_, PM_L)(int mode, const ColParams& p, int grid, hip
 }
 
 hipError_t PM_CAT(launch_adj_row_, PM_L)(int mode, const AdjParams& p, int batch, hipStream_t s) {
-    const dim3 grid(p.H / kGR, batch), block(kGR * LineShape<PM_L>::T);
+    const dim3 grid(p.H / row_lines(PM_L), batch), block(row_lines(PM_L) * LineShape<PM_L>::T);
     switch (mode) {
         case ROW_INIT: k_row_adj<PM_L, ROW_INIT><<<grid, block, 0, s>>>(p); break;
         case ROW_GRAD: k_row_adj<PM_L, ROW_GRAD><<<grid, block, 0, s>>>(p); break;
