@@ -307,6 +307,46 @@ __host__ __device__ constexpr int lds_pad(int i) {
 }
 __host__ __device__ constexpr int lds_line_len(int L) { return lds_pad(L) + PM_LDS_LINE_EXTRA; }
 
+// LDS-resident transforms.  For lengths whose register plan would need too
+// many points per thread (1920 needs P = 60 and spills), every stage reads
+// its butterfly inputs from LDS and writes its outputs back to LDS, so the
+// stage radices need not divide the points per thread: T threads per line
+// share the L / R butterflies of a stage in rounds.  Costs one more LDS
+// write and read per transform (the line enters and leaves LDS in natural
+// order) and, with ragged rounds, some idle lanes.  PM_LDS_MODE_<L> selects
+// the scheme for the other mixed-radix lengths; measured on MI355X, LDS mode
+// is faster for 600 (column pass 9.2 -> 6.9 us at 800 x 600) and 1080 (22
+// -> 14 us at 1080 x 1920), slower for 800 (7.1 -> 8.0 us).
+#ifndef PM_LDS_MODE_600
+#define PM_LDS_MODE_600 1
+#endif
+#ifndef PM_LDS_MODE_800
+#define PM_LDS_MODE_800 0
+#endif
+#ifndef PM_LDS_MODE_1080
+#define PM_LDS_MODE_1080 1
+#endif
+__host__ __device__ constexpr bool lds_mode(int L) {
+    return L == 1920 || (L == 600 && PM_LDS_MODE_600) || (L == 800 && PM_LDS_MODE_800) ||
+           (L == 1080 && PM_LDS_MODE_1080);
+}
+// Threads per line in LDS mode.
+__host__ __device__ constexpr int lds_threads(int L) {
+    return L == 1920 ? 128 : (L == 600 ? 60 : (L == 800 ? 80 : 120));
+}
+// Radix sequences in LDS mode (largest radix first, where no inter-stage
+// twiddles are needed): 1920 = 16*12*10, 600 = 10*6*10, 800 = 20*10*4,
+// 1080 = 30*6*6.
+__host__ __device__ constexpr int lds_stage_radix(int L, int NS) {
+    return L == 1920 ? (NS == 1 ? 16 : (NS == 16 ? 12 : 10))
+         : L == 600 ? (NS == 1 ? 10 : (NS == 10 ? 6 : 10))
+         : L == 800 ? (NS == 1 ? 20 : (NS == 20 ? 10 : 4))
+                    : (NS == 1 ? 30 : 6);
+}
+__host__ __device__ constexpr int lds_num_stages(int L, int NS = 1) {
+    return NS >= L ? 0 : 1 + lds_num_stages(L, NS * lds_stage_radix(L, NS));
+}
+
 // Radix of the stage that starts at sub-transform length NS.  Powers of two
 // take P, P, ..., remainder.  The non-power-of-two lengths of common SLM
 // panels (800 x 600, 1920 x 1080) take fixed mixed-radix sequences whose
@@ -343,8 +383,8 @@ constexpr int kMaxTwiddleRegs = PM_MAX_TWIDDLE_REGS;
 
 template <int L, int P>
 struct LineTwiddles {
-    static constexpr int NEED = twiddles_from(L, P, 1);
-    static constexpr bool PRELOAD = NEED <= kMaxTwiddleRegs;
+    static constexpr int NEED = lds_mode(L) ? 0 : twiddles_from(L, P, 1);
+    static constexpr bool PRELOAD = !lds_mode(L) && NEED <= kMaxTwiddleRegs;
     static constexpr int COUNT = (PRELOAD && NEED > 0) ? NEED : 1;
     float2 w[COUNT];
     const float2* table;
@@ -389,7 +429,7 @@ __device__ __forceinline__ void load_twiddles(LineTwiddles<L, P>& tw, int j, con
 template <int L, int G>
 struct LdsPlan {
     static constexpr int LP = lds_line_len(L);
-    static constexpr int NBUF = (2 * G * LP * 8 <= 80 * 1024) ? 2 : 1;
+    static constexpr int NBUF = (lds_mode(L) || 2 * G * LP * 8 <= 80 * 1024) ? 2 : 1;
     static constexpr int FLOATS2 = NBUF * G * LP;  // float2 elements per work-group
     static constexpr int STRIDE = G * LP;
 };
@@ -453,6 +493,64 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, i
     }
 }
 
+// LDS-mode stages from sub-length NS on: read src, write dst, barrier, swap.
+// Thread j takes butterflies b = j + T m of each stage (the last round may
+// leave some threads idle); butterfly b reads src[b + q L/R], multiplies by
+// exp(-+2 pi i q (b mod NS) / (NS R)), does the R-point DFT and writes
+// dst[(b - b mod NS) R + b mod NS + q NS], as in the register scheme.
+template <int L, int NS, bool INV>
+__device__ __forceinline__ void lds_stages(float2* src, float2* dst, int j, const float2* __restrict__ table,
+                                           int step) {
+    if constexpr (NS < L) {
+        constexpr int T = lds_threads(L);
+        constexpr int R = lds_stage_radix(L, NS);
+        constexpr int NB = L / R;
+        constexpr int ROUNDS = (NB + T - 1) / T;
+#pragma unroll
+        for (int m = 0; m < ROUNDS; ++m) {
+            const int b = j + T * m;
+            if (NB % T == 0 || b < NB) {
+                float2 x[R];
+#pragma unroll
+                for (int q = 0; q < R; ++q) x[q] = src[b + q * NB];
+                const int k = b % NS;
+                if constexpr (NS > 1) {
+#pragma unroll
+                    for (int q = 1; q < R; ++q) {
+                        float2 w = table[q * k * (L / (NS * R)) * step];
+                        if constexpr (INV) w.y = -w.y;
+                        x[q] = cmul(x[q], w);
+                    }
+                }
+                dft<R, INV>(x);
+                const int base = (b - k) * R + k;
+#pragma unroll
+                for (int q = 0; q < R; ++q) dst[base + q * NS] = x[q];
+            }
+        }
+        __syncthreads();
+        lds_stages<L, NS * R, INV>(dst, src, j, table, step);
+    }
+}
+
+// Whole LDS-mode transform of one line held as v[t] = x[j + T t]: into LDS,
+// the stages, back into registers.  Ends with a barrier, so the next
+// transform may reuse both buffers.
+template <int L, int P, bool INV>
+__device__ __forceinline__ void fft_line_lds(float2 (&v)[P], int j, float2* a, float2* b,
+                                             const float2* __restrict__ table, int step) {
+    constexpr int T = lds_threads(L);
+    static_assert(T * P == L, "LDS-mode lines hold L / T points per thread");
+#pragma unroll
+    for (int t = 0; t < P; ++t) a[j + T * t] = v[t];
+    __syncthreads();
+    lds_stages<L, 1, INV>(a, b, j, table, step);
+    float2* res = (lds_num_stages(L) % 2 == 0) ? a : b;
+#pragma unroll
+    for (int t = 0; t < P; ++t) v[t] = res[j + T * t];
+    __syncthreads();
+}
+
 // Full length-L transform of one line; every thread of the work-group must
 // call it (it contains work-group barriers).  Consecutive transforms in one
 // kernel must pass PAR = the parity after the previous one
@@ -460,12 +558,17 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, i
 template <int L, int P, bool INV, int NBUF, int PAR>
 __device__ __forceinline__ void fft_line(float2 (&v)[P], int j, float2* line, int stride,
                                          const LineTwiddles<L, P>& tw) {
-    fft_stage<L, P, 1, 0, INV, NBUF, PAR>(v, j, line, stride, tw);
+    if constexpr (lds_mode(L)) {
+        static_assert(NBUF == 2, "LDS mode ping-pongs between two buffers");
+        fft_line_lds<L, P, INV>(v, j, line, line + stride, tw.table, tw.step);
+    } else {
+        fft_stage<L, P, 1, 0, INV, NBUF, PAR>(v, j, line, stride, tw);
+    }
 }
 
 template <int L, int P, int PAR>
 __host__ __device__ constexpr int fft_parity_after() {
-    return (PAR + exchanges_from(L, P, 1)) & 1;
+    return lds_mode(L) ? PAR : (PAR + exchanges_from(L, P, 1)) & 1;
 }
 
 // Points per thread for a line of L points.  At 1024, P = 8 (radix 8-8-8-2,
@@ -473,7 +576,8 @@ __host__ __device__ constexpr int fft_parity_after() {
 // one more LDS exchange, but two waves per SIMD instead of one to hide the
 // load latency behind (the one-mask 1024^2 passes hold one line per SIMD).
 __host__ __device__ constexpr int points_per_thread(int L) {
-    return L == 800 ? 20
+    return lds_mode(L) ? L / lds_threads(L)
+         : L == 800 ? 20
          : L == 600 ? 30
          : L == 1080 ? 30
          : L == 1920 ? 60
