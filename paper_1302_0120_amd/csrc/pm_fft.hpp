@@ -331,8 +331,11 @@ __host__ __device__ constexpr bool lds_mode(int L) {
            (L == 1080 && PM_LDS_MODE_1080);
 }
 // Threads per line in LDS mode.
+#ifndef PM_LDS_T_1920
+#define PM_LDS_T_1920 128
+#endif
 __host__ __device__ constexpr int lds_threads(int L) {
-    return L == 1920 ? 128 : (L == 600 ? 60 : (L == 800 ? 80 : 120));
+    return L == 1920 ? PM_LDS_T_1920 : (L == 600 ? 60 : (L == 800 ? 80 : 120));
 }
 // Radix sequences in LDS mode (largest radix first, where no inter-stage
 // twiddles are needed): 1920 = 16*12*10, 600 = 10*6*10, 800 = 20*10*4,
@@ -589,6 +592,11 @@ __host__ __device__ constexpr int points_per_thread(int L) {
 #ifndef PM_ROWS_800
 #define PM_ROWS_800 4
 #endif
-__host__ __device__ constexpr int row_lines(int W) { return W == 800 ? PM_ROWS_800 : kGR; }
+#ifndef PM_ROWS_1920
+#define PM_ROWS_1920 4
+#endif
+__host__ __device__ constexpr int row_lines(int W) {
+    return W == 800 ? PM_ROWS_800 : (W == 1920 ? PM_ROWS_1920 : kGR);
+}
 
 }  // namespace pm
