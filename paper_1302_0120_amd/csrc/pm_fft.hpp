@@ -349,6 +349,21 @@ __host__ __device__ constexpr int lds_stage_radix(int L, int NS) {
 __host__ __device__ constexpr int lds_num_stages(int L, int NS = 1) {
     return NS >= L ? 0 : 1 + lds_num_stages(L, NS * lds_stage_radix(L, NS));
 }
+// LDS mode preloads its inter-stage twiddles into registers only for 600
+// points (measured: 800 x 600 solve 3% faster); for 1080 the extra
+// registers halve the work-groups per CU (pass 14 -> 20 us), for 1920 it
+// is neutral, so those read the table stage by stage.
+__host__ __device__ constexpr bool lds_preload(int L) { return L == 600; }
+
+// Inter-stage twiddles a thread multiplies in LDS mode from sub-length NS on
+// (R - 1 per butterfly round of every stage with NS > 1).
+__host__ __device__ constexpr int lds_twiddles_from(int L, int NS) {
+    return NS >= L ? 0
+                   : (NS > 1 ? ((L / lds_stage_radix(L, NS) + lds_threads(L) - 1) / lds_threads(L)) *
+                                   (lds_stage_radix(L, NS) - 1)
+                             : 0) +
+                         lds_twiddles_from(L, NS * lds_stage_radix(L, NS));
+}
 
 // Radix of the stage that starts at sub-transform length NS.  Powers of two
 // take P, P, ..., remainder.  The non-power-of-two lengths of common SLM
@@ -386,8 +401,8 @@ constexpr int kMaxTwiddleRegs = PM_MAX_TWIDDLE_REGS;
 
 template <int L, int P>
 struct LineTwiddles {
-    static constexpr int NEED = lds_mode(L) ? 0 : twiddles_from(L, P, 1);
-    static constexpr bool PRELOAD = !lds_mode(L) && NEED <= kMaxTwiddleRegs;
+    static constexpr int NEED = lds_mode(L) ? lds_twiddles_from(L, 1) : twiddles_from(L, P, 1);
+    static constexpr bool PRELOAD = lds_mode(L) ? lds_preload(L) : NEED <= kMaxTwiddleRegs;
     static constexpr int COUNT = (PRELOAD && NEED > 0) ? NEED : 1;
     float2 w[COUNT];
     const float2* table;
@@ -416,6 +431,32 @@ __device__ __forceinline__ void load_twiddles_from(LineTwiddles<L, P>& tw, int j
     }
 }
 
+// LDS mode: the twiddles of every round of every stage (rounds past the
+// last butterfly load a harmless entry and are never used).
+template <int L, int P, int NS, int OFF>
+__device__ __forceinline__ void lds_load_twiddles_from(LineTwiddles<L, P>& tw, int j,
+                                                       const float2* __restrict__ table, int step) {
+    if constexpr (NS < L) {
+        constexpr int T = lds_threads(L);
+        constexpr int R = lds_stage_radix(L, NS);
+        constexpr int NB = L / R;
+        constexpr int ROUNDS = (NB + T - 1) / T;
+        if constexpr (NS > 1) {
+            constexpr int STRIDE = L / (NS * R);
+#pragma unroll
+            for (int m = 0; m < ROUNDS; ++m) {
+                const int b = j + T * m;
+                const int k = b < NB ? b % NS : 0;
+#pragma unroll
+                for (int q = 1; q < R; ++q) tw.w[OFF + m * (R - 1) + (q - 1)] = table[q * k * STRIDE * step];
+            }
+            lds_load_twiddles_from<L, P, NS * R, OFF + ROUNDS * (R - 1)>(tw, j, table, step);
+        } else {
+            lds_load_twiddles_from<L, P, NS * R, OFF>(tw, j, table, step);
+        }
+    }
+}
+
 // `table` holds exp(-2 pi i k / (L step)); entry k step is exp(-2 pi i k / L),
 // so one table of the largest length serves every shorter power of two.
 template <int L, int P>
@@ -423,7 +464,13 @@ __device__ __forceinline__ void load_twiddles(LineTwiddles<L, P>& tw, int j, con
                                               int step) {
     tw.table = table;
     tw.step = step;
-    if constexpr (LineTwiddles<L, P>::PRELOAD) load_twiddles_from<L, P, 1, 0>(tw, j, table, step);
+    if constexpr (LineTwiddles<L, P>::PRELOAD) {
+        if constexpr (lds_mode(L)) {
+            lds_load_twiddles_from<L, P, 1, 0>(tw, j, table, step);
+        } else {
+            load_twiddles_from<L, P, 1, 0>(tw, j, table, step);
+        }
+    }
 }
 
 // LDS exchange buffers per line: two (alternating, one barrier per
@@ -501,9 +548,8 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, i
 // leave some threads idle); butterfly b reads src[b + q L/R], multiplies by
 // exp(-+2 pi i q (b mod NS) / (NS R)), does the R-point DFT and writes
 // dst[(b - b mod NS) R + b mod NS + q NS], as in the register scheme.
-template <int L, int NS, bool INV>
-__device__ __forceinline__ void lds_stages(float2* src, float2* dst, int j, const float2* __restrict__ table,
-                                           int step) {
+template <int L, int P, int NS, int OFF, bool INV>
+__device__ __forceinline__ void lds_stages(float2* src, float2* dst, int j, const LineTwiddles<L, P>& tw) {
     if constexpr (NS < L) {
         constexpr int T = lds_threads(L);
         constexpr int R = lds_stage_radix(L, NS);
@@ -520,7 +566,12 @@ __device__ __forceinline__ void lds_stages(float2* src, float2* dst, int j, cons
                 if constexpr (NS > 1) {
 #pragma unroll
                     for (int q = 1; q < R; ++q) {
-                        float2 w = table[q * k * (L / (NS * R)) * step];
+                        float2 w;
+                        if constexpr (LineTwiddles<L, P>::PRELOAD) {
+                            w = tw.w[OFF + m * (R - 1) + (q - 1)];
+                        } else {
+                            w = tw.table[q * k * (L / (NS * R)) * tw.step];
+                        }
                         if constexpr (INV) w.y = -w.y;
                         x[q] = cmul(x[q], w);
                     }
@@ -532,7 +583,7 @@ __device__ __forceinline__ void lds_stages(float2* src, float2* dst, int j, cons
             }
         }
         __syncthreads();
-        lds_stages<L, NS * R, INV>(dst, src, j, table, step);
+        lds_stages<L, P, NS * R, (NS > 1 ? OFF + ROUNDS * (R - 1) : OFF), INV>(dst, src, j, tw);
     }
 }
 
@@ -541,13 +592,13 @@ __device__ __forceinline__ void lds_stages(float2* src, float2* dst, int j, cons
 // transform may reuse both buffers.
 template <int L, int P, bool INV>
 __device__ __forceinline__ void fft_line_lds(float2 (&v)[P], int j, float2* a, float2* b,
-                                             const float2* __restrict__ table, int step) {
+                                             const LineTwiddles<L, P>& tw) {
     constexpr int T = lds_threads(L);
     static_assert(T * P == L, "LDS-mode lines hold L / T points per thread");
 #pragma unroll
     for (int t = 0; t < P; ++t) a[j + T * t] = v[t];
     __syncthreads();
-    lds_stages<L, 1, INV>(a, b, j, table, step);
+    lds_stages<L, P, 1, 0, INV>(a, b, j, tw);
     float2* res = (lds_num_stages(L) % 2 == 0) ? a : b;
 #pragma unroll
     for (int t = 0; t < P; ++t) v[t] = res[j + T * t];
@@ -563,7 +614,7 @@ __device__ __forceinline__ void fft_line(float2 (&v)[P], int j, float2* line, in
                                          const LineTwiddles<L, P>& tw) {
     if constexpr (lds_mode(L)) {
         static_assert(NBUF == 2, "LDS mode ping-pongs between two buffers");
-        fft_line_lds<L, P, INV>(v, j, line, line + stride, tw.table, tw.step);
+        fft_line_lds<L, P, INV>(v, j, line, line + stride, tw);
     } else {
         fft_stage<L, P, 1, 0, INV, NBUF, PAR>(v, j, line, stride, tw);
     }
