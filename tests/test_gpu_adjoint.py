@@ -103,3 +103,26 @@ def test_adam_steps_reduce_loss(pmb):
         opt.step()
     last = pmb.intensity_loss(p.detach(), it_d).sum().item()
     assert last < 0.5 * first
+
+
+def test_intensity_workload_16x512(pmb):
+    """The 16 x 512^2 intensity workload of the benchmark (its seeds and
+    target recipe): every loss against the oracle, gradients of sampled
+    entries (the oracle computes them one by one)."""
+    from paper_1302_0120_amd import synth as sy
+    it, ph = sy.intensity_problems()
+    it = it.astype(np.float64)
+    it = (it * (it.shape[1] * it.shape[2] / it.sum(axis=(1, 2), keepdims=True))).astype(np.float32)
+    n = it.shape[1]
+    plan = pmb.PhaseMask(n, n)
+    ph_d = torch.from_numpy(ph).cuda()
+    loss, saved = plan.intensity_loss_fwd(ph_d, torch.from_numpy(it).cuda())
+    gl = torch.ones(it.shape[0], dtype=torch.float64, device="cuda")
+    grad = plan.intensity_loss_bwd(ph_d, saved, gl).cpu().numpy()
+    loss = loss.cpu().numpy()
+    for b in range(it.shape[0]):
+        ref_l = gs.intensity_loss(ph[b], it[b])
+        assert abs(loss[b] - ref_l) / ref_l <= 1e-5, (b, loss[b], ref_l)
+    for b in (0, 7, 15):
+        ref_g = gs.intensity_loss_grad(ph[b], it[b])
+        assert np.linalg.norm(grad[b] - ref_g) / np.linalg.norm(ref_g) <= 1e-4, b
