@@ -73,6 +73,12 @@ typedef enum {
                                    replaying a captured HIP graph           */
 #define PM_FLAG_NO_TUNE 0x2u    /* batched plans: use FFT schedule 0 instead
                                    of timing the schedules at creation      */
+#define PM_FLAG_VALIDATE 0x4u   /* one-mask plans: before each call check the
+                                   inputs on the device (target >= 0, finite,
+                                   not all zero; phases finite; illumination
+                                   >= 0, finite, not all zero) and return
+                                   PM_EINVAL if a check fails.  Synchronises
+                                   the handle's stream on every call.       */
 
 /*
  * Create a plan for masks of height x width pixels (Sec. II: n_y = height,

@@ -52,6 +52,7 @@ _SIGNATURES = {
 
 PM_FLAG_NO_GRAPH = 0x1
 PM_FLAG_NO_TUNE = 0x2
+PM_FLAG_VALIDATE = 0x4
 
 STATUS = {0: "PM_OK", -1: "PM_EINVAL", -2: "PM_EUNSUPPORTED", -3: "PM_ENOMEM",
           -4: "PM_EDEVICE", -5: "PM_ESTATE"}

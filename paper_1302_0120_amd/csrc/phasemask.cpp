@@ -133,6 +133,7 @@ struct pm_plan {
     float* illum = nullptr;            // illumination amplitude p, strip-tiled, on first use
     double* pn2 = nullptr;             // ||p||^2 on the device
     bool illum_on = false;             // solves use p (else p = 1)
+    int* vflags = nullptr;             // PM_FLAG_VALIDATE: two check words on the device
     double* part = nullptr;
     size_t part_entries = 0;           // capacity of `part` in history entries
     pm::PmIo* io = nullptr;
@@ -185,6 +186,7 @@ void free_plan(pm_plan* h) {
     (void)hipFree(h->Z);
     (void)hipFree(h->illum);
     (void)hipFree(h->pn2);
+    (void)hipFree(h->vflags);
     (void)hipFree(h->part);
     (void)hipFree(h->io);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -265,6 +267,23 @@ pm::ColParams col_params(pm_plan* h, double* part) {
         hipError_t e_ = (expr);                     \
         if (e_ != hipSuccess) return fail_hip(e_, what); \
     } while (0)
+
+// PM_FLAG_VALIDATE: checks `n` floats at x on the device (sign only when
+// `nonneg`; all zero is an error only when `need_nonzero`) and waits for the
+// result.  `what` names the argument in the error message.
+pm_status validate_input(pm_plan* h, const float* x, bool nonneg, bool need_nonzero, const char* what) {
+    if ((h->flags & PM_FLAG_VALIDATE) == 0 || x == nullptr) return PM_OK;
+    PM_TRY(hipMemsetAsync(h->vflags, 0, 2 * sizeof(int), h->stream), "hipMemsetAsync(check)");
+    PM_TRY(pm::launch_validate(x, h->N, nonneg, h->vflags, h->stream), "input check");
+    int f[2] = {0, 0};
+    PM_TRY(hipMemcpyAsync(f, h->vflags, sizeof(f), hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync(check)");
+    PM_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize(check)");
+    if (f[0] & 2) return fail(PM_EINVAL, std::string(what) + " has a non-finite entry");
+    if (f[0] & 1) return fail(PM_EINVAL, std::string(what) + " has a negative entry");
+    if (need_nonzero && f[1] == 0) return fail(PM_EINVAL, std::string(what) + " is all zero");
+    return PM_OK;
+}
+
 
 // Target normalisation + tiling (the rescaled m used by every column pass).
 pm_status enqueue_target(pm_plan* h, hipStream_t s) {
@@ -652,7 +671,7 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
     if (len_slot(height) < 0 || len_slot(width) < 0)
         return fail(PM_EUNSUPPORTED,
                     "height and width must each be a power of two in [16, 4096], 600, 800, 1080 or 1920");
-    if ((flags & ~PM_FLAG_NO_GRAPH) != 0) return fail(PM_EINVAL, "unknown flag bits");
+    if ((flags & ~(PM_FLAG_NO_GRAPH | PM_FLAG_VALIDATE)) != 0) return fail(PM_EINVAL, "unknown flag bits");
     pm_plan* h = new (std::nothrow) pm_plan;
     if (h == nullptr) return fail(PM_ENOMEM, "host allocation failed");
     h->H = height;
@@ -694,6 +713,8 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
         return bail(e, "hipMemcpy(twiddles)");
     if ((e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess)
         return bail(e, "hipStreamCreate");
+    if ((flags & PM_FLAG_VALIDATE) != 0 && (e = hipMalloc(&h->vflags, 2 * sizeof(int))) != hipSuccess)
+        return bail(e, "hipMalloc(check)");
     *out = h;
     return PM_OK;
 }
@@ -718,6 +739,7 @@ pm_status phasemask_set_illumination(pm_handle h, const float* illumination) {
     if (illumination != nullptr && misaligned(illumination, 16))
         return fail(PM_EINVAL, "illumination must be 16-byte aligned");
     const bool on = illumination != nullptr;
+    if ((st = validate_input(h, illumination, true, true, "illumination")) != PM_OK) return st;
     if (on != h->illum_on) {
         // Captured graphs hold the kernels of the other case.
         hipError_t e = hipStreamSynchronize(h->stream);
@@ -761,6 +783,8 @@ pm_status phasemask_solve(pm_handle h, const float* target_amplitude, const floa
     const bool hist = err_history != nullptr;
     if (hist && overlaps(err_history, (2 * (size_t)n_iter + 1) * sizeof(double), target_amplitude, nb))
         return fail(PM_EINVAL, "err_history overlaps the target");
+    if ((st = validate_input(h, target_amplitude, true, true, "target")) != PM_OK) return st;
+    if ((st = validate_input(h, init_phase, false, false, "init_phase")) != PM_OK) return st;
     st = ensure_partials(h, 2 * (size_t)n_iter + 1);
     if (st != PM_OK) return st;
     pm::PmIo io{target_amplitude, init_phase, out_phase, err_history};
@@ -784,6 +808,8 @@ pm_status phasemask_solve_raar(pm_handle h, const float* target_amplitude, const
     const bool hist = err_history != nullptr;
     if (hist && overlaps(err_history, ((size_t)n_iter + 1) * sizeof(double), target_amplitude, nb))
         return fail(PM_EINVAL, "err_history overlaps the target");
+    if ((st = validate_input(h, target_amplitude, true, true, "target")) != PM_OK) return st;
+    if ((st = validate_input(h, init_phase, false, false, "init_phase")) != PM_OK) return st;
     st = ensure_partials(h, 2 * (size_t)n_iter + 1);
     if (st != PM_OK) return st;
     if (h->Z == nullptr) {
@@ -806,6 +832,8 @@ pm_status phasemask_error(pm_handle h, const float* target_amplitude, const floa
     if (!target_amplitude || !phase || !errors) return fail(PM_EINVAL, "null array argument");
     if (misaligned(target_amplitude, 16)) return fail(PM_EINVAL, "target must be 16-byte aligned");
     if (misaligned(phase, 4) || misaligned(errors, 8)) return fail(PM_EINVAL, "misaligned array argument");
+    if ((st = validate_input(h, target_amplitude, true, true, "target")) != PM_OK) return st;
+    if ((st = validate_input(h, phase, false, false, "phase")) != PM_OK) return st;
     st = ensure_partials(h, 2);
     if (st != PM_OK) return st;
     pm::PmIo io{target_amplitude, phase, nullptr, errors};
@@ -1024,6 +1052,7 @@ pm_status phasemask_initial_phase(pm_handle h, const float* target_amplitude, do
     if (!(t_dark >= 0.0 && t_dark < 1.0)) return fail(PM_EINVAL, "t_dark must be in [0, 1)");
     if (overlaps(out_phase, (size_t)h->N * sizeof(float), target_amplitude, (size_t)h->N * sizeof(float)))
         return fail(PM_EINVAL, "out_phase overlaps the target");
+    if ((st = validate_input(h, target_amplitude, true, true, "target")) != PM_OK) return st;
     hipStream_t s = h->stream;
     pm::PmIo io{target_amplitude, nullptr, out_phase, nullptr};
     PM_TRY(pm::launch_set_io(h->io, io, s), "set io");
@@ -1048,6 +1077,8 @@ pm_status phasemask_physical_error(pm_handle h, const float* target_amplitude, c
     if (misaligned(target_amplitude, 16) || misaligned(phase, 4) || misaligned(errors, 8))
         return fail(PM_EINVAL, "misaligned array argument");
     if (!(t_lit > 0.0) || !(t_dark >= 0.0 && t_dark < 1.0)) return fail(PM_EINVAL, "need t_lit > 0, 0 <= t_dark < 1");
+    if ((st = validate_input(h, target_amplitude, true, true, "target")) != PM_OK) return st;
+    if ((st = validate_input(h, phase, false, false, "phase")) != PM_OK) return st;
     const size_t nblk = ((size_t)h->N / 4 + 255) / 256;
     st = ensure_partials(h, 1 + (2 * nblk + h->stride - 1) / h->stride);
     if (st != PM_OK) return st;

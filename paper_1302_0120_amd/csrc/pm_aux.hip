@@ -125,6 +125,22 @@ k_finalize(const double* part, int stride, int n_col, int n_row, double invN,
     }
 }
 
+// Input checks (PM_FLAG_VALIDATE): flags[0] gets bit 1 for a negative
+// entry (when `nonneg`), bit 2 for a non-finite one; flags[1] is set when
+// any entry is non-zero.  Plain vector atomics; flags are cleared by the
+// host before the launch.
+__global__ void __launch_bounds__(kAuxThreads) k_validate(const float* x, int n, int nonneg, int* flags) {
+    int bad = 0, nz = 0;
+    for (int i = blockIdx.x * kAuxThreads + threadIdx.x; i < n; i += gridDim.x * kAuxThreads) {
+        const float v = x[i];
+        if (!isfinite(v)) bad |= 2;
+        else if (nonneg && v < 0.0f) bad |= 1;
+        if (v != 0.0f) nz = 1;
+    }
+    if (bad) atomicOr(&flags[0], bad);
+    if (nz) atomicOr(&flags[1], 1);
+}
+
 // out = atan2(sin phi, cos phi): the phase of u^0 for a zero-iteration solve.
 __global__ void __launch_bounds__(kAuxThreads) k_wrap_phase(const PmIo* io, int n) {
     const int i = blockIdx.x * kAuxThreads + threadIdx.x;
@@ -403,6 +419,11 @@ hipError_t launch_illum_prep(const float* p, int H, int W, double* part, int gri
     if (e != hipSuccess) return e;
     const int tgrid = (H * (W / 4) + kAuxThreads - 1) / kAuxThreads;
     k_tile_plain<<<tgrid, kAuxThreads, 0, s>>>(p, H, W, illum, part, grid, pn2);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const float* x, int n, bool nonneg, int* flags, hipStream_t s) {
+    k_validate<<<256, kAuxThreads, 0, s>>>(x, n, nonneg ? 1 : 0, flags);
     return hipGetLastError();
 }
 

@@ -280,6 +280,8 @@ hipError_t launch_finalize(const double* part, int stride, int n_col, int n_row,
 hipError_t launch_illum_prep(const float* p, int H, int W, double* part, int grid, float* illum,
                              double* pn2, hipStream_t s);
 hipError_t launch_wrap_phase(const PmIo* io, int n, hipStream_t s);
+// Input check of PM_FLAG_VALIDATE over n floats (see k_validate).
+hipError_t launch_validate(const float* x, int n, bool nonneg, int* flags, hipStream_t s);
 // Per-work-group maxima of a float array (n a multiple of 4).
 hipError_t launch_max_partial(const float* x, int n, float* part, int grid, hipStream_t s);
 // Physical error of Eq. 8 (E_lit, E_dark) from the strip-tiled power

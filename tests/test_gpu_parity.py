@@ -274,3 +274,65 @@ def test_all_zero_target_is_defined(pmb):
     assert torch.count_nonzero(ph).item() == 0
     hg = hist.cpu().numpy()
     assert np.all(np.abs(hg - 1.0) <= 1e-6), hg
+
+
+def test_validate_flag(pmb):
+    """PM_FLAG_VALIDATE rejects a negative, non-finite or all-zero target, a
+    non-finite phase and a bad illumination with PM_EINVAL before any work;
+    valid inputs give bitwise the results of a plan without the flag."""
+    h, w = 64, 64
+    rng = np.random.default_rng(31)
+    m = synth.spot_amplitude(h, w, 5, 2.0, 0.5, 1.0, rng)
+    phi0 = synth.uniform_phase(h, w, rng)
+    plan = pmb.PhaseMask(h, w, flags=pmb.PM_FLAG_VALIDATE)
+    ref = pmb.PhaseMask(h, w)
+    a, ha = plan.solve(_dev(m), _dev(phi0), 4)
+    b, hb = ref.solve(_dev(m), _dev(phi0), 4)
+    assert torch.equal(a, b) and torch.equal(ha, hb)
+    bad = m.copy()
+    bad[3, 5] = -1.0
+    nan_phase = phi0.copy()
+    nan_phase[7, 7] = np.nan
+    inf_target = m.copy()
+    inf_target[0, 1] = np.inf
+    cases = [
+        (lambda: plan.solve(_dev(bad), _dev(phi0), 2), b"negative"),
+        (lambda: plan.solve(_dev(inf_target), _dev(phi0), 2), b"non-finite"),
+        (lambda: plan.solve(torch.zeros(h, w, device="cuda"), _dev(phi0), 2), b"all zero"),
+        (lambda: plan.solve(_dev(m), _dev(nan_phase), 2), b"non-finite"),
+        (lambda: plan.error(_dev(bad), _dev(phi0)), b"negative"),
+        (lambda: plan.solve_raar(_dev(m), _dev(nan_phase), 2, 0.5), b"non-finite"),
+        (lambda: plan.initial_phase(_dev(bad)), b"negative"),
+        (lambda: plan.physical_error(_dev(m), _dev(nan_phase)), b"non-finite"),
+        (lambda: plan.set_illumination(-torch.ones(h, w, device="cuda")), b"negative"),
+        (lambda: plan.set_illumination(torch.zeros(h, w, device="cuda")), b"all zero"),
+    ]
+    for fn, why in cases:
+        with pytest.raises(pmb.PhaseMaskError) as ei:
+            fn()
+        assert ei.value.status == -1
+        assert why in pmb.lib.phasemask_last_error()
+    c, _ = plan.solve(_dev(m), _dev(phi0), 4)   # still usable
+    assert torch.equal(a, c)
+
+
+def test_resume_from_returned_phase(pmb):
+    """Resuming from a returned phase (the whole state of the method is the
+    phase of u): solve(a + b) and solve(b, init = solve(a)) agree to the
+    FP32 round trip of atan2 and sincos; the resumed history starts at the
+    combined run's entry 2a."""
+    h = w = 256
+    rng = np.random.default_rng(41)
+    m = synth.spot_amplitude(h, w, 20, 2.0, 0.5, 1.0, rng)
+    phi0 = synth.uniform_phase(h, w, rng)
+    plan = pmb.PhaseMask(h, w)
+    md = _dev(m)
+    full, hf = plan.solve(md, _dev(phi0), 12)
+    full, hf = full.clone(), hf.clone().cpu().numpy()
+    mid, _ = plan.solve(md, _dev(phi0), 5)
+    rest, hr = plan.solve(md, mid.clone(), 7)
+    hr = hr.cpu().numpy()
+    u_full = np.exp(1j * full.cpu().numpy().astype(np.float64))
+    u_rest = np.exp(1j * rest.cpu().numpy().astype(np.float64))
+    assert _rel_l2(u_rest, u_full) <= 1e-4
+    assert np.max(np.abs(hr - hf[10:]) / hf[10:]) <= 1e-5
