@@ -42,6 +42,23 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def environment(torch):
+    """Where the numbers were measured."""
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    prop = torch.cuda.get_device_properties(0)
+    return {"gpu": prop.name, "arch": getattr(prop, "gcnArchName", "unknown"),
+            "compute_units": prop.multi_processor_count, "hip": torch.version.hip,
+            "torch": torch.__version__, "host_cpu": cpu, "host_threads": os.cpu_count()}
+
+
 def cpu_baseline(m, phi0, n_iter_sample):
     """The FP64 oracle, as it stands, on a bounded sample of the workload."""
     from oracle import gs
@@ -100,6 +117,7 @@ def bench_batched(torch, binding, synth, steps):
         "algorithmic_gbs": gbs,
         "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
         "max_final_error": float(err.max().item()),
+        "schedule": bp.schedule,
     }
 
 
@@ -358,6 +376,7 @@ def main():
         "passes_us": {"column": col_ms * 1e3, "row": row_ms * 1e3},
         "solve_algorithmic_gbs": solve_gbs,
         "final_fourier_error": final_ef,
+        "env": environment(torch),
     }
     if not args.no_batched:
         line["batched"] = bench_batched(torch, binding, synth, args.batched_steps)

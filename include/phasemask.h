@@ -87,6 +87,8 @@ typedef enum {
  * pixel plus 16 bytes per pixel-iteration-row of partials) on the current
  * device.  `stream` is a hipStream_t (NULL = the null stream) used by every
  * later call until phasemask_set_stream changes it.
+ * With the environment variable PHASEMASK_LOG set, the plan's transform
+ * schemes and work-group counts are printed to stderr.
  * Errors: PM_EINVAL if out is NULL; PM_EUNSUPPORTED for sizes outside the
  * supported set; PM_ENOMEM, PM_EDEVICE.  On error *out is set to NULL.
  */

@@ -715,6 +715,17 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
         return bail(e, "hipStreamCreate");
     if ((flags & PM_FLAG_VALIDATE) != 0 && (e = hipMalloc(&h->vflags, 2 * sizeof(int))) != hipSuccess)
         return bail(e, "hipMalloc(check)");
+    if (std::getenv("PHASEMASK_LOG") != nullptr) {
+        auto line = [](int L) {
+            std::ostringstream os;
+            os << L << " points: " << (pm::lds_mode(L) ? "LDS" : "register") << " scheme, "
+               << pm::points_per_thread(L) << " points x " << L / pm::points_per_thread(L) << " threads";
+            return os.str();
+        };
+        std::fprintf(stderr, "phasemask plan %dx%d: rows %s, %d work-groups of %d rows; columns %s, %d work-groups; "
+                     "workspace %zu bytes\n", height, width, line(width).c_str(), h->nwg_row,
+                     pm::row_lines(width), line(height).c_str(), h->nwg_col, h->ws_bytes);
+    }
     *out = h;
     return PM_OK;
 }
