@@ -237,10 +237,12 @@ pm_status phasemask_fft2(pm_handle h, const void* in, void* out, int inverse);
  * runs as one column-pass launch and one row-pass launch over the masks of
  * a group; the whole solve is one captured graph.  Groups: consecutive
  * masks (largest first) whose working sets (12 bytes per pixel) add up to
- * at most 224 MiB, so that a group stays in the last-level cache while it
- * runs all its iterations before the next group starts; the environment
- * variable PHASEMASK_GROUP_MB=<m> sets the budget at creation (0 = one
- * group).  Results do not depend on the grouping.
+ * at most 48 MiB; a group runs all its iterations before the next group of
+ * its chain, and the groups are spread over 4 chains of launches that run
+ * concurrently (balanced by bytes), so that the chains' working sets stay
+ * in the last-level cache together.  The environment variables
+ * PHASEMASK_GROUP_MB=<m> (0 = one group) and PHASEMASK_CHAINS=<1..8> set
+ * these at creation.  Results do not depend on the grouping or chains.
  *   heights, widths   HOST arrays of `count` sizes, each a power of two in
  *                     [64, 1024] (else PM_EUNSUPPORTED).
  * FFT schedules: the batched passes have several compiled schedules (points
@@ -253,7 +255,8 @@ pm_status phasemask_fft2(pm_handle h, const void* in, void* out, int inverse);
  * `stream` (synchronised) and the fastest is kept.  PM_FLAG_NO_TUNE selects
  * schedule 0 without timing.  PHASEMASK_LOG=1 prints the timings to stderr.
  * Errors: PM_EINVAL for NULL arguments, count < 1 or an out-of-range
- * PHASEMASK_SCHEDULE or PHASEMASK_GROUP_MB; PM_ENOMEM; PM_EDEVICE.
+ * PHASEMASK_SCHEDULE, PHASEMASK_GROUP_MB or PHASEMASK_CHAINS; PM_ENOMEM;
+ * PM_EDEVICE.
  * A batched handle works with phasemask_solve_batched, phasemask_set_stream,
  * phasemask_workspace_bytes and phasemask_destroy; other entry points
  * return PM_ESTATE for it.

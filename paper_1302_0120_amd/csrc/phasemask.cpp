@@ -100,7 +100,10 @@ constexpr int kNormGrid = 64;          // work-groups of the target-norm partial
 // last-level cache of an MI355X; measured on the 64-mask workload (385 MB
 // of iterates and targets) 8% faster than one group, while groups of
 // 32-160 MiB lose more to smaller launches than they gain in cache hits.
-constexpr size_t kBatchGroupBytes = (size_t)224 << 20;
+constexpr size_t kBatchGroupBytes = (size_t)48 << 20;
+// Default number of concurrent chains the groups are spread over
+// (PHASEMASK_CHAINS overrides, 1..8).
+constexpr int kBatchChains = 4;
 constexpr size_t kMaxCachedGraphs = 8;
 
 }  // namespace
@@ -111,6 +114,8 @@ constexpr size_t kMaxCachedGraphs = 8;
 // while all iterations run.
 struct pm_batch_group {
     int c0, c1, r0, r1;
+    size_t bytes;  // working set of the group's masks
+    int chain;     // chain of launches the group runs on
 };
 
 struct pm_plan {
@@ -157,6 +162,12 @@ struct pm_plan {
     size_t batch_ws_bytes = 0;
     size_t group_bytes = 0;            // cache budget of one group (0 = one group)
     std::vector<pm_batch_group> groups;
+    // Groups are spread over `chains` independent chains of launches (the
+    // caller's stream plus side streams joined by events), which a graph
+    // runs concurrently.
+    int chains = 1;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> fork_ev, join_ev;
 };
 
 namespace {
@@ -168,6 +179,9 @@ void drop_graphs(pm_plan* h) {
 
 void free_plan(pm_plan* h) {
     drop_graphs(h);
+    for (hipStream_t x : h->side) (void)hipStreamDestroy(x);
+    for (hipEvent_t x : h->fork_ev) (void)hipEventDestroy(x);
+    for (hipEvent_t x : h->join_ev) (void)hipEventDestroy(x);
     (void)hipFree(h->batch_ws);
     (void)hipFree(h->masks);
     (void)hipFree(h->col_tasks);
@@ -452,14 +466,27 @@ pm_status enqueue_batch(pm_plan* h, hipStream_t s, int n_iter, bool err) {
     PM_TRY(pm::launch_batch_tile(h->bio, h->masks, h->prep_tasks, h->n_prep_tasks, h->mask_prep0, h->part_m, s),
            "batch tile");
     PM_TRY(batch_row(h, pm::ROW_INIT, s), "batch row init");
-    // All iterations of one group of masks before the next group, so that
-    // the group's working set stays cache-resident across iterations.
+    // All iterations of one group of masks before the next group of the same
+    // chain, so that the group's working set stays cache-resident across its
+    // iterations; groups alternate between the chains, which run
+    // concurrently (fork and join through events).
+    const int chains = std::min<int>(h->chains, (int)h->groups.size());
+    for (int c = 1; c < chains; ++c) {
+        PM_TRY(hipEventRecord(h->fork_ev[c - 1], s), "hipEventRecord(fork)");
+        PM_TRY(hipStreamWaitEvent(h->side[c - 1], h->fork_ev[c - 1], 0), "hipStreamWaitEvent(fork)");
+    }
     for (const pm_batch_group& g : h->groups) {
+        const int c = g.chain < chains ? g.chain : 0;
+        hipStream_t cs = c == 0 ? s : h->side[c - 1];
         for (int nu = 0; nu < n_iter; ++nu) {
-            PM_TRY(batch_col(h, pm::COL_ITER_NE, s, nullptr, nullptr, g.c0, g.c1), "batch column pass");
+            PM_TRY(batch_col(h, pm::COL_ITER_NE, cs, nullptr, nullptr, g.c0, g.c1), "batch column pass");
             const int mode = nu < n_iter - 1 ? pm::ROW_ITER_NE : (err ? pm::ROW_LAST_FWD_NE : pm::ROW_LAST_NE);
-            PM_TRY(batch_row(h, mode, s, nullptr, nullptr, g.r0, g.r1), "batch row pass");
+            PM_TRY(batch_row(h, mode, cs, nullptr, nullptr, g.r0, g.r1), "batch row pass");
         }
+    }
+    for (int c = 1; c < chains; ++c) {
+        PM_TRY(hipEventRecord(h->join_ev[c - 1], h->side[c - 1]), "hipEventRecord(join)");
+        PM_TRY(hipStreamWaitEvent(s, h->join_ev[c - 1], 0), "hipStreamWaitEvent(join)");
     }
     if (err) {
         PM_TRY(batch_col(h, pm::COL_ERR, s), "batch column error");
@@ -515,14 +542,27 @@ std::vector<pm_batch_group> batch_groups(const BatchLayout& l, size_t budget) {
         const pm::BatchMask& mk = l.masks[i];
         const size_t b = (size_t)mk.H * mk.W * (sizeof(float2) + sizeof(float));
         if (g.empty() || (budget > 0 && bytes + b > budget)) {
-            g.push_back(pm_batch_group{mk.col_wg0, mk.col_wg0, l.row0[i], l.row0[i]});
+            g.push_back(pm_batch_group{mk.col_wg0, mk.col_wg0, l.row0[i], l.row0[i], 0, 0});
             bytes = 0;
         }
         g.back().c1 = mk.col_wg0 + mk.col_wgs;
         g.back().r1 = l.row0[i] + l.rows[i];
+        g.back().bytes += b;
         bytes += b;
     }
     return g;
+}
+
+// Spreads the groups over `chains` chains, each group (largest first, in the
+// order they were formed) to the chain with the fewest bytes so far, so the
+// concurrent chains finish at about the same time.
+void assign_chains(std::vector<pm_batch_group>& g, int chains) {
+    std::vector<size_t> load((size_t)std::max(chains, 1), 0);
+    for (pm_batch_group& x : g) {
+        const size_t c = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+        x.chain = (int)c;
+        load[c] += x.bytes;
+    }
 }
 
 hipError_t upload_layout(pm_plan* h, const BatchLayout& l) {
@@ -534,6 +574,7 @@ hipError_t upload_layout(pm_plan* h, const BatchLayout& l) {
     h->n_col_tasks = (int)l.col.size();
     h->n_row_tasks = (int)l.row.size();
     h->groups = batch_groups(l, h->group_bytes);
+    assign_chains(h->groups, h->chains);
     return e;
 }
 
@@ -912,6 +953,15 @@ pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights
         }
         h->group_bytes = (size_t)mb << 20;
     }
+    h->chains = kBatchChains;
+    if (const char* c = std::getenv("PHASEMASK_CHAINS"); c != nullptr && c[0] != '\0') {
+        const long n = std::atol(c);
+        if (n < 1 || n > 8) {
+            delete h;
+            return fail(PM_EINVAL, "PHASEMASK_CHAINS out of range");
+        }
+        h->chains = (int)n;
+    }
     auto bail = [&](hipError_t e, const char* what) {
         pm_status st = fail_hip(e, what);
         free_plan(h);
@@ -983,6 +1033,16 @@ pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights
     if ((e = upload_layout(h, layouts[h->sched])) != hipSuccess) return bail(e, "hipMemcpy(layout)");
     if ((e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess)
         return bail(e, "hipStreamCreate");
+    for (int c = 1; c < h->chains; ++c) {
+        hipStream_t x = nullptr;
+        hipEvent_t f = nullptr, j = nullptr;
+        if ((e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking)) != hipSuccess) return bail(e, "hipStreamCreate");
+        h->side.push_back(x);
+        if ((e = hipEventCreateWithFlags(&f, hipEventDisableTiming)) != hipSuccess) return bail(e, "hipEventCreate");
+        h->fork_ev.push_back(f);
+        if ((e = hipEventCreateWithFlags(&j, hipEventDisableTiming)) != hipSuccess) return bail(e, "hipEventCreate");
+        h->join_ev.push_back(j);
+    }
     h->ws_bytes = off + npart * sizeof(double) + prep.size() * (sizeof(double) + sizeof(pm::BatchTask)) +
                   (max_col + max_row) * sizeof(pm::BatchTask) + count * (sizeof(pm::BatchMask) + sizeof(int)) +
                   sizeof(pm::BatchIo) + pm::kBatchMaxLen * sizeof(float2);

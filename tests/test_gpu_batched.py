@@ -193,18 +193,29 @@ def test_tuner_picks_and_caches(pmb, monkeypatch, tmp_path):
 
 
 def test_cache_groups_do_not_change_results(pmb, monkeypatch):
-    """Masks iterated in cache-sized groups (here one group per mask) give
-    bitwise the results of one group with all masks."""
+    """Masks iterated in cache-sized groups (here one group per mask), also
+    spread over concurrent chains, give bitwise the results of one group
+    with all masks."""
     shapes = [(256, 256), (64, 512), (512, 128), (128, 128)]
     probs = _problems(shapes, 900)
     targets = [_dev(m) for m, _ in probs]
     phases = [_dev(p) for _, p in probs]
     monkeypatch.setenv("PHASEMASK_GROUP_MB", "0")
+    monkeypatch.setenv("PHASEMASK_CHAINS", "1")
     a, ea = pmb.BatchedPhaseMask(shapes).solve(targets, phases, 7)
     monkeypatch.setenv("PHASEMASK_GROUP_MB", "1")
     b, eb = pmb.BatchedPhaseMask(shapes).solve(targets, phases, 7)
     assert all(torch.equal(x, y) for x, y in zip(a, b)) and torch.equal(ea, eb)
-    monkeypatch.setenv("PHASEMASK_GROUP_MB", "-3")
-    with pytest.raises(pmb.PhaseMaskError) as ei:
-        pmb.BatchedPhaseMask(shapes)
-    assert ei.value.status == -1
+    # the same groups spread over three concurrent chains, graph and eager
+    monkeypatch.setenv("PHASEMASK_CHAINS", "3")
+    c, ec = pmb.BatchedPhaseMask(shapes).solve(targets, phases, 7)
+    assert all(torch.equal(x, y) for x, y in zip(a, c)) and torch.equal(ea, ec)
+    d, ed = pmb.BatchedPhaseMask(shapes, flags=pmb.PM_FLAG_NO_GRAPH).solve(targets, phases, 7)
+    assert all(torch.equal(x, y) for x, y in zip(a, d)) and torch.equal(ea, ed)
+    for var, val in (("PHASEMASK_GROUP_MB", "-3"), ("PHASEMASK_CHAINS", "0"), ("PHASEMASK_CHAINS", "9")):
+        monkeypatch.setenv(var, val)
+        with pytest.raises(pmb.PhaseMaskError) as ei:
+            pmb.BatchedPhaseMask(shapes)
+        assert ei.value.status == -1
+        monkeypatch.setenv("PHASEMASK_GROUP_MB", "1")
+        monkeypatch.setenv("PHASEMASK_CHAINS", "3")
