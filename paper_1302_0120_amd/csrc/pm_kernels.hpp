@@ -274,7 +274,11 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
         for (int t = 0; t < P; ++t) {
             float sn, cs;
             sincosf(phase_in[natural(t)], &sn, &cs);
-            v[t] = ILLUM ? make_float2(pil[t] * cs, pil[t] * sn) : make_float2(cs, sn);
+            if constexpr (ILLUM) {
+                v[t] = make_float2(pil[t] * cs, pil[t] * sn);
+            } else {
+                v[t] = make_float2(cs, sn);
+            }
         }
     } else if constexpr ((MODE & RIN_NAT) != 0) {
 #pragma unroll
@@ -313,7 +317,9 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
             const float r = nz ? __builtin_amdgcn_rsqf(a2) : 0.0f;
             const float2 e = nz ? make_float2(w.x * r, w.y * r) : make_float2(1.0f, 0.0f);
             if constexpr (ERR) {
-                const double d = (double)(a2 * r) - (ILLUM ? (double)pil[t] : 1.0);
+                double p = 1.0;
+                if constexpr (ILLUM) p = (double)pil[t];
+                const double d = (double)(a2 * r) - p;
                 acc = fma(d, d, acc);
             }
             if constexpr (ILLUM) {
