@@ -215,13 +215,24 @@ pm_status check_handle(pm_plan* h, bool batched = false) {
     return PM_OK;
 }
 
-// exp(-2 pi i k / L), k < L, in double, rounded once to float.
-std::vector<float2> twiddles(int L) {
-    std::vector<float2> t(L);
+// Staged twiddle table of the line plan (L, P) (layout: twiddle_block in
+// pm_fft.hpp): entry (q - 1) NS + k of the stage at NS with radix R is
+// exp(-2 pi i q k / (NS R)) = exp(-2 pi i e / L) with e = q k L / (NS R) < L,
+// evaluated in double and rounded once to float.
+std::vector<float2> staged_twiddles(int L, int P) {
+    std::vector<float2> t(std::max(1, pm::twiddle_entries(L, P)), make_float2(1.0f, 0.0f));
     const double two_pi = 6.283185307179586476925286766559;
-    for (int k = 0; k < L; ++k) {
-        const double a = two_pi * (double)k / (double)L;
-        t[k] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
+    for (int ns = 1; ns < L; ns *= pm::line_stage_radix(L, P, ns)) {
+        const int R = pm::line_stage_radix(L, P, ns);
+        if (ns == 1) continue;
+        const int base = pm::twiddle_block(L, P, ns);
+        for (int q = 1; q < R; ++q) {
+            for (int k = 0; k < ns; ++k) {
+                const int e = q * k * (L / (ns * R));
+                const double a = two_pi * (double)e / (double)L;
+                t[base + (q - 1) * ns + k] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
+            }
+        }
     }
     return t;
 }
@@ -248,7 +259,6 @@ pm::RowParams row_params(pm_plan* h, double* part) {
     pm::RowParams r{};
     r.X = h->X;
     r.tw = h->twW;
-    r.tw_step = 1;
     r.io = h->io;
     r.part = part;
     r.H = h->H;
@@ -268,7 +278,6 @@ pm::ColParams col_params(pm_plan* h, double* part) {
     c.X = h->X;
     c.mhat = h->mhat;
     c.tw = h->twH;
-    c.tw_step = 1;
     c.part = part;
     c.W = h->W;
     c.invN = 1.0 / (double)h->N;
@@ -740,17 +749,18 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
     const size_t n = (size_t)h->N;
     if ((e = hipMalloc(&h->X, n * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(iterate)");
     if ((e = hipMalloc(&h->mhat, n * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc(target)");
-    if ((e = hipMalloc(&h->twW, width * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
-    if ((e = hipMalloc(&h->twH, height * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
+    const std::vector<float2> tw_w = staged_twiddles(width, pm::points_per_thread(width));
+    const std::vector<float2> tw_h = staged_twiddles(height, pm::points_per_thread(height));
+    if ((e = hipMalloc(&h->twW, tw_w.size() * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
+    if ((e = hipMalloc(&h->twH, tw_h.size() * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
     if ((e = hipMalloc(&h->part_m, kNormGrid * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(norm)");
     if ((e = hipMalloc(&h->part_mx, kNormGrid * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc(max)");
     if ((e = hipMalloc(&h->io, sizeof(pm::PmIo))) != hipSuccess) return bail(e, "hipMalloc(io)");
-    h->ws_bytes = n * (sizeof(float2) + sizeof(float)) + (size_t)(width + height) * sizeof(float2) +
+    h->ws_bytes = n * (sizeof(float2) + sizeof(float)) + (tw_w.size() + tw_h.size()) * sizeof(float2) +
                   kNormGrid * sizeof(double) + sizeof(pm::PmIo);
-    const std::vector<float2> tw_w = twiddles(width), tw_h = twiddles(height);
-    if ((e = hipMemcpy(h->twW, tw_w.data(), width * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = hipMemcpy(h->twW, tw_w.data(), tw_w.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
         return bail(e, "hipMemcpy(twiddles)");
-    if ((e = hipMemcpy(h->twH, tw_h.data(), height * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = hipMemcpy(h->twH, tw_h.data(), tw_h.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
         return bail(e, "hipMemcpy(twiddles)");
     if ((e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess)
         return bail(e, "hipStreamCreate");
@@ -1016,10 +1026,17 @@ pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights
     if ((e = hipMalloc(&h->part, npart * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(partials)");
     if ((e = hipMalloc(&h->part_m, prep.size() * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(norm)");
     if ((e = hipMalloc(&h->bio, sizeof(pm::BatchIo))) != hipSuccess) return bail(e, "hipMalloc(io)");
-    if ((e = hipMalloc(&h->tw_batch, pm::kBatchMaxLen * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
+    std::vector<float2> tw(pm::batch_twiddle_offset(pm::kBatchSchedules, 0));
+    for (int sc = 0; sc < pm::kBatchSchedules; ++sc) {
+        for (int l = pm::kBatchMinLen; l <= pm::kBatchMaxLen; l *= 2) {
+            const std::vector<float2> t = staged_twiddles(l, pm::batch_points(sc, l));
+            std::copy(t.begin(), t.begin() + pm::twiddle_entries(l, pm::batch_points(sc, l)),
+                      tw.begin() + pm::batch_twiddle_offset(sc, l));
+        }
+    }
+    if ((e = hipMalloc(&h->tw_batch, tw.size() * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
     h->part_entries = 1;
     h->stride = (int)npart;
-    const std::vector<float2> tw = twiddles(pm::kBatchMaxLen);
     if ((e = hipMemcpy(h->prep_tasks, prep.data(), prep.size() * sizeof(pm::BatchTask), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(h->mask_prep0, prep0.data(), count * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(h->tw_batch, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)

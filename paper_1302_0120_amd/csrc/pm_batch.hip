@@ -35,12 +35,12 @@ constexpr int batch_lds_floats2() {
 
 #define PM_COL_CASE(L)                                                                             \
     case L:                                                                                        \
-        a.tw_step = kBatchMaxLen / L;                                                              \
+        a.tw = p.tw + batch_twiddle_offset(SCHED, L);                                              \
         col_body<L, BatchShape<SCHED, L>::P, BatchShape<SCHED, L>::G, MODE>(a, task.first, slot, lds, red); \
         break;
 #define PM_ROW_CASE(L)                                                                             \
     case L:                                                                                        \
-        a.tw_step = kBatchMaxLen / L;                                                              \
+        a.tw = p.tw + batch_twiddle_offset(SCHED, L);                                              \
         row_body<L, BatchShape<SCHED, L>::P, BatchShape<SCHED, L>::G, MODE>(a, task.first, pin, pout, slot, \
                                                                            lds, red);              \
         break;
@@ -54,7 +54,6 @@ __global__ void __launch_bounds__(kBatchThreads) k_col_batch(BatchParams p) {
     ColParams a{};
     a.X = mk.X;
     a.mhat = mk.mhat;
-    a.tw = p.tw;
     a.W = mk.W;
     a.invN = 1.0 / ((double)mk.H * (double)mk.W);
     double* slot = p.part + blockIdx.x * red_slots(kBatchThreads);
@@ -76,7 +75,6 @@ __global__ void __launch_bounds__(kBatchThreads) k_row_batch(BatchParams p) {
     const BatchMask mk = p.masks[task.mask];
     RowParams a{};
     a.X = mk.X;
-    a.tw = p.tw;
     a.H = mk.H;
     const float* pin = nullptr;
     float* pout = nullptr;

@@ -98,8 +98,7 @@ constexpr int COL_POW = CIN_TILED | C_FWD | C_POW;
 
 struct RowParams {
     float2* X;             // tiled iterate
-    const float2* tw;      // twiddle table exp(-2 pi i k / (W tw_step))
-    int tw_step;
+    const float2* tw;      // staged twiddle table of the row plan (W, P)
     const PmIo* io;
     const float2* nat_in;  // natural-layout input (RIN_NAT)
     float2* nat_out;       // natural-layout output (ROUT_NAT)
@@ -115,8 +114,7 @@ struct RowParams {
 struct ColParams {
     float2* X;             // tiled iterate
     const float* mhat;     // tiled target divided by its 2-norm
-    const float2* tw;      // twiddle table exp(-2 pi i k / (H tw_step))
-    int tw_step;
+    const float2* tw;      // staged twiddle table of the column plan (H, P)
     const float2* nat_in;
     float2* nat_out;
     double* part;          // one Fourier-error partial per work-group
@@ -235,7 +233,7 @@ struct BatchIo {
 struct BatchParams {
     const BatchMask* masks;
     const BatchTask* tasks;          // one per work-group of this launch
-    const float2* tw;                // exp(-2 pi i k / kBatchMaxLen)
+    const float2* tw;                // staged twiddle tables, batch_twiddle_offset
     const BatchIo* io;
     double* part;                    // one partial per work-group (error passes)
 };

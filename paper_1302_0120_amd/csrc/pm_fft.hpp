@@ -27,7 +27,23 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
+#include "pm_common.h"
+
 namespace pm {
+
+// Pointer to element i of a device array, from a base pointer and a 32-bit
+// element offset.  The byte offset is formed in 32 bits and zero-extended,
+// which lets the compiler use the scalar-base form of the global memory
+// instructions (base in scalar registers, one 32-bit offset per lane)
+// instead of 64-bit address arithmetic on every lane.  Offsets stay below
+// 2^29 elements: the largest array indexed this way holds 4096^2 elements.
+template <class T>
+__device__ __forceinline__ T* elem_ptr(T* base, unsigned i) {
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + (size_t)(i * (unsigned)sizeof(T)));
+}
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -387,6 +403,40 @@ __host__ __device__ constexpr int twiddles_from(int L, int P, int NS) {
                          twiddles_from(L, P, NS * stage_radix(L, P, NS));
 }
 
+// Radix of the stage at sub-length NS in the scheme the length uses.
+__host__ __device__ constexpr int line_stage_radix(int L, int P, int NS) {
+    return lds_mode(L) ? lds_stage_radix(L, NS) : stage_radix(L, P, NS);
+}
+
+// Staged twiddle table of a line plan (L, P): one block per stage with
+// NS > 1, in stage order; the block of the stage at NS with radix R holds
+// (R - 1) NS entries, entry (q - 1) NS + k = exp(-2 pi i q k / (NS R)) for
+// q = 1 .. R - 1 and k = 0 .. NS - 1.  A wave's threads read consecutive k
+// for a fixed q, so each table read of a wave touches a few contiguous
+// cache lines instead of one line per lane.  twiddle_block gives the first
+// entry of the stage at NS (stages before it summed from `cur` on).
+__host__ __device__ constexpr int twiddle_block(int L, int P, int NS, int cur = 1) {
+    return cur >= NS ? 0
+                     : (cur > 1 ? (line_stage_radix(L, P, cur) - 1) * cur : 0) +
+                           twiddle_block(L, P, NS, cur * line_stage_radix(L, P, cur));
+}
+__host__ __device__ constexpr int twiddle_entries(int L, int P) { return twiddle_block(L, P, L); }
+
+// The batched plans keep the staged tables of every schedule and power-of-two
+// length in one buffer, schedule by schedule, lengths ascending; this is the
+// first entry of (schedule sched, length L), and with sched = kBatchSchedules
+// the total.
+__host__ __device__ constexpr int batch_twiddle_offset(int sched, int L) {
+    int off = 0;
+    for (int s = 0; s < kBatchSchedules; ++s) {
+        for (int l = kBatchMinLen; l <= kBatchMaxLen; l *= 2) {
+            if (s == sched && l == L) return off;
+            off += twiddle_entries(l, batch_points(s, l));
+        }
+    }
+    return off;
+}
+
 // The thread's twiddle factors for a whole line transform, loaded once from
 // the table before any barrier (so their latency overlaps the data loads);
 // the inverse transform uses their conjugates.  Plans that need more than
@@ -405,28 +455,27 @@ struct LineTwiddles {
     static constexpr bool PRELOAD = lds_mode(L) ? lds_preload(L) : NEED <= kMaxTwiddleRegs;
     static constexpr int COUNT = (PRELOAD && NEED > 0) ? NEED : 1;
     float2 w[COUNT];
-    const float2* table;
-    int step;
+    const float2* table;   // the staged table of (L, P)
 };
 
 template <int L, int P, int NS, int OFF>
-__device__ __forceinline__ void load_twiddles_from(LineTwiddles<L, P>& tw, int j, const float2* __restrict__ table,
-                                                   int step) {
+__device__ __forceinline__ void load_twiddles_from(LineTwiddles<L, P>& tw, int j, const float2* __restrict__ table) {
     if constexpr (NS < L) {
         constexpr int T = L / P;
         constexpr int R = stage_radix(L, P, NS);
         constexpr int M = P / R;
         if constexpr (NS > 1) {
-            constexpr int STRIDE = L / (NS * R);
+            constexpr int BLOCK = twiddle_block(L, P, NS);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                const int k = (j + T * m) % NS;
+                const unsigned k = (unsigned)((j + T * m) % NS);
 #pragma unroll
-                for (int q = 1; q < R; ++q) tw.w[OFF + m * (R - 1) + (q - 1)] = table[q * k * STRIDE * step];
+                for (int q = 1; q < R; ++q)
+                    tw.w[OFF + m * (R - 1) + (q - 1)] = *elem_ptr(table, BLOCK + (q - 1) * NS + k);
             }
-            load_twiddles_from<L, P, NS * R, OFF + M * (R - 1)>(tw, j, table, step);
+            load_twiddles_from<L, P, NS * R, OFF + M * (R - 1)>(tw, j, table);
         } else {
-            load_twiddles_from<L, P, NS * R, OFF>(tw, j, table, step);
+            load_twiddles_from<L, P, NS * R, OFF>(tw, j, table);
         }
     }
 }
@@ -435,40 +484,38 @@ __device__ __forceinline__ void load_twiddles_from(LineTwiddles<L, P>& tw, int j
 // last butterfly load a harmless entry and are never used).
 template <int L, int P, int NS, int OFF>
 __device__ __forceinline__ void lds_load_twiddles_from(LineTwiddles<L, P>& tw, int j,
-                                                       const float2* __restrict__ table, int step) {
+                                                       const float2* __restrict__ table) {
     if constexpr (NS < L) {
         constexpr int T = lds_threads(L);
         constexpr int R = lds_stage_radix(L, NS);
         constexpr int NB = L / R;
         constexpr int ROUNDS = (NB + T - 1) / T;
         if constexpr (NS > 1) {
-            constexpr int STRIDE = L / (NS * R);
+            constexpr int BLOCK = twiddle_block(L, P, NS);
 #pragma unroll
             for (int m = 0; m < ROUNDS; ++m) {
                 const int b = j + T * m;
-                const int k = b < NB ? b % NS : 0;
+                const unsigned k = (unsigned)(b < NB ? b % NS : 0);
 #pragma unroll
-                for (int q = 1; q < R; ++q) tw.w[OFF + m * (R - 1) + (q - 1)] = table[q * k * STRIDE * step];
+                for (int q = 1; q < R; ++q)
+                    tw.w[OFF + m * (R - 1) + (q - 1)] = *elem_ptr(table, BLOCK + (q - 1) * NS + k);
             }
-            lds_load_twiddles_from<L, P, NS * R, OFF + ROUNDS * (R - 1)>(tw, j, table, step);
+            lds_load_twiddles_from<L, P, NS * R, OFF + ROUNDS * (R - 1)>(tw, j, table);
         } else {
-            lds_load_twiddles_from<L, P, NS * R, OFF>(tw, j, table, step);
+            lds_load_twiddles_from<L, P, NS * R, OFF>(tw, j, table);
         }
     }
 }
 
-// `table` holds exp(-2 pi i k / (L step)); entry k step is exp(-2 pi i k / L),
-// so one table of the largest length serves every shorter power of two.
+// `table` is the staged twiddle table of (L, P) (twiddle_block).
 template <int L, int P>
-__device__ __forceinline__ void load_twiddles(LineTwiddles<L, P>& tw, int j, const float2* __restrict__ table,
-                                              int step) {
+__device__ __forceinline__ void load_twiddles(LineTwiddles<L, P>& tw, int j, const float2* __restrict__ table) {
     tw.table = table;
-    tw.step = step;
     if constexpr (LineTwiddles<L, P>::PRELOAD) {
         if constexpr (lds_mode(L)) {
-            lds_load_twiddles_from<L, P, 1, 0>(tw, j, table, step);
+            lds_load_twiddles_from<L, P, 1, 0>(tw, j, table);
         } else {
-            load_twiddles_from<L, P, 1, 0>(tw, j, table, step);
+            load_twiddles_from<L, P, 1, 0>(tw, j, table);
         }
     }
 }
@@ -514,7 +561,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, i
                 if constexpr (LineTwiddles<L, P>::PRELOAD) {
                     w = tw.w[OFF + m * (R - 1) + (q - 1)];
                 } else {
-                    w = tw.table[q * k * (L / (NS * R)) * tw.step];
+                    w = *elem_ptr(tw.table, (unsigned)(twiddle_block(L, P, NS) + (q - 1) * NS + k));
                 }
                 if constexpr (INV) w.y = -w.y;
                 x[q] = cmul(x[q], w);
@@ -570,7 +617,7 @@ __device__ __forceinline__ void lds_stages(float2* src, float2* dst, int j, cons
                         if constexpr (LineTwiddles<L, P>::PRELOAD) {
                             w = tw.w[OFF + m * (R - 1) + (q - 1)];
                         } else {
-                            w = tw.table[q * k * (L / (NS * R)) * tw.step];
+                            w = *elem_ptr(tw.table, (unsigned)(twiddle_block(L, P, NS) + (q - 1) * NS + k));
                         }
                         if constexpr (INV) w.y = -w.y;
                         x[q] = cmul(x[q], w);

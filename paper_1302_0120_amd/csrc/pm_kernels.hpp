@@ -110,7 +110,8 @@ struct LineShape {
 // strip0 + sl, column c of that strip, rows j + T t.  For a fixed t a wave's
 // loads are 64 / kC consecutive rows of one strip: one contiguous run.
 // `lds` holds LdsPlan<H, G>::FLOATS2 elements, `red` red_slots(G T) doubles;
-// the FP64 partials go to part_slot[0 .. red_slots(G T)).
+// the FP64 partials go to part_slot[0 .. red_slots(G T)); a.tw is the staged
+// twiddle table of (H, P).
 template <int H, int P, int G, int MODE>
 __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double* part_slot,
                                          float2* lds, double* red) {
@@ -124,14 +125,23 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
     const int c = tid & (kC - 1);
     const int j = (tid / kC) % T;
     const int sl = tid / (kC * T);
-    const int s = strip0 + sl;
-    const size_t sb = (size_t)s * H * kC;
+    // Element (row j + T t, column c) of strip strip0 + sl: a uniform base
+    // per t plus a per-thread 32-bit offset, in the strip-tiled layout and in
+    // the natural row-major layout.
+    const unsigned toff = (unsigned)((sl * H + j) * kC + c);
+    const unsigned noff = (unsigned)(j * a.W + sl * kC + c);
+    auto tiled = [&](auto* base, int t) {
+        return elem_ptr(base + ((size_t)strip0 * H * kC + (size_t)T * t * kC), toff);
+    };
+    auto natural = [&](auto* base, int t) {
+        return elem_ptr(base + ((size_t)T * t * a.W + (size_t)strip0 * kC), noff);
+    };
     LineTwiddles<H, P> tw;
-    load_twiddles(tw, j, a.tw, a.tw_step);
+    load_twiddles(tw, j, a.tw);
     float mt[P];
     if constexpr ((MODE & (C_PROJ | C_ERR)) != 0) {
 #pragma unroll
-        for (int t = 0; t < P; ++t) mt[t] = a.mhat[sb + (size_t)(j + T * t) * kC + c];
+        for (int t = 0; t < P; ++t) mt[t] = *tiled(a.mhat, t);
     }
     float2 v[P];
     if constexpr ((MODE & C_BIT) != 0) {
@@ -143,15 +153,15 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
         const double mx2 = (double)mx * (double)mx;
 #pragma unroll
         for (int t = 0; t < P; ++t) {
-            const double m = (double)a.tnat[(size_t)(j + T * t) * a.W + s * kC + c];
+            const double m = (double)*natural(a.tnat, t);
             v[t] = make_float2((m * m) / mx2 > a.t_dark ? 1.0f : 0.0f, 0.0f);
         }
     } else if constexpr ((MODE & CIN_NAT) != 0) {
 #pragma unroll
-        for (int t = 0; t < P; ++t) v[t] = a.nat_in[(size_t)(j + T * t) * a.W + s * kC + c];
+        for (int t = 0; t < P; ++t) v[t] = *natural(a.nat_in, t);
     } else {
 #pragma unroll
-        for (int t = 0; t < P; ++t) v[t] = a.X[sb + (size_t)(j + T * t) * kC + c];
+        for (int t = 0; t < P; ++t) v[t] = *tiled(a.X, t);
     }
     float2* line = lds + (sl * kC + c) * LP;
 
@@ -194,7 +204,7 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
 #pragma unroll
         for (int t = 0; t < P; ++t) {
             const float q = fmaf(v[t].x, v[t].x, v[t].y * v[t].y) * (float)a.invN;
-            a.pw[sb + (size_t)(j + T * t) * kC + c] = q;
+            *tiled(a.pw, t) = q;
             mx = fmaxf(mx, q);
         }
     }
@@ -206,7 +216,7 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
         // 1/sqrt(N) factors are folded into the gradient scale.
 #pragma unroll
         for (int t = 0; t < P; ++t) {
-            const float I = a.inten[(size_t)(j + T * t) * a.W + s * kC + c];
+            const float I = *natural(a.inten, t);
             const float2 U = v[t];
             const float r = fmaf(fmaf(U.x, U.x, U.y * U.y), (float)a.invN, -I);
             acc = fma((double)r, (double)r, acc);
@@ -218,11 +228,11 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
 
     if constexpr ((MODE & COUT_TILED) != 0) {
 #pragma unroll
-        for (int t = 0; t < P; ++t) store_shared(&a.X[sb + (size_t)(j + T * t) * kC + c], v[t]);
+        for (int t = 0; t < P; ++t) store_shared(tiled(a.X, t), v[t]);
     }
     if constexpr ((MODE & COUT_NAT) != 0) {
 #pragma unroll
-        for (int t = 0; t < P; ++t) a.nat_out[(size_t)(j + T * t) * a.W + s * kC + c] = v[t];
+        for (int t = 0; t < P; ++t) *natural(a.nat_out, t) = v[t];
     }
 
     constexpr bool SUM = ((MODE & (C_PROJ | C_ERR)) != 0 && (MODE & C_NOERR) == 0) || (MODE & C_LOSS) != 0;
@@ -233,7 +243,8 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
 // Row pass over G adjacent rows starting at `row0`.  Thread tid = (jhi, rho,
 // c), c fastest: row row0 + rho, thread index within the row j = jhi kC + c.
 // For a fixed t the element (row, j + T t) lies in strip jhi + (T / kC) t at
-// column c, so a wave's loads are runs of G kC contiguous elements.
+// column c, so a wave's loads are runs of G kC contiguous elements; a.tw is
+// the staged twiddle table of (W, P).
 template <int W, int P, int G, int MODE>
 __device__ __forceinline__ void row_body(const RowParams& a, int row0, const float* phase_in,
                                          float* phase_out, double* part_slot, float2* lds,
@@ -249,14 +260,18 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
     const int rho = (tid / kC) % G;
     const int jhi = tid / (kC * G);
     const int j = jhi * kC + c;
-    const int row = row0 + rho;
-    const size_t H = (size_t)a.H;
-    auto tiled = [&](int t) -> size_t {
-        return ((size_t)(jhi + (T / kC) * t) * H + row) * kC + c;
+    const int H = a.H;
+    // Element (row row0 + rho, column j + T t): a uniform base per t plus a
+    // per-thread 32-bit offset.  Strip-tiled: strip jhi + (T / kC) t, row,
+    // column c; natural: row-major.
+    const unsigned toff = (unsigned)((jhi * H + rho) * kC + c);
+    const unsigned noff = (unsigned)(rho * W + j);
+    auto tiled = [&](auto* base, int t) {
+        return elem_ptr(base + ((size_t)row0 * kC + (size_t)T * t * H), toff);
     };
-    auto natural = [&](int t) -> size_t { return (size_t)row * W + j + T * t; };
+    auto natural = [&](auto* base, int t) { return elem_ptr(base + ((size_t)row0 * W + (size_t)T * t), noff); };
     LineTwiddles<W, P> tw;
-    load_twiddles(tw, j, a.tw, a.tw_step);
+    load_twiddles(tw, j, a.tw);
     float2 v[P];
     // Illumination amplitude p of Eq. 1 (S = fields of modulus p): the
     // projections below take modulus p instead of 1.
@@ -266,14 +281,14 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
     float pil[ILLUM ? P : 1];
     if constexpr (ILLUM) {
 #pragma unroll
-        for (int t = 0; t < P; ++t) pil[t] = a.illum[tiled(t)];
+        for (int t = 0; t < P; ++t) pil[t] = *tiled(a.illum, t);
     }
 
     if constexpr ((MODE & RIN_PHASE) != 0) {
 #pragma unroll
         for (int t = 0; t < P; ++t) {
             float sn, cs;
-            sincosf(phase_in[natural(t)], &sn, &cs);
+            sincosf(*natural(phase_in, t), &sn, &cs);
             if constexpr (ILLUM) {
                 v[t] = make_float2(pil[t] * cs, pil[t] * sn);
             } else {
@@ -282,19 +297,19 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
         }
     } else if constexpr ((MODE & RIN_NAT) != 0) {
 #pragma unroll
-        for (int t = 0; t < P; ++t) v[t] = a.nat_in[natural(t)];
+        for (int t = 0; t < P; ++t) v[t] = *natural(a.nat_in, t);
     } else {
 #pragma unroll
-        for (int t = 0; t < P; ++t) v[t] = a.X[tiled(t)];
+        for (int t = 0; t < P; ++t) v[t] = *tiled(a.X, t);
     }
     float2 zx[(MODE & R_RAAR) != 0 ? P : 1];
     if constexpr ((MODE & R_RAAR) != 0) {
 #pragma unroll
-        for (int t = 0; t < P; ++t) zx[t] = a.Z[tiled(t)];
+        for (int t = 0; t < P; ++t) zx[t] = *tiled(a.Z, t);
     }
     if constexpr ((MODE & R_STOREZ) != 0) {
 #pragma unroll
-        for (int t = 0; t < P; ++t) a.Z[tiled(t)] = v[t];
+        for (int t = 0; t < P; ++t) *tiled(a.Z, t) = v[t];
     }
     float2* line = lds + rho * LP;
 
@@ -324,7 +339,7 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
             }
             if constexpr (ILLUM) {
                 // the phase of the mask is that of e (also where p = 0)
-                if constexpr ((MODE & ROUT_PHASE) != 0) phase_out[natural(t)] = atan2f(e.y, e.x);
+                if constexpr ((MODE & ROUT_PHASE) != 0) *natural(phase_out, t) = atan2f(e.y, e.x);
                 v[t] = make_float2(pil[t] * e.x, pil[t] * e.y);
             } else {
                 v[t] = e;
@@ -356,13 +371,13 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
                 const float qr = qz ? __builtin_amdgcn_rsqf(q2) : 0.0f;
                 const float2 e = qz ? make_float2(xn.x * qr, xn.y * qr) : make_float2(1.0f, 0.0f);
                 if constexpr (ILLUM) {
-                    phase_out[natural(t)] = atan2f(e.y, e.x);
+                    *natural(phase_out, t) = atan2f(e.y, e.x);
                     v[t] = make_float2(pil[t] * e.x, pil[t] * e.y);
                 } else {
                     v[t] = e;
                 }
             } else {
-                a.Z[tiled(t)] = xn;
+                *tiled(a.Z, t) = xn;
                 v[t] = xn;
             }
         }
@@ -370,11 +385,11 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
 
     if constexpr ((MODE & ROUT_PHASE) != 0 && !ILLUM) {
 #pragma unroll
-        for (int t = 0; t < P; ++t) phase_out[natural(t)] = atan2f(v[t].y, v[t].x);
+        for (int t = 0; t < P; ++t) *natural(phase_out, t) = atan2f(v[t].y, v[t].x);
     }
     if constexpr ((MODE & ROUT_NAT) != 0) {
 #pragma unroll
-        for (int t = 0; t < P; ++t) a.nat_out[natural(t)] = v[t];
+        for (int t = 0; t < P; ++t) *natural(a.nat_out, t) = v[t];
     }
     if constexpr ((MODE & ROUT_GRAD) != 0) {
         // v = unnormalised inverse of r U, i.e. N F^H(r U) up to the scale the
@@ -382,14 +397,14 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
 #pragma unroll
         for (int t = 0; t < P; ++t) {
             float sn, cs;
-            sincosf(phase_in[natural(t)], &sn, &cs);
-            phase_out[natural(t)] = a.gscale * fmaf(cs, v[t].y, -(sn * v[t].x));
+            sincosf(*natural(phase_in, t), &sn, &cs);
+            *natural(phase_out, t) = a.gscale * fmaf(cs, v[t].y, -(sn * v[t].x));
         }
     }
     if constexpr ((MODE & R_FWD) != 0) {
         fft_line<W, P, false, LD::NBUF, PAR1>(v, j, line, LD::STRIDE, tw);
 #pragma unroll
-        for (int t = 0; t < P; ++t) store_shared(&a.X[tiled(t)], v[t]);
+        for (int t = 0; t < P; ++t) store_shared(tiled(a.X, t), v[t]);
     }
     if constexpr ((MODE & R_PS) != 0 && (MODE & R_NOERR) == 0) group_sum_store<NT>(acc, part_slot);
 }
@@ -432,7 +447,6 @@ k_row_adj(AdjParams p) {
     RowParams a{};
     a.X = p.saved + b * n;
     a.tw = p.twW;
-    a.tw_step = 1;
     a.H = p.H;
     float* out = nullptr;
     if constexpr ((MODE & ROUT_GRAD) != 0) {
@@ -453,7 +467,6 @@ k_col_adj(AdjParams p) {
     ColParams a{};
     a.X = p.saved + b * n;
     a.tw = p.twH;
-    a.tw_step = 1;
     a.W = p.W;
     a.invN = 1.0 / (double)n;
     a.inten = p.inten + b * n;
