@@ -536,16 +536,83 @@ __host__ __device__ constexpr int exchanges_from(int L, int P, int NS) {
     return NS * stage_radix(L, P, NS) >= L ? 0 : 1 + exchanges_from(L, P, NS * stage_radix(L, P, NS));
 }
 
+// Sub-length at which the last stage of the register scheme starts.
+__host__ __device__ constexpr int last_stage_ns(int L, int P, int NS = 1) {
+    return NS * stage_radix(L, P, NS) >= L ? NS : last_stage_ns(L, P, NS * stage_radix(L, P, NS));
+}
+
+// Plans whose last stage is radix 2 right after a stage of radix P (one
+// butterfly per thread), e.g. 8-8-8-2 at 1024, 16-16-2 at 512, 8-8-2 at 128:
+// there the last stage can take its operands across lanes instead of through
+// LDS (fft_last_radix2_lanes), provided lanes i and i + 32 of every wave hold
+// threads j and j + T/2 of one line.  T % 16 == 0 keeps the lane layouts of
+// the passes whole (8 threads of a line per half-wave and column).
+__host__ __device__ constexpr bool lane_swap_plan(int L, int P) {
+    return !lds_mode(L) && stage_radix(L, P, last_stage_ns(L, P)) == 2 && last_stage_ns(L, P) > P &&
+           stage_radix(L, P, last_stage_ns(L, P) / P) == P && (L / P) % 16 == 0;
+}
+
+// Exchanges one float between the halves of a wave: afterwards lanes 0..31
+// hold in `hi` the `lo` of lane i + 32, and lanes 32..63 hold in `lo` the
+// `hi` of lane i - 32; the other two values stay.
+__device__ __forceinline__ void swap_halves(float& lo, float& hi) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+    lo = __uint_as_float(r[0]);
+    hi = __uint_as_float(r[1]);
+}
+
+// The last stage (radix 2, sub-length L/2) of a lane_swap_plan, with lanes i
+// and i + 32 holding threads j and j + T/2 of the line.  After the stage
+// before it, v[q] of thread j is element (L/2)(j / (T/2)) + j % (T/2) +
+// (T/2) q.  Butterfly m of thread j pairs elements p = j + T m and p + L/2:
+// for the lower thread p is its own v[2m] and p + L/2 the partner's v[2m];
+// for the upper thread p is the partner's v[2m + 1] and p + L/2 its own.
+// Swapping v[2m + 1] of the lower lanes with v[2m] of the upper lanes hands
+// every thread both operands.  Twiddles, arithmetic and the result slots
+// (v[m], v[m + P/2]) are those of the LDS exchange path, so both give
+// identical results.
+template <int L, int P, int OFF, bool INV>
+__device__ __forceinline__ void fft_last_radix2_lanes(float2 (&v)[P], int j, const LineTwiddles<L, P>& tw) {
+    constexpr int T = L / P;
+    constexpr int NS = L / 2;
+    constexpr int H2 = P / 2;
+    float2 y[P];
+#pragma unroll
+    for (int m = 0; m < H2; ++m) {
+        float2 a = v[2 * m];
+        float2 b = v[2 * m + 1];
+        swap_halves(a.x, b.x);
+        swap_halves(a.y, b.y);
+        const int k = j + T * m;  // < L/2, so this is also (j + T m) mod NS
+        float2 w;
+        if constexpr (LineTwiddles<L, P>::PRELOAD) {
+            w = tw.w[OFF + m];
+        } else {
+            w = *elem_ptr(tw.table, (unsigned)(twiddle_block(L, P, NS) + k));
+        }
+        if constexpr (INV) w.y = -w.y;
+        float2 x[2] = {a, cmul(b, w)};
+        dft<2, INV>(x);
+        y[m] = x[0];
+        y[m + H2] = x[1];
+    }
+#pragma unroll
+    for (int t = 0; t < P; ++t) v[t] = y[t];
+}
+
 // One Stockham stage on the thread's P register points (see header); OFF is
 // this stage's first entry in the thread's twiddle registers, PAR the LDS
-// buffer this stage's exchange uses when NBUF == 2.
-template <int L, int P, int NS, int OFF, bool INV, int NBUF, int PAR>
+// buffer this stage's exchange uses when NBUF == 2.  SW: the lanes hold
+// their threads as fft_last_radix2_lanes needs, so a lane_swap_plan runs its
+// last stage across lanes.
+template <int L, int P, int NS, int OFF, bool INV, int NBUF, int PAR, bool SW>
 __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, int stride,
                                           const LineTwiddles<L, P>& tw) {
     constexpr int T = L / P;
     constexpr int R = stage_radix(L, P, NS);
     constexpr int M = P / R;
     constexpr bool LAST = (NS * R == L);
+    constexpr bool LANES_NEXT = SW && lane_swap_plan(L, P) && !LAST && NS * R * 2 == L;
     float2* buf = (NBUF == 2 && PAR == 1) ? line + stride : line;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -568,7 +635,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, i
             }
         }
         dft<R, INV>(x);
-        if constexpr (LAST) {
+        if constexpr (LAST || LANES_NEXT) {
 #pragma unroll
             for (int q = 0; q < R; ++q) v[m + q * M] = x[q];
         } else {
@@ -577,7 +644,10 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, i
             for (int q = 0; q < R; ++q) buf[lds_pad(base + q * NS)] = x[q];
         }
     }
-    if constexpr (!LAST) {
+    if constexpr (LANES_NEXT) {
+        static_assert(M == 1, "one butterfly per thread before the cross-lane stage");
+        fft_last_radix2_lanes<L, P, (NS > 1 ? OFF + M * (R - 1) : OFF), INV>(v, j, tw);
+    } else if constexpr (!LAST) {
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < P; ++t) v[t] = buf[lds_pad(j + T * t)];
@@ -585,8 +655,8 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, i
         // with two they go to the other buffer, whose last reads finished
         // before the barrier above.
         if constexpr (NBUF == 1) __syncthreads();
-        fft_stage<L, P, NS * R, (NS > 1 ? OFF + M * (R - 1) : OFF), INV, NBUF, PAR ^ 1>(v, j, line,
-                                                                                     stride, tw);
+        fft_stage<L, P, NS * R, (NS > 1 ? OFF + M * (R - 1) : OFF), INV, NBUF, PAR ^ 1, SW>(v, j, line,
+                                                                                         stride, tw);
     }
 }
 
@@ -655,21 +725,23 @@ __device__ __forceinline__ void fft_line_lds(float2 (&v)[P], int j, float2* a, f
 // Full length-L transform of one line; every thread of the work-group must
 // call it (it contains work-group barriers).  Consecutive transforms in one
 // kernel must pass PAR = the parity after the previous one
-// (fft_parity_after) so that the buffers keep alternating.
-template <int L, int P, bool INV, int NBUF, int PAR>
+// (fft_parity_after, with the same SW) so that the buffers keep alternating.
+// SW: see fft_stage.
+template <int L, int P, bool INV, int NBUF, int PAR, bool SW = false>
 __device__ __forceinline__ void fft_line(float2 (&v)[P], int j, float2* line, int stride,
                                          const LineTwiddles<L, P>& tw) {
     if constexpr (lds_mode(L)) {
         static_assert(NBUF == 2, "LDS mode ping-pongs between two buffers");
         fft_line_lds<L, P, INV>(v, j, line, line + stride, tw);
     } else {
-        fft_stage<L, P, 1, 0, INV, NBUF, PAR>(v, j, line, stride, tw);
+        fft_stage<L, P, 1, 0, INV, NBUF, PAR, SW>(v, j, line, stride, tw);
     }
 }
 
-template <int L, int P, int PAR>
+template <int L, int P, int PAR, bool SW = false>
 __host__ __device__ constexpr int fft_parity_after() {
-    return lds_mode(L) ? PAR : (PAR + exchanges_from(L, P, 1)) & 1;
+    return lds_mode(L) ? PAR
+                       : (PAR + exchanges_from(L, P, 1) - ((SW && lane_swap_plan(L, P)) ? 1 : 0)) & 1;
 }
 
 // Points per thread for a line of L points.  At 1024, P = 8 (radix 8-8-8-2,

@@ -111,8 +111,10 @@ struct LineShape {
 // loads are 64 / kC consecutive rows of one strip: one contiguous run.
 // `lds` holds LdsPlan<H, G>::FLOATS2 elements, `red` red_slots(G T) doubles;
 // the FP64 partials go to part_slot[0 .. red_slots(G T)); a.tw is the staged
-// twiddle table of (H, P).
-template <int H, int P, int G, int MODE>
+// twiddle table of (H, P).  SW (one strip, G = kC): lanes i and i + 32 of a
+// wave hold rows j and j + T/2 of one column, 8 rows per half-wave, so a
+// lane_swap_plan runs its last FFT stage across lanes.
+template <int H, int P, int G, int MODE, bool SW = false>
 __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double* part_slot,
                                          float2* lds, double* red) {
     constexpr int T = LineShape<H, P>::T;
@@ -122,9 +124,18 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
     static_assert(G % kC == 0, "whole strips per work-group");
 
     const int tid = threadIdx.x;
-    const int c = tid & (kC - 1);
-    const int j = (tid / kC) % T;
-    const int sl = tid / (kC * T);
+    int c, j, sl;
+    if constexpr (SW) {
+        static_assert(G == kC && kC == 4 && T % 16 == 0, "one strip, 8 rows per half-wave");
+        const int lane = tid & 63;
+        c = lane & 3;
+        j = (tid >> 6) * 8 + ((lane >> 2) & 7) + (lane >> 5) * (T / 2);
+        sl = 0;
+    } else {
+        c = tid & (kC - 1);
+        j = (tid / kC) % T;
+        sl = tid / (kC * T);
+    }
     // Element (row j + T t, column c) of strip strip0 + sl: a uniform base
     // per t plus a per-thread 32-bit offset, in the strip-tiled layout and in
     // the natural row-major layout.
@@ -165,8 +176,8 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
     }
     float2* line = lds + (sl * kC + c) * LP;
 
-    constexpr int PAR1 = (MODE & C_FWD) != 0 ? fft_parity_after<H, P, 0>() : 0;
-    if constexpr ((MODE & C_FWD) != 0) fft_line<H, P, false, LD::NBUF, 0>(v, j, line, LD::STRIDE, tw);
+    constexpr int PAR1 = (MODE & C_FWD) != 0 ? fft_parity_after<H, P, 0, SW>() : 0;
+    if constexpr ((MODE & C_FWD) != 0) fft_line<H, P, false, LD::NBUF, 0, SW>(v, j, line, LD::STRIDE, tw);
 
     // Per-thread partial of this pass's FP64 sum (Fourier error or loss);
     // reduced at the very end, after the stores, into one partial per
@@ -224,7 +235,7 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
         }
     }
 
-    if constexpr ((MODE & C_INV) != 0) fft_line<H, P, true, LD::NBUF, PAR1>(v, j, line, LD::STRIDE, tw);
+    if constexpr ((MODE & C_INV) != 0) fft_line<H, P, true, LD::NBUF, PAR1, SW>(v, j, line, LD::STRIDE, tw);
 
     if constexpr ((MODE & COUT_TILED) != 0) {
 #pragma unroll
@@ -244,8 +255,10 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
 // c), c fastest: row row0 + rho, thread index within the row j = jhi kC + c.
 // For a fixed t the element (row, j + T t) lies in strip jhi + (T / kC) t at
 // column c, so a wave's loads are runs of G kC contiguous elements; a.tw is
-// the staged twiddle table of (W, P).
-template <int W, int P, int G, int MODE>
+// the staged twiddle table of (W, P).  SW (G = 4): lanes i and i + 32 of a
+// wave hold threads j and j + T/2 of one row (jhi and jhi + T/8), so a
+// lane_swap_plan runs its last FFT stage across lanes.
+template <int W, int P, int G, int MODE, bool SW = false>
 __device__ __forceinline__ void row_body(const RowParams& a, int row0, const float* phase_in,
                                          float* phase_out, double* part_slot, float2* lds,
                                          double* red) {
@@ -256,9 +269,18 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
     using LD = LdsPlan<W, G>;
 
     const int tid = threadIdx.x;
-    const int c = tid & (kC - 1);
-    const int rho = (tid / kC) % G;
-    const int jhi = tid / (kC * G);
+    int c, rho, jhi;
+    if constexpr (SW) {
+        static_assert(G == 4 && kC == 4 && T % 16 == 0, "4 rows, two strips per half-wave");
+        const int lane = tid & 63;
+        c = lane & 3;
+        rho = (lane >> 2) & 3;
+        jhi = (tid >> 6) * 2 + ((lane >> 4) & 1) + (lane >> 5) * (T / 8);
+    } else {
+        c = tid & (kC - 1);
+        rho = (tid / kC) % G;
+        jhi = tid / (kC * G);
+    }
     const int j = jhi * kC + c;
     const int H = a.H;
     // Element (row row0 + rho, column j + T t): a uniform base per t plus a
@@ -313,8 +335,8 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
     }
     float2* line = lds + rho * LP;
 
-    constexpr int PAR1 = (MODE & R_INV) != 0 ? fft_parity_after<W, P, 0>() : 0;
-    if constexpr ((MODE & R_INV) != 0) fft_line<W, P, true, LD::NBUF, 0>(v, j, line, LD::STRIDE, tw);
+    constexpr int PAR1 = (MODE & R_INV) != 0 ? fft_parity_after<W, P, 0, SW>() : 0;
+    if constexpr ((MODE & R_INV) != 0) fft_line<W, P, true, LD::NBUF, 0, SW>(v, j, line, LD::STRIDE, tw);
 
     // Per-thread gap partial; reduced at the very end (see col_body).
     double acc = 0.0;
@@ -402,7 +424,7 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
         }
     }
     if constexpr ((MODE & R_FWD) != 0) {
-        fft_line<W, P, false, LD::NBUF, PAR1>(v, j, line, LD::STRIDE, tw);
+        fft_line<W, P, false, LD::NBUF, PAR1, SW>(v, j, line, LD::STRIDE, tw);
 #pragma unroll
         for (int t = 0; t < P; ++t) store_shared(tiled(a.X, t), v[t]);
     }
@@ -416,7 +438,8 @@ k_col(ColParams a) {
     constexpr int NT = kC * LineShape<H>::T;
     __shared__ float2 lds[LdsPlan<H, kC>::FLOATS2];
     __shared__ double red[red_slots(NT)];
-    col_body<H, LineShape<H>::P, kC, MODE>(a, blockIdx.x, a.part + blockIdx.x * red_slots(NT), lds, red);
+    col_body<H, LineShape<H>::P, kC, MODE, lane_swap_plan(H, LineShape<H>::P)>(
+        a, blockIdx.x, a.part + blockIdx.x * red_slots(NT), lds, red);
 }
 
 template <int W, int MODE>
@@ -429,8 +452,8 @@ k_row(RowParams a) {
     float* pout = nullptr;
     if constexpr ((MODE & RIN_PHASE) != 0) pin = a.io->phase_in;
     if constexpr ((MODE & ROUT_PHASE) != 0) pout = a.io->phase_out;
-    row_body<W, LineShape<W>::P, row_lines(W), MODE>(a, blockIdx.x * row_lines(W), pin, pout, a.part + blockIdx.x * red_slots(NT), lds,
-                                            red);
+    row_body<W, LineShape<W>::P, row_lines(W), MODE, lane_swap_plan(W, LineShape<W>::P) && row_lines(W) == 4>(
+        a, blockIdx.x * row_lines(W), pin, pout, a.part + blockIdx.x * red_slots(NT), lds, red);
 }
 
 // Intensity-loss kernels over a batch of same-size phases, sample = blockIdx.y.
@@ -453,7 +476,8 @@ k_row_adj(AdjParams p) {
         a.gscale = (float)(4.0 * p.grad_loss[b] / (double)n);
         out = p.grad + b * n;
     }
-    row_body<W, LineShape<W>::P, row_lines(W), MODE>(a, blockIdx.x * row_lines(W), p.phase + b * n, out, nullptr, lds, red);
+    row_body<W, LineShape<W>::P, row_lines(W), MODE, lane_swap_plan(W, LineShape<W>::P) && row_lines(W) == 4>(
+        a, blockIdx.x * row_lines(W), p.phase + b * n, out, nullptr, lds, red);
 }
 
 template <int H>
@@ -470,8 +494,8 @@ k_col_adj(AdjParams p) {
     a.W = p.W;
     a.invN = 1.0 / (double)n;
     a.inten = p.inten + b * n;
-    col_body<H, LineShape<H>::P, kC, COL_LOSS>(a, blockIdx.x, p.part + b * p.nwg + blockIdx.x * red_slots(NT), lds,
-                                               red);
+    col_body<H, LineShape<H>::P, kC, COL_LOSS, lane_swap_plan(H, LineShape<H>::P)>(
+        a, blockIdx.x, p.part + b * p.nwg + blockIdx.x * red_slots(NT), lds, red);
 }
 
 }  // namespace pm
