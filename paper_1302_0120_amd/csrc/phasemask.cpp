@@ -99,8 +99,8 @@ constexpr int kNormGrid = 64;          // work-groups of the target-norm partial
 // PHASEMASK_GROUP_MB overrides it, 0 = all masks in one group.  With
 // kBatchChains groups in flight at once, 4 x 48 MiB stays inside the 256 MB
 // last-level cache of an MI355X.  Measured on the 64-mask workload (385 MB
-// of iterates and targets): 22.2 ms per batch, against 27.9 ms for one
-// group and 25.8 ms for 224 MiB groups on one chain.
+// of iterates and targets): 18.0 ms per batch, against 22.6 ms for one
+// group and 19.6 ms for 224 MiB groups on one chain.
 constexpr size_t kBatchGroupBytes = (size_t)48 << 20;
 // Default number of concurrent chains the groups are spread over
 // (PHASEMASK_CHAINS overrides, 1..8).

@@ -20,7 +20,7 @@ template <int SCHED, int L>
 struct BatchShape {
     static constexpr int P = batch_points(SCHED, L);
     static constexpr int G = batch_lines(SCHED, L);
-    static constexpr int FLOATS2 = LdsPlan<L, G>::FLOATS2;
+    static constexpr int FLOATS2 = LdsPlan<L, G, 1>::FLOATS2;  // one exchange buffer (LdsPlan)
 };
 
 template <int SCHED>
@@ -33,16 +33,19 @@ constexpr int batch_lds_floats2() {
     return m;
 }
 
-#define PM_COL_CASE(L)                                                                             \
-    case L:                                                                                        \
-        a.tw = p.tw + batch_twiddle_offset(SCHED, L);                                              \
-        col_body<L, BatchShape<SCHED, L>::P, BatchShape<SCHED, L>::G, MODE>(a, task.first, slot, lds, red); \
+// One case per transform length: the staged twiddle table of (L, P) and the
+// pass body with one LDS exchange buffer (LdsPlan, NBMAX = 1).
+#define PM_COL_CASE(L)                                                                    \
+    case L:                                                                               \
+        a.tw = p.tw + batch_twiddle_offset(SCHED, L);                                     \
+        col_body<L, BatchShape<SCHED, L>::P, BatchShape<SCHED, L>::G, MODE, false, 1>(    \
+            a, task.first, slot, lds, red);                                               \
         break;
-#define PM_ROW_CASE(L)                                                                             \
-    case L:                                                                                        \
-        a.tw = p.tw + batch_twiddle_offset(SCHED, L);                                              \
-        row_body<L, BatchShape<SCHED, L>::P, BatchShape<SCHED, L>::G, MODE>(a, task.first, pin, pout, slot, \
-                                                                           lds, red);              \
+#define PM_ROW_CASE(L)                                                                    \
+    case L:                                                                               \
+        a.tw = p.tw + batch_twiddle_offset(SCHED, L);                                     \
+        row_body<L, BatchShape<SCHED, L>::P, BatchShape<SCHED, L>::G, MODE, false, 1>(    \
+            a, task.first, pin, pout, slot, lds, red);                                    \
         break;
 
 template <int MODE, int SCHED>

@@ -522,11 +522,16 @@ __device__ __forceinline__ void load_twiddles(LineTwiddles<L, P>& tw, int j, con
 
 // LDS exchange buffers per line: two (alternating, one barrier per
 // exchange) when that leaves room for two work-groups per CU, else one (two
-// barriers per exchange).  `stride` is the distance between the buffers.
-template <int L, int G>
+// barriers per exchange).  NBMAX = 1 asks for one buffer wherever the scheme
+// allows it (LDS mode always ping-pongs): the batched passes, whose many
+// independent work-groups gain more from twice the work-groups per CU than
+// they lose to the second barrier (64-mask workload: 2970 -> 3570 masks/s;
+// the one-mask 1024^2 solve, one work-group per CU, is 1% slower that way).
+// `stride` is the distance between the buffers.
+template <int L, int G, int NBMAX = 2>
 struct LdsPlan {
     static constexpr int LP = lds_line_len(L);
-    static constexpr int NBUF = (lds_mode(L) || 2 * G * LP * 8 <= 80 * 1024) ? 2 : 1;
+    static constexpr int NBUF = (lds_mode(L) || (NBMAX == 2 && 2 * G * LP * 8 <= 80 * 1024)) ? 2 : 1;
     static constexpr int FLOATS2 = NBUF * G * LP;  // float2 elements per work-group
     static constexpr int STRIDE = G * LP;
 };

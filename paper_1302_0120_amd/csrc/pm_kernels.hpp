@@ -109,18 +109,18 @@ struct LineShape {
 // `strip0` (G a multiple of kC).  Thread tid = (sl, j, c), c fastest: strip
 // strip0 + sl, column c of that strip, rows j + T t.  For a fixed t a wave's
 // loads are 64 / kC consecutive rows of one strip: one contiguous run.
-// `lds` holds LdsPlan<H, G>::FLOATS2 elements, `red` red_slots(G T) doubles;
+// `lds` holds LdsPlan<H, G, NBMAX>::FLOATS2 elements, `red` red_slots(G T) doubles;
 // the FP64 partials go to part_slot[0 .. red_slots(G T)); a.tw is the staged
 // twiddle table of (H, P).  SW (one strip, G = kC): lanes i and i + 32 of a
 // wave hold rows j and j + T/2 of one column, 8 rows per half-wave, so a
 // lane_swap_plan runs its last FFT stage across lanes.
-template <int H, int P, int G, int MODE, bool SW = false>
+template <int H, int P, int G, int MODE, bool SW = false, int NBMAX = 2>
 __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double* part_slot,
                                          float2* lds, double* red) {
     constexpr int T = LineShape<H, P>::T;
     constexpr int NT = G * T;
     constexpr int LP = LineShape<H, P>::LP;
-    using LD = LdsPlan<H, G>;
+    using LD = LdsPlan<H, G, NBMAX>;
     static_assert(G % kC == 0, "whole strips per work-group");
 
     const int tid = threadIdx.x;
@@ -258,7 +258,7 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
 // the staged twiddle table of (W, P).  SW (G = 4): lanes i and i + 32 of a
 // wave hold threads j and j + T/2 of one row (jhi and jhi + T/8), so a
 // lane_swap_plan runs its last FFT stage across lanes.
-template <int W, int P, int G, int MODE, bool SW = false>
+template <int W, int P, int G, int MODE, bool SW = false, int NBMAX = 2>
 __device__ __forceinline__ void row_body(const RowParams& a, int row0, const float* phase_in,
                                          float* phase_out, double* part_slot, float2* lds,
                                          double* red) {
@@ -266,7 +266,7 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
     constexpr int NT = G * T;
     constexpr int LP = LineShape<W, P>::LP;
     static_assert(T % kC == 0, "row threads must cover whole strips");
-    using LD = LdsPlan<W, G>;
+    using LD = LdsPlan<W, G, NBMAX>;
 
     const int tid = threadIdx.x;
     int c, rho, jhi;
