@@ -14,16 +14,19 @@
 //   * Between stages the outputs go through LDS and each thread gathers its
 //     next inputs x[j + T t]; the last stage's outputs land exactly in the
 //     thread's own slots, so a line needs (#stages - 1) LDS exchanges and the
-//     first read / last write can go straight to or from global memory.
+//     first read / last write can go straight to or from global memory.  A
+//     last radix-2 stage after a radix-P stage can instead swap operands
+//     between the two halves of a wave (fft_last_radix2_lanes).
 //   * Radix sequence: P, P, ..., then the remaining factor (each divides P)
 //     for powers of two; fixed mixed-radix sequences (radices 4, 6, 10, 12,
 //     20, 30) for the non-power-of-two lengths 600, 800, 1080 and 1920,
 //     whose butterfly index b and sub-length NS are then not powers of two
 //     (b mod NS is a true modulo).
-//   * Twiddles come from a table tw[i] = exp(-2 pi i i / L) computed on the
-//     host in double precision and rounded once to float; each thread loads
-//     the ones it needs into registers at kernel start (or, for the long
-//     mixed-radix plans, reads them from the table stage by stage).
+//   * Twiddles come from a staged table (one block per stage, see
+//     twiddle_block) computed on the host in double precision and rounded
+//     once to float; each thread loads the ones it needs into registers at
+//     kernel start (or, for the long mixed-radix plans, reads them from the
+//     table stage by stage).
 #pragma once
 #include <hip/hip_runtime.h>
 
