@@ -106,6 +106,9 @@ constexpr size_t kBatchGroupBytes = (size_t)48 << 20;
 // (PHASEMASK_CHAINS overrides, 1..8).
 constexpr int kBatchChains = 4;
 constexpr size_t kMaxCachedGraphs = 8;
+// Iterations per schedule the batched tuner times (groups on chains, as a
+// solve runs them).
+constexpr int kTuneIterations = 6;
 
 }  // namespace
 
@@ -466,20 +469,12 @@ hipError_t batch_row(pm_plan* h, int mode, hipStream_t s, hipEvent_t e0 = nullpt
     return h->sched == 0 ? batch_row_s<0>(mode, p, t1 - t0, s, e0, e1) : batch_row_s<1>(mode, p, t1 - t0, s, e0, e1);
 }
 
-// Whole batched solve after the pointer block is set.
-pm_status enqueue_batch(pm_plan* h, hipStream_t s, int n_iter, bool err) {
-    if (n_iter == 0) {
-        PM_TRY(pm::launch_batch_wrap(h->bio, h->masks, h->prep_tasks, h->n_prep_tasks, s), "batch wrap");
-        if (!err) return PM_OK;
-    }
-    PM_TRY(pm::launch_batch_norm(h->bio, h->prep_tasks, h->n_prep_tasks, h->part_m, s), "batch norm");
-    PM_TRY(pm::launch_batch_tile(h->bio, h->masks, h->prep_tasks, h->n_prep_tasks, h->mask_prep0, h->part_m, s),
-           "batch tile");
-    PM_TRY(batch_row(h, pm::ROW_INIT, s), "batch row init");
-    // All iterations of one group of masks before the next group of the same
-    // chain, so that the group's working set stays cache-resident across its
-    // iterations; groups alternate between the chains, which run
-    // concurrently (fork and join through events).
+// n_iter iterations of every mask: all iterations of one group of masks
+// before the next group of the same chain, so that the group's working set
+// stays cache-resident across its iterations; groups alternate between the
+// chains, which run concurrently (fork and join through events on s).  The
+// last row pass of a group runs in `last_mode`.
+pm_status enqueue_groups(pm_plan* h, hipStream_t s, int n_iter, int last_mode) {
     const int chains = std::min<int>(h->chains, (int)h->groups.size());
     for (int c = 1; c < chains; ++c) {
         PM_TRY(hipEventRecord(h->fork_ev[c - 1], s), "hipEventRecord(fork)");
@@ -490,7 +485,7 @@ pm_status enqueue_batch(pm_plan* h, hipStream_t s, int n_iter, bool err) {
         hipStream_t cs = c == 0 ? s : h->side[c - 1];
         for (int nu = 0; nu < n_iter; ++nu) {
             PM_TRY(batch_col(h, pm::COL_ITER_NE, cs, nullptr, nullptr, g.c0, g.c1), "batch column pass");
-            const int mode = nu < n_iter - 1 ? pm::ROW_ITER_NE : (err ? pm::ROW_LAST_FWD_NE : pm::ROW_LAST_NE);
+            const int mode = nu < n_iter - 1 ? pm::ROW_ITER_NE : last_mode;
             PM_TRY(batch_row(h, mode, cs, nullptr, nullptr, g.r0, g.r1), "batch row pass");
         }
     }
@@ -498,6 +493,21 @@ pm_status enqueue_batch(pm_plan* h, hipStream_t s, int n_iter, bool err) {
         PM_TRY(hipEventRecord(h->join_ev[c - 1], h->side[c - 1]), "hipEventRecord(join)");
         PM_TRY(hipStreamWaitEvent(s, h->join_ev[c - 1], 0), "hipStreamWaitEvent(join)");
     }
+    return PM_OK;
+}
+
+// Whole batched solve after the pointer block is set.
+pm_status enqueue_batch(pm_plan* h, hipStream_t s, int n_iter, bool err) {
+    if (n_iter == 0) {
+        PM_TRY(pm::launch_batch_wrap(h->bio, h->masks, h->prep_tasks, h->n_prep_tasks, s), "batch wrap");
+        if (!err) return PM_OK;
+    }
+    PM_TRY(pm::launch_batch_norm(h->bio, h->prep_tasks, h->n_prep_tasks, h->part_m, s), "batch norm");
+    PM_TRY(pm::launch_batch_tile(h->bio, h->masks, h->prep_tasks, h->n_prep_tasks, h->mask_prep0, h->part_m, s),
+           "batch tile");
+    PM_TRY(batch_row(h, pm::ROW_INIT, s), "batch row init");
+    pm_status st = enqueue_groups(h, s, n_iter, err ? pm::ROW_LAST_FWD_NE : pm::ROW_LAST_NE);
+    if (st != PM_OK) return st;
     if (err) {
         PM_TRY(batch_col(h, pm::COL_ERR, s), "batch column error");
         PM_TRY(pm::launch_batch_finalize(h->bio, h->masks, h->count, h->part, s), "batch finalize");
@@ -605,32 +615,40 @@ std::string tune_key(int device, int count, const int* heights, const int* width
     return os.str();
 }
 
-// Average device time of `iters` batched iterations (column + row pass),
-// summed from the launches' own start/end events.
-hipError_t time_batch(pm_plan* h, int iters, double* ms_out) {
-    std::vector<hipEvent_t> ev(4 * (size_t)iters, nullptr);
-    hipError_t e = hipSuccess;
-    for (auto& x : ev)
-        if (e == hipSuccess) e = hipEventCreate(&x);
-    for (int w = 0; w < 2 && e == hipSuccess; ++w) {  // warm-up
-        e = batch_col(h, pm::COL_ITER_NE, h->stream);
-        if (e == hipSuccess) e = batch_row(h, pm::ROW_ITER_NE, h->stream);
+// Average device time of one batched iteration run the way a solve runs it:
+// `iters` iterations of every group on the plan's concurrent chains,
+// captured in a graph (on the capture stream) and replayed twice on the
+// plan's stream; the second replay is timed.
+pm_status time_batch(pm_plan* h, int iters, double* ms_out) {
+    hipGraph_t graph = nullptr;
+    PM_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture(tune)");
+    pm_status st = enqueue_groups(h, h->cap_stream, iters, pm::ROW_ITER_NE);
+    hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
+    if (st != PM_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
     }
-    for (int i = 0; i < iters && e == hipSuccess; ++i) {
-        e = batch_col(h, pm::COL_ITER_NE, h->stream, ev[4 * i], ev[4 * i + 1]);
-        if (e == hipSuccess) e = batch_row(h, pm::ROW_ITER_NE, h->stream, ev[4 * i + 2], ev[4 * i + 3]);
-    }
+    if (ec != hipSuccess) return fail_hip(ec, "hipStreamEndCapture(tune)");
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate(tune)");
+    hipEvent_t a = nullptr, b = nullptr;
+    e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, h->stream);  // untimed
+    if (e == hipSuccess) e = hipEventRecord(a, h->stream);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(b, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    double tot = 0.0;
-    for (int i = 0; i < 2 * iters && e == hipSuccess; ++i) {
-        float ms = 0.f;
-        e = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
-        tot += ms;
-    }
-    for (auto& x : ev)
-        if (x) (void)hipEventDestroy(x);
-    *ms_out = tot / iters;
-    return e;
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipGraphExecDestroy(exec);
+    if (e != hipSuccess) return fail_hip(e, "tune timing");
+    *ms_out = (double)ms / iters;
+    return PM_OK;
 }
 
 // Picks the FFT schedule of a batched plan: PHASEMASK_SCHEDULE forces one;
@@ -673,7 +691,8 @@ pm_status tune_batch(pm_plan* h, const std::vector<BatchLayout>& layouts, const 
         h->sched = sc;
         PM_TRY(upload_layout(h, layouts[sc]), "upload layout");
         double ms = 0.0;
-        PM_TRY(time_batch(h, 5, &ms), "tune timing");
+        const pm_status tst = time_batch(h, kTuneIterations, &ms);
+        if (tst != PM_OK) return tst;
         if (std::getenv("PHASEMASK_LOG") != nullptr)
             std::fprintf(stderr, "phasemask tune %s schedule %d: %.1f us/iteration\n", key.c_str(), sc, ms * 1e3);
         if (ms < best) {
@@ -1042,13 +1061,6 @@ pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights
         (e = hipMemcpy(h->mask_prep0, prep0.data(), count * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(h->tw_batch, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
         return bail(e, "hipMemcpy(plan)");
-    const std::string key = tune_key(h->device, count, heights, widths);
-    pm_status ts = tune_batch(h, layouts, key);
-    if (ts != PM_OK) {
-        free_plan(h);
-        return ts;
-    }
-    if ((e = upload_layout(h, layouts[h->sched])) != hipSuccess) return bail(e, "hipMemcpy(layout)");
     if ((e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess)
         return bail(e, "hipStreamCreate");
     for (int c = 1; c < h->chains; ++c) {
@@ -1061,9 +1073,16 @@ pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights
         if ((e = hipEventCreateWithFlags(&j, hipEventDisableTiming)) != hipSuccess) return bail(e, "hipEventCreate");
         h->join_ev.push_back(j);
     }
+    const std::string key = tune_key(h->device, count, heights, widths);
+    pm_status ts = tune_batch(h, layouts, key);
+    if (ts != PM_OK) {
+        free_plan(h);
+        return ts;
+    }
+    if ((e = upload_layout(h, layouts[h->sched])) != hipSuccess) return bail(e, "hipMemcpy(layout)");
     h->ws_bytes = off + npart * sizeof(double) + prep.size() * (sizeof(double) + sizeof(pm::BatchTask)) +
                   (max_col + max_row) * sizeof(pm::BatchTask) + count * (sizeof(pm::BatchMask) + sizeof(int)) +
-                  sizeof(pm::BatchIo) + pm::kBatchMaxLen * sizeof(float2);
+                  sizeof(pm::BatchIo) + tw.size() * sizeof(float2);
     *out = h;
     return PM_OK;
 }
