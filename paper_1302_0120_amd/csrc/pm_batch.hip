@@ -21,6 +21,10 @@ struct BatchShape {
     static constexpr int P = batch_points(SCHED, L);
     static constexpr int G = batch_lines(SCHED, L);
     static constexpr int FLOATS2 = LdsPlan<L, G, 1>::FLOATS2;  // one exchange buffer (LdsPlan)
+    // Last FFT stage across lanes where the tile has the lane layout for it
+    // (a strip of kC columns, or 4 rows): 16-16-4 at 1024.
+    static constexpr bool SW_COL = lane_swap_plan(L, P) && G == kC;
+    static constexpr bool SW_ROW = lane_swap_plan(L, P) && G == 4;
 };
 
 template <int SCHED>
@@ -38,13 +42,15 @@ constexpr int batch_lds_floats2() {
 #define PM_COL_CASE(L)                                                                    \
     case L:                                                                               \
         a.tw = p.tw + batch_twiddle_offset(SCHED, L);                                     \
-        col_body<L, BatchShape<SCHED, L>::P, BatchShape<SCHED, L>::G, MODE, false, 1>(    \
+        col_body<L, BatchShape<SCHED, L>::P, BatchShape<SCHED, L>::G, MODE,               \
+                 BatchShape<SCHED, L>::SW_COL, 1>(                                        \
             a, task.first, slot, lds, red);                                               \
         break;
 #define PM_ROW_CASE(L)                                                                    \
     case L:                                                                               \
         a.tw = p.tw + batch_twiddle_offset(SCHED, L);                                     \
-        row_body<L, BatchShape<SCHED, L>::P, BatchShape<SCHED, L>::G, MODE, false, 1>(    \
+        row_body<L, BatchShape<SCHED, L>::P, BatchShape<SCHED, L>::G, MODE,               \
+                 BatchShape<SCHED, L>::SW_ROW, 1>(                                        \
             a, task.first, pin, pout, slot, lds, red);                                    \
         break;
 

@@ -549,22 +549,36 @@ __host__ __device__ constexpr int last_stage_ns(int L, int P, int NS = 1) {
     return NS * stage_radix(L, P, NS) >= L ? NS : last_stage_ns(L, P, NS * stage_radix(L, P, NS));
 }
 
-// Plans whose last stage is radix 2 right after a stage of radix P (one
-// butterfly per thread), e.g. 8-8-8-2 at 1024, 16-16-2 at 512, 8-8-2 at 128:
-// there the last stage can take its operands across lanes instead of through
-// LDS (fft_last_radix2_lanes), provided lanes i and i + 32 of every wave hold
-// threads j and j + T/2 of one line.  T % 16 == 0 keeps the lane layouts of
-// the passes whole (8 threads of a line per half-wave and column).
-__host__ __device__ constexpr bool lane_swap_plan(int L, int P) {
-    return !lds_mode(L) && stage_radix(L, P, last_stage_ns(L, P)) == 2 && last_stage_ns(L, P) > P &&
-           stage_radix(L, P, last_stage_ns(L, P) / P) == P && (L / P) % 16 == 0;
+// Plans whose last stage has radix Q = 2 or 4 right after a stage of radix P
+// (one butterfly per thread), e.g. 8-8-8-2 at 1024, 16-16-2 at 512, 8-8-2 at
+// 128, 16-16-4 at 1024: there the last stage can take its operands across
+// lanes instead of through LDS (fft_last_radix2_lanes, _radix4_lanes),
+// provided lanes i + 64 k / Q, k < Q, of every wave hold threads j + k T / Q
+// of one line.  T % 16 == 0 keeps the lane layouts of the passes whole.
+// lane_group is that Q, 0 for other plans.
+__host__ __device__ constexpr int lane_group(int L, int P) {
+    return (!lds_mode(L) && last_stage_ns(L, P) > P && stage_radix(L, P, last_stage_ns(L, P) / P) == P &&
+            (L / P) % 16 == 0 &&
+            (stage_radix(L, P, last_stage_ns(L, P)) == 2 || stage_radix(L, P, last_stage_ns(L, P)) == 4))
+               ? stage_radix(L, P, last_stage_ns(L, P))
+               : 0;
 }
+__host__ __device__ constexpr bool lane_swap_plan(int L, int P) { return lane_group(L, P) != 0; }
 
 // Exchanges one float between the halves of a wave: afterwards lanes 0..31
 // hold in `hi` the `lo` of lane i + 32, and lanes 32..63 hold in `lo` the
 // `hi` of lane i - 32; the other two values stay.
 __device__ __forceinline__ void swap_halves(float& lo, float& hi) {
     const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+    lo = __uint_as_float(r[0]);
+    hi = __uint_as_float(r[1]);
+}
+
+// The same between the quarters of each half: afterwards lanes of quarters
+// 0 and 2 hold in `hi` the `lo` of lane i + 16, and lanes of quarters 1 and 3
+// hold in `lo` the `hi` of lane i - 16.
+__device__ __forceinline__ void swap_quarters(float& lo, float& hi) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
     lo = __uint_as_float(r[0]);
     hi = __uint_as_float(r[1]);
 }
@@ -608,6 +622,53 @@ __device__ __forceinline__ void fft_last_radix2_lanes(float2 (&v)[P], int j, con
     for (int t = 0; t < P; ++t) v[t] = y[t];
 }
 
+// The last stage (radix 4, sub-length L/4) of a plan with lane_group 4,
+// lanes i, i + 16, i + 32, i + 48 holding threads j, j + T/4, j + T/2,
+// j + 3T/4 of the line (quarter s of the wave holds the threads with
+// j / (T/4) = s).  After the stage before it, v[q] of the thread in quarter r
+// is element (L/4) r + j % (T/4) + (T/4) q.  Butterfly m of the thread in
+// quarter s takes elements b + (L/4) r, r < 4, with b = j + T m, i.e. v[s +
+// 4m] of the thread in quarter r: for each m the 4 x 4 block v[4m .. 4m + 3]
+// of the four threads is transposed (one half swap and one quarter swap per
+// pair of registers), after which v[4m + r] holds input r.  Twiddles,
+// arithmetic and result slots (v[m + q P/4]) are those of the LDS path.
+template <int L, int P, int OFF, bool INV>
+__device__ __forceinline__ void fft_last_radix4_lanes(float2 (&v)[P], int j, const LineTwiddles<L, P>& tw) {
+    constexpr int T = L / P;
+    constexpr int NS = L / 4;
+    constexpr int M = P / 4;
+    float2 y[P];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        float2 x[4] = {v[4 * m], v[4 * m + 1], v[4 * m + 2], v[4 * m + 3]};
+        swap_halves(x[0].x, x[2].x);
+        swap_halves(x[0].y, x[2].y);
+        swap_halves(x[1].x, x[3].x);
+        swap_halves(x[1].y, x[3].y);
+        swap_quarters(x[0].x, x[1].x);
+        swap_quarters(x[0].y, x[1].y);
+        swap_quarters(x[2].x, x[3].x);
+        swap_quarters(x[2].y, x[3].y);
+        const int k = j + T * m;  // < L/4, so this is also (j + T m) mod NS
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+            float2 w;
+            if constexpr (LineTwiddles<L, P>::PRELOAD) {
+                w = tw.w[OFF + m * 3 + (r - 1)];
+            } else {
+                w = *elem_ptr(tw.table, (unsigned)(twiddle_block(L, P, NS) + (r - 1) * NS + k));
+            }
+            if constexpr (INV) w.y = -w.y;
+            x[r] = cmul(x[r], w);
+        }
+        dft<4, INV>(x);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) y[m + q * M] = x[q];
+    }
+#pragma unroll
+    for (int t = 0; t < P; ++t) v[t] = y[t];
+}
+
 // One Stockham stage on the thread's P register points (see header); OFF is
 // this stage's first entry in the thread's twiddle registers, PAR the LDS
 // buffer this stage's exchange uses when NBUF == 2.  SW: the lanes hold
@@ -620,7 +681,8 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, i
     constexpr int R = stage_radix(L, P, NS);
     constexpr int M = P / R;
     constexpr bool LAST = (NS * R == L);
-    constexpr bool LANES_NEXT = SW && lane_swap_plan(L, P) && !LAST && NS * R * 2 == L;
+    constexpr int QN = lane_group(L, P);
+    constexpr bool LANES_NEXT = SW && QN != 0 && !LAST && NS * R * QN == L;
     float2* buf = (NBUF == 2 && PAR == 1) ? line + stride : line;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -654,7 +716,11 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, i
     }
     if constexpr (LANES_NEXT) {
         static_assert(M == 1, "one butterfly per thread before the cross-lane stage");
-        fft_last_radix2_lanes<L, P, (NS > 1 ? OFF + M * (R - 1) : OFF), INV>(v, j, tw);
+        if constexpr (QN == 2) {
+            fft_last_radix2_lanes<L, P, (NS > 1 ? OFF + M * (R - 1) : OFF), INV>(v, j, tw);
+        } else {
+            fft_last_radix4_lanes<L, P, (NS > 1 ? OFF + M * (R - 1) : OFF), INV>(v, j, tw);
+        }
     } else if constexpr (!LAST) {
         __syncthreads();
 #pragma unroll

@@ -111,9 +111,10 @@ struct LineShape {
 // loads are 64 / kC consecutive rows of one strip: one contiguous run.
 // `lds` holds LdsPlan<H, G, NBMAX>::FLOATS2 elements, `red` red_slots(G T) doubles;
 // the FP64 partials go to part_slot[0 .. red_slots(G T)); a.tw is the staged
-// twiddle table of (H, P).  SW (one strip, G = kC): lanes i and i + 32 of a
-// wave hold rows j and j + T/2 of one column, 8 rows per half-wave, so a
-// lane_swap_plan runs its last FFT stage across lanes.
+// twiddle table of (H, P).  SW (one strip, G = kC): with Q = lane_group(H, P),
+// lanes i + 64 k / Q (k < Q) of a wave hold rows j + k T / Q of one column,
+// 16 / Q rows per lane group and column, so the plan runs its last FFT stage
+// across lanes.
 template <int H, int P, int G, int MODE, bool SW = false, int NBMAX = 2>
 __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double* part_slot,
                                          float2* lds, double* red) {
@@ -126,10 +127,11 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
     const int tid = threadIdx.x;
     int c, j, sl;
     if constexpr (SW) {
-        static_assert(G == kC && kC == 4 && T % 16 == 0, "one strip, 8 rows per half-wave");
+        constexpr int Q = lane_group(H, P);
+        static_assert(Q != 0 && G == kC && kC == 4 && T % 16 == 0, "one strip, whole lane groups");
         const int lane = tid & 63;
         c = lane & 3;
-        j = (tid >> 6) * 8 + ((lane >> 2) & 7) + (lane >> 5) * (T / 2);
+        j = (tid >> 6) * (16 / Q) + ((lane >> 2) % (16 / Q)) + (lane / (64 / Q)) * (T / Q);
         sl = 0;
     } else {
         c = tid & (kC - 1);
@@ -255,9 +257,9 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
 // c), c fastest: row row0 + rho, thread index within the row j = jhi kC + c.
 // For a fixed t the element (row, j + T t) lies in strip jhi + (T / kC) t at
 // column c, so a wave's loads are runs of G kC contiguous elements; a.tw is
-// the staged twiddle table of (W, P).  SW (G = 4): lanes i and i + 32 of a
-// wave hold threads j and j + T/2 of one row (jhi and jhi + T/8), so a
-// lane_swap_plan runs its last FFT stage across lanes.
+// the staged twiddle table of (W, P).  SW (G = 4): with Q = lane_group(W, P),
+// lanes i + 64 k / Q (k < Q) of a wave hold threads j + k T / Q of one row
+// (jhi + k T / (4 Q)), so the plan runs its last FFT stage across lanes.
 template <int W, int P, int G, int MODE, bool SW = false, int NBMAX = 2>
 __device__ __forceinline__ void row_body(const RowParams& a, int row0, const float* phase_in,
                                          float* phase_out, double* part_slot, float2* lds,
@@ -271,11 +273,12 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
     const int tid = threadIdx.x;
     int c, rho, jhi;
     if constexpr (SW) {
-        static_assert(G == 4 && kC == 4 && T % 16 == 0, "4 rows, two strips per half-wave");
+        constexpr int Q = lane_group(W, P);
+        static_assert(Q != 0 && G == 4 && kC == 4 && T % 16 == 0, "4 rows, whole lane groups");
         const int lane = tid & 63;
         c = lane & 3;
         rho = (lane >> 2) & 3;
-        jhi = (tid >> 6) * 2 + ((lane >> 4) & 1) + (lane >> 5) * (T / 8);
+        jhi = (tid >> 6) * (4 / Q) + ((lane >> 4) % (4 / Q)) + (lane / (64 / Q)) * (T / (4 * Q));
     } else {
         c = tid & (kC - 1);
         rho = (tid / kC) % G;
