@@ -275,9 +275,9 @@ pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights
  *                     returned mask (the last history entry of a one-mask
  *                     solve).
  * Results equal `count` separate phasemask_solve calls on the same inputs
- * up to FP32 rounding; under schedule 0 (the one-mask radix schedules for
- * sides below 1024) the phases of masks without a side of 1024 are bitwise
- * equal and the errors equal up to the order of the FP64 sums.
+ * up to FP32 rounding; where a mask's sides run the one-mask radix plans
+ * (schedule 1 at 64 and 512 points) its phases are bitwise equal and its
+ * error equal up to the order of the FP64 sums.
  * Errors: PM_EINVAL for NULL pointer arrays, n_iter < 0 or misaligned
  * arguments; PM_ESTATE for a one-mask handle; PM_EDEVICE.
  */

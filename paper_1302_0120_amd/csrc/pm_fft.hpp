@@ -818,18 +818,24 @@ __host__ __device__ constexpr int fft_parity_after() {
                        : (PAR + exchanges_from(L, P, 1) - ((SW && lane_swap_plan(L, P)) ? 1 : 0)) & 1;
 }
 
-// Points per thread for a line of L points.  At 1024, P = 8 (radix 8-8-8-2,
-// 128 threads per line) measured faster than P = 16 (16-16-4, 64 threads):
-// one more LDS exchange, but two waves per SIMD instead of one to hide the
-// load latency behind (the one-mask 1024^2 passes hold one line per SIMD).
+// Points per thread for a line of L points.  The one-mask passes run one
+// work-group of 4 lines per CU or fewer, so more threads per line (smaller
+// P) hide more latency, at the cost of more stages: measured on MI355X
+// (solve time per iteration), P = 4 (radix 4-4-4 ... with the last stage
+// across lanes) is fastest for 64 .. 256 points (64^2: 6.0 -> 5.2 us
+// against P = 8; 256^2: 8.5 -> 6.4 us against P = 16), P = 8 for 512
+// (8-8-8: 10.1 -> 8.5 us against 16-16-2) and 1024 (8-8-8-2: P = 16 is 8%
+// slower, P = 4 12%), P = 16 from 2048 on (P = 8 is within 0.5% at 2048
+// and does not fit a 4-line work-group at 4096).
 __host__ __device__ constexpr int points_per_thread(int L) {
     return lds_mode(L) ? L / lds_threads(L)
          : L == 800 ? 20
          : L == 600 ? 30
          : L == 1080 ? 30
          : L == 1920 ? 60
-         : L == 1024 ? 8
-         : (L >= 256 ? 16 : (L >= 32 ? 8 : 4));
+         : (L == 512 || L == 1024) ? 8
+         : (L >= 64 && L <= 256) ? 4
+         : (L >= 2048 ? 16 : (L >= 32 ? 8 : 4));
 }
 
 // Rows per work-group of the one-mask row pass for rows of W points.
