@@ -251,8 +251,9 @@ pm_status phasemask_fft2(pm_handle h, const void* in, void* out, int inverse);
  * forces schedule k; else a choice cached for the same multiset of sizes on
  * the same GPU architecture (in this process, or in the file named by
  * PHASEMASK_TUNE_CACHE, one "key schedule" line per entry, appended to);
- * else each schedule runs a few iterations on the plan's own buffers on
- * `stream` (synchronised) and the fastest is kept.  PM_FLAG_NO_TUNE selects
+ * else each schedule runs a few iterations on the plan's own buffers, grouped
+ * and spread over the chains as a solve runs them (one captured graph,
+ * replayed on `stream`, synchronised), and the fastest is kept.  PM_FLAG_NO_TUNE selects
  * schedule 0 without timing.  PHASEMASK_LOG=1 prints the timings to stderr.
  * Errors: PM_EINVAL for NULL arguments, count < 1 or an out-of-range
  * PHASEMASK_SCHEDULE, PHASEMASK_GROUP_MB or PHASEMASK_CHAINS; PM_ENOMEM;
