@@ -128,6 +128,7 @@ struct pm_plan {
     int device = 0;
     hipStream_t stream = nullptr;      // caller's stream
     hipStream_t cap_stream = nullptr;  // private stream used only for graph capture
+    int rows = 0;                      // rows per row-pass work-group (rows_for_plan)
     int nwg_row = 0, nwg_col = 0, stride = 0;
     int slots_row = 0, slots_col = 0;  // FP64 partials per row / column pass (one per reduction group)
     int num_cu = 0;                    // compute units of the device
@@ -749,14 +750,6 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
     h->N = height * width;
     h->flags = flags;
     h->stream = (hipStream_t)stream;
-    h->nwg_row = height / pm::row_lines(width);
-    h->nwg_col = width / pm::kC;
-    // Threads per work-group: lines x (length / points per thread).
-    h->slots_row = h->nwg_row * pm::red_slots(pm::row_lines(width) * (width / pm::points_per_thread(width)));
-    h->slots_col = h->nwg_col * pm::red_slots(pm::kC * (height / pm::points_per_thread(height)));
-    h->stride = h->slots_row > h->slots_col ? h->slots_row : h->slots_col;
-    if (h->stride < kNormGrid) h->stride = kNormGrid;
-
     auto bail = [&](hipError_t e, const char* what) {
         pm_status s = fail_hip(e, what);
         free_plan(h);
@@ -766,6 +759,14 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
     if (e != hipSuccess) return bail(e, "hipGetDevice");
     if ((e = hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device)) != hipSuccess)
         return bail(e, "hipDeviceGetAttribute");
+    h->rows = pm::rows_for_plan(height, width, h->num_cu);
+    h->nwg_row = height / h->rows;
+    h->nwg_col = width / pm::kC;
+    // Threads per work-group: lines x (length / points per thread).
+    h->slots_row = h->nwg_row * pm::red_slots(h->rows * (width / pm::points_per_thread(width)));
+    h->slots_col = h->nwg_col * pm::red_slots(pm::kC * (height / pm::points_per_thread(height)));
+    h->stride = h->slots_row > h->slots_col ? h->slots_row : h->slots_col;
+    if (h->stride < kNormGrid) h->stride = kNormGrid;
     const size_t n = (size_t)h->N;
     if ((e = hipMalloc(&h->X, n * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(iterate)");
     if ((e = hipMalloc(&h->mhat, n * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc(target)");
@@ -795,7 +796,7 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
         };
         std::fprintf(stderr, "phasemask plan %dx%d: rows %s, %d work-groups of %d rows; columns %s, %d work-groups; "
                      "workspace %zu bytes\n", height, width, line(width).c_str(), h->nwg_row,
-                     pm::row_lines(width), line(height).c_str(), h->nwg_col, h->ws_bytes);
+                     h->rows, line(height).c_str(), h->nwg_col, h->ws_bytes);
     }
     *out = h;
     return PM_OK;

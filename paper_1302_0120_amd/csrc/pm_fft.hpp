@@ -849,4 +849,21 @@ __host__ __device__ constexpr int row_lines(int W) {
     return W == 800 ? PM_ROWS_800 : (W == 1920 ? PM_ROWS_1920 : kGR);
 }
 
+// A second, taller row tile for 1920-point rows (0: none).  A 1920-point
+// row work-group holds 123 KB of LDS at 4 rows, so one fits on a CU and
+// 1080 rows make 270 work-groups: two rounds on 256 CUs, the second nearly
+// empty.  Five rows (154 KB, 216 work-groups) run in one round; the plan
+// takes them when that is the case (rows_for_plan).
+__host__ __device__ constexpr int row_lines_alt(int W) { return W == 1920 ? 5 : 0; }
+
+// Rows per work-group of the one-mask row pass of an H x W plan on a GPU with
+// `cus` compute units: the taller tile where it turns two rounds of
+// work-groups into one, else row_lines(W).
+__host__ __device__ constexpr int rows_for_plan(int H, int W, int cus) {
+    return (row_lines_alt(W) != 0 && H % row_lines_alt(W) == 0 && H / row_lines(W) > cus &&
+            H / row_lines_alt(W) <= cus)
+               ? row_lines_alt(W)
+               : row_lines(W);
+}
+
 }  // namespace pm

@@ -434,7 +434,8 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
     if constexpr ((MODE & R_PS) != 0 && (MODE & R_NOERR) == 0) group_sum_store<NT>(acc, part_slot);
 }
 
-// One-mask kernels: kC columns (one strip) or row_lines(W) rows per work-group.
+// One-mask kernels: kC columns (one strip) or G rows per work-group
+// (row_lines(W), or row_lines_alt(W) where the plan takes it).
 template <int H, int MODE>
 __global__ void __launch_bounds__(kC * LineShape<H>::T)
 k_col(ColParams a) {
@@ -445,18 +446,18 @@ k_col(ColParams a) {
         a, blockIdx.x, a.part + blockIdx.x * red_slots(NT), lds, red);
 }
 
-template <int W, int MODE>
-__global__ void __launch_bounds__(row_lines(W) * LineShape<W>::T)
+template <int W, int MODE, int G = row_lines(W)>
+__global__ void __launch_bounds__(G * LineShape<W>::T)
 k_row(RowParams a) {
-    constexpr int NT = row_lines(W) * LineShape<W>::T;
-    __shared__ float2 lds[LdsPlan<W, row_lines(W)>::FLOATS2];
+    constexpr int NT = G * LineShape<W>::T;
+    __shared__ float2 lds[LdsPlan<W, G>::FLOATS2];
     __shared__ double red[red_slots(NT)];
     const float* pin = nullptr;
     float* pout = nullptr;
     if constexpr ((MODE & RIN_PHASE) != 0) pin = a.io->phase_in;
     if constexpr ((MODE & ROUT_PHASE) != 0) pout = a.io->phase_out;
-    row_body<W, LineShape<W>::P, row_lines(W), MODE, lane_swap_plan(W, LineShape<W>::P) && row_lines(W) == 4>(
-        a, blockIdx.x * row_lines(W), pin, pout, a.part + blockIdx.x * red_slots(NT), lds, red);
+    row_body<W, LineShape<W>::P, G, MODE, lane_swap_plan(W, LineShape<W>::P) && G == 4>(
+        a, blockIdx.x * G, pin, pout, a.part + blockIdx.x * red_slots(NT), lds, red);
 }
 
 // Intensity-loss kernels over a batch of same-size phases, sample = blockIdx.y.

@@ -51,21 +51,39 @@ hipError_t launch(void (*kern)(Params), int grid, int block, hipStream_t s, hipE
     X(ROW_INIT) X(ROW_ITER) X(ROW_LAST) X(ROW_LAST_FWD) X(ROW_GAP) X(ROW_ITER_NE) X(ROW_LAST_NE) \
     X(ROW_INIT_Z) X(ROW_RAAR) X(ROW_RAAR_LAST) X(ROW_RAAR_LAST_FWD)
 #define PM_ROW_CASE(M)                                                                         \
-    case M: return launch(k_row<PM_L, M>, grid, block, s, ev0, ev1, p);                        \
-    case M | R_ILLUM: return launch(k_row<PM_L, M | R_ILLUM>, grid, block, s, ev0, ev1, p);
+    case M: return launch(k_row<PM_L, M, G>, grid, block, s, ev0, ev1, p);                     \
+    case M | R_ILLUM: return launch(k_row<PM_L, M | R_ILLUM, G>, grid, block, s, ev0, ev1, p);
 
-hipError_t PM_CAT(launch_row_, PM_L)(int mode, const RowParams& p, int grid, hipStream_t s,
-                                     hipEvent_t ev0, hipEvent_t ev1) {
-    const int block = row_lines(PM_L) * LineShape<PM_L>::T;
+namespace {
+
+template <int G>
+hipError_t launch_rows(int mode, const RowParams& p, int grid, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    const int block = G * LineShape<PM_L>::T;
     switch (mode) {
         PM_ROW_SOLVE_MODES(PM_ROW_CASE)
-        case ROW_FFT_FWD: return launch(k_row<PM_L, ROW_FFT_FWD>, grid, block, s, ev0, ev1, p);
-        case ROW_FFT_INV: return launch(k_row<PM_L, ROW_FFT_INV>, grid, block, s, ev0, ev1, p);
+        case ROW_FFT_FWD: return launch(k_row<PM_L, ROW_FFT_FWD, G>, grid, block, s, ev0, ev1, p);
+        case ROW_FFT_INV: return launch(k_row<PM_L, ROW_FFT_INV, G>, grid, block, s, ev0, ev1, p);
         default: return hipErrorInvalidValue;
     }
 }
+
+}  // namespace
 #undef PM_ROW_CASE
 #undef PM_ROW_SOLVE_MODES
+
+// The row tile is p.H / grid rows: row_lines(PM_L), or row_lines_alt(PM_L)
+// where the length has one.
+hipError_t PM_CAT(launch_row_, PM_L)(int mode, const RowParams& p, int grid, hipStream_t s,
+                                     hipEvent_t ev0, hipEvent_t ev1) {
+    if (grid <= 0) return hipErrorInvalidValue;
+    const int g = p.H / grid;
+    if (g * grid != p.H) return hipErrorInvalidValue;
+    if (g == row_lines(PM_L)) return launch_rows<row_lines(PM_L)>(mode, p, grid, s, ev0, ev1);
+    if constexpr (row_lines_alt(PM_L) != 0) {
+        if (g == row_lines_alt(PM_L)) return launch_rows<row_lines_alt(PM_L)>(mode, p, grid, s, ev0, ev1);
+    }
+    return hipErrorInvalidValue;
+}
 
 hipError_t PM_CAT(launch_col_, PM_L)(int mode, const ColParams& p, int grid, hipStream_t s,
                                      hipEvent_t ev0, hipEvent_t ev1) {
