@@ -162,6 +162,34 @@ def bench_paper_slm(torch, binding, synth, steps=20):
     return res
 
 
+def bench_other_configs(torch, binding, synth, steps=20):
+    """The two other one-mask spot workloads: 64 x 64 (5 spots, 100
+    iterations) and 512 x 512 (20 spots, 50 iterations), each one
+    graph-replayed solve with the FP64 history, inputs resident; ms per mask
+    and the final Fourier error."""
+    dev = torch.device("cuda", 0)
+    res = {}
+    for name, spec in (("spots64x100", synth.SPOTS_64), ("spots512x50", synth.SPOTS_512)):
+        m, phi0 = synth.spot_problem(spec)
+        md = torch.from_numpy(m).to(dev)
+        pd = torch.from_numpy(phi0).to(dev)
+        plan = binding.PhaseMask(spec.height, spec.width, device=dev)
+        out = torch.empty_like(pd)
+        hist = torch.empty(2 * spec.n_iter + 1, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            plan.solve(md, pd, spec.n_iter, out=out, history=hist)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.solve(md, pd, spec.n_iter, out=out, history=hist)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[name] = {"height": spec.height, "width": spec.width, "n_iter": spec.n_iter, "ms_per_mask": ms,
+                     "us_per_iteration": ms * 1e3 / spec.n_iter, "final_fourier_error": float(hist[-1].item())}
+        plan.close()
+    return res
+
+
 def bench_next_rows(torch, binding, synth, m, phi0, plan_steps=10, reps=100):
     """The other device entry points on the same 1024 x 1024 workload: RAAR
     (100 iterations), the paper's initial mask, the physical error of Eq. 8,
@@ -387,6 +415,7 @@ def main():
         line["paper_slm"] = bench_paper_slm(torch, binding, synth)
     if not args.no_next_rows:
         line["next_rows"] = bench_next_rows(torch, binding, synth, m, phi0)
+        line["other_configs"] = bench_other_configs(torch, binding, synth)
     if not args.no_cpu_baseline:
         rate, cdt = cpu_baseline(m, phi0, args.cpu_iters)
         line["cpu_baseline"] = {
