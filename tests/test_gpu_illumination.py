@@ -60,7 +60,7 @@ def test_uniform_illumination_is_the_phase_only_solve(pmb):
 
 
 @pytest.mark.parametrize("shape,aperture", [((64, 64), None), ((256, 128), None), ((512, 512), 0.45),
-                                            ((600, 800), None), ((1024, 1024), 0.4)])
+                                            ((600, 800), None), ((1024, 1024), 0.4), ((1080, 1920), 0.45)])
 def test_one_iteration_with_illumination(pmb, shape, aperture):
     h, w = shape
     print(f"illumination one iteration {shape} aperture={aperture}", flush=True)

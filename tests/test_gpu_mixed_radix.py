@@ -113,11 +113,14 @@ def test_paper_slm_workload(pmb):
     assert abs(hg[-1] - ef_out) / ef_out <= 1e-5
 
 
-def test_paper_slm_other_entry_points(pmb):
+@pytest.mark.parametrize("shape", [(600, 800), (1080, 1920)])
+def test_panel_other_entry_points(pmb, shape):
     """RAAR (one iteration exact), the paper's initial mask, the physical
-    error and the intensity-loss adjoint on the 800 x 600 panel."""
-    h, w = 600, 800
-    rng = np.random.default_rng(8600)
+    error and the intensity-loss adjoint on the 800 x 600 panel and on a
+    1080-row 1920-column panel (whose row passes take 5-row work-groups)."""
+    h, w = shape
+    print(f"panel entry points {shape}", flush=True)
+    rng = np.random.default_rng(8600 + h)
     m = synth.spot_amplitude(h, w, 25, 2.0, 0.5, 1.0, rng)
     phi0 = synth.uniform_phase(h, w, rng)
     plan = pmb.PhaseMask(h, w)
