@@ -387,10 +387,11 @@ __host__ __device__ constexpr int lds_twiddles_from(int L, int NS) {
 // Radix of the stage that starts at sub-transform length NS.  Powers of two
 // take P, P, ..., remainder.  The non-power-of-two lengths of common SLM
 // panels (800 x 600, 1920 x 1080) take fixed mixed-radix sequences whose
-// radices divide P: 800 = 20*10*4 (P = 20), 600 = 6*10*10 (P = 30),
-// 1080 = 30*6*6 (P = 30), 1920 = 12*10*4*4 (P = 60).  The largest radix
-// goes first, where no inter-stage twiddles are needed.
+// radices divide P: 800 = 10*10*2*2*2 (P = 10; 20*10*4 with P = 20),
+// 600 = 6*10*10 (P = 30), 1080 = 30*6*6 (P = 30), 1920 = 12*10*4*4 (P = 60).
+// The largest radix goes first, where no inter-stage twiddles are needed.
 __host__ __device__ constexpr int stage_radix(int L, int P, int NS) {
+    if (L == 800 && P == 10) return NS <= 10 ? 10 : 2;
     if (L == 800) return NS == 1 ? 20 : (NS == 20 ? 10 : 4);
     if (L == 600) return NS == 1 ? 6 : 10;
     if (L == 1080) return NS == 1 ? 30 : 6;
@@ -829,7 +830,7 @@ __host__ __device__ constexpr int fft_parity_after() {
 // and does not fit a 4-line work-group at 4096).
 __host__ __device__ constexpr int points_per_thread(int L) {
     return lds_mode(L) ? L / lds_threads(L)
-         : L == 800 ? 20
+         : L == 800 ? 10
          : L == 600 ? 30
          : L == 1080 ? 30
          : L == 1920 ? 60
