@@ -28,8 +28,8 @@ ROW_BYTES_PER_PX = 8 + 8       # read iterate, write iterate
 # WRITE_SIZE x 1.0, factors from a plain 64 MiB copy; summary under profiles/),
 # valid only for the kernel sources it was taken on (hash below).
 KERNEL_SOURCES = ("pm_common.h", "pm_fft.hpp", "pm_kernels.hpp", "pm_pass.hip")
-TRAFFIC_SOURCE_HASH = "e91516528ebba4dd"
-TRAFFIC_BYTES = {"row pass": 16944141, "column pass": 21127581}
+TRAFFIC_SOURCE_HASH = "867b77c59feb30a6"
+TRAFFIC_BYTES = {"row pass": 16944069, "column pass": 21127554}
 
 
 def kernel_source_hash() -> str:
@@ -362,21 +362,47 @@ def main():
     for _ in range(args.warmup):
         plan.solve(md, pd, n_iter, out=out, history=hist)
     torch.cuda.synchronize()
+    # The solves run on torch's current stream (the plan follows it), so
+    # these events bracket the timed region on the kernels' own stream.
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    ev0.record()
     for _ in range(args.steps):
         plan.solve(md, pd, n_iter, out=out, history=hist)
+    ev1.record()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = dt * 1e3 / args.steps
+    region_ms = ev0.elapsed_time(ev1) / args.steps
     final_ef = float(hist[-1].item())
 
-    # Dominant kernel: average duration of each fused pass from the launches'
-    # own start/end events over an iteration sequence on the same stream.
+    # Per-iteration device time inside the timed solves: the difference
+    # between the n_iter-iteration solve and a short one of the same plan
+    # (same graph shape, so the per-solve work -- target preparation, u^0,
+    # final error, finalisation -- cancels).
+    n_short = 20
+    hist_s = torch.empty(2 * n_short + 1, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        plan.solve(md, pd, n_short, out=out, history=hist_s)
+    ev0.record()
+    for _ in range(args.steps):
+        plan.solve(md, pd, n_short, out=out, history=hist_s)
+    ev1.record()
+    torch.cuda.synchronize()
+    short_ms = ev0.elapsed_time(ev1) / args.steps
+    iter_us = (region_ms - short_ms) * 1e3 / (n_iter - n_short)
+
+    # Dominant kernel: the launches' own start/end events over an eager
+    # iteration sequence on the same stream give each pass's share of an
+    # iteration; its average duration in the timed solves is that share of
+    # the per-iteration time above.
     col_ms, row_ms = plan.time_passes(md, pd, reps=args.kernel_reps)
+    col_us = iter_us * col_ms / (col_ms + row_ms)
+    row_us = iter_us * row_ms / (col_ms + row_ms)
     if col_ms >= row_ms:
-        kname, kms, kbytes = "column pass", col_ms, COL_BYTES_PER_PX * npx
+        kname, kms, kbytes = "column pass", col_us * 1e-3, COL_BYTES_PER_PX * npx
     else:
-        kname, kms, kbytes = "row pass", row_ms, ROW_BYTES_PER_PX * npx
+        kname, kms, kbytes = "row pass", row_us * 1e-3, ROW_BYTES_PER_PX * npx
     achieved = kbytes / (kms * 1e-3) / 1e9
     traffic = TRAFFIC_BYTES[kname] if kernel_source_hash() == TRAFFIC_SOURCE_HASH else None
     solve_gbs = (COL_BYTES_PER_PX + ROW_BYTES_PER_PX) * npx * n_iter / (ms_per_step * 1e-3) / 1e9
@@ -402,7 +428,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel_us": kms * 1e3, "bytes_per_launch": kbytes},
-        "passes_us": {"column": col_ms * 1e3, "row": row_ms * 1e3},
+        # per-launch durations in the timed solves (per-iteration device
+        # time split by the eager launch-event ratio), and the eager ones
+        "passes_us": {"column": col_us, "row": row_us},
+        "passes_eager_us": {"column": col_ms * 1e3, "row": row_ms * 1e3},
+        "iteration_us": iter_us,
         "solve_algorithmic_gbs": solve_gbs,
         "final_fourier_error": final_ef,
         "env": environment(torch),
