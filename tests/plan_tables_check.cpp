@@ -1,0 +1,84 @@
+// Host-side consistency check of the transform plans (compiled and run by
+// tests/test_plan_tables_cpu.py; no GPU needed).  Every line plan the
+// library can build -- one-mask lengths with points_per_thread, batched
+// lengths with batch_points of every schedule -- is walked stage by stage:
+//   * the stage radices multiply to the line length;
+//   * the staged twiddle table blocks tile [0, twiddle_entries) exactly, and
+//     every entry's exponent q k L / (NS R) lies in [0, L);
+//   * the batched table offsets add up schedule by schedule;
+// and the cross-lane and row-tile choices are checked on known plans.
+// Prints "ok" and exits 0, or prints the first violation and exits 1.
+#include <cstdio>
+#include <vector>
+
+#include "pm_common.h"
+#include "pm_fft.hpp"
+
+namespace {
+
+int failures = 0;
+
+void check(bool ok, const char* what, int a = 0, int b = 0, int c = 0) {
+    if (!ok && failures++ == 0) std::printf("violation: %s (%d, %d, %d)\n", what, a, b, c);
+}
+
+void walk(int L, int P) {
+    long prod = 1;
+    int next_block = 0;
+    for (int ns = 1; ns < L; ns *= pm::line_stage_radix(L, P, ns)) {
+        const int R = pm::line_stage_radix(L, P, ns);
+        check(R >= 2 && L % (ns * R) == 0, "stage radix divides the remaining length", L, P, ns);
+        if (R < 2) return;
+        prod *= R;
+        if (!pm::lds_mode(L)) check(P % R == 0, "register-scheme radix divides P", L, P, R);
+        if (ns > 1) {
+            check(pm::twiddle_block(L, P, ns) == next_block, "twiddle blocks are contiguous", L, P, ns);
+            next_block += (R - 1) * ns;
+            for (int q = 1; q < R; ++q)
+                for (int k = 0; k < ns; ++k) {
+                    const long e = (long)q * k * (L / (ns * R));
+                    check(e >= 0 && e < L, "twiddle exponent in range", L, q, k);
+                }
+        }
+    }
+    check(prod == L, "radices multiply to L", L, P, (int)prod);
+    check(pm::twiddle_entries(L, P) == next_block, "twiddle_entries is the last block end", L, P, next_block);
+    check(pm::twiddle_entries(L, P) < L, "staged table shorter than L", L, P);
+}
+
+}  // namespace
+
+int main() {
+    const int lengths[] = {16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 600, 800, 1080, 1920};
+    for (int L : lengths) {
+        walk(L, pm::points_per_thread(L));
+        check(L % pm::points_per_thread(L) == 0, "P divides L", L);
+    }
+    int off = 0;
+    for (int s = 0; s < pm::kBatchSchedules; ++s) {
+        for (int L = pm::kBatchMinLen; L <= pm::kBatchMaxLen; L *= 2) {
+            walk(L, pm::batch_points(s, L));
+            check(pm::batch_twiddle_offset(s, L) == off, "batched table offsets add up", s, L, off);
+            off += pm::twiddle_entries(L, pm::batch_points(s, L));
+        }
+    }
+    check(pm::batch_twiddle_offset(pm::kBatchSchedules, 0) == off, "batched table total", off);
+    // cross-lane last stages: radix 2 after radix P, radix 4 after radix P
+    check(pm::lane_group(1024, 8) == 2, "8-8-8-2 takes its radix-2 stage across lanes");
+    check(pm::lane_group(512, 8) == 0, "8-8-8 has no last stage across lanes");
+    check(pm::lane_group(512, 16) == 2, "16-16-2 takes its radix-2 stage across lanes");
+    check(pm::lane_group(1024, 16) == 4, "16-16-4 takes its radix-4 stage across lanes");
+    check(pm::lane_group(256, 4) == 4 && pm::lane_group(64, 4) == 4, "4-4-4(-4) across lanes");
+    check(pm::lane_group(128, 4) == 2, "4-4-4-2 across lanes");
+    check(pm::lane_group(4096, 16) == 0 && pm::lane_group(2048, 16) == 0, "16-16-16 and 16-16-8 stay in LDS");
+    check(pm::lane_group(800, 10) == 0 && pm::lane_group(1920, pm::points_per_thread(1920)) == 0,
+          "mixed-radix plans stay in LDS");
+    // row tiles: five 1920-point rows per work-group only where that makes one round
+    check(pm::rows_for_plan(1080, 1920, 256) == 5, "1080 rows of 1920 take 5-row tiles on 256 CUs");
+    check(pm::rows_for_plan(1920, 1920, 256) == 4, "1920 rows of 1920 keep 4-row tiles");
+    check(pm::rows_for_plan(600, 1920, 256) == 4, "600 rows of 1920 fit one round with 4-row tiles");
+    check(pm::rows_for_plan(1080, 1920, 304) == 4, "270 tiles fit 304 CUs");
+    check(pm::rows_for_plan(1080, 1024, 256) == pm::row_lines(1024), "only 1920-point rows have a taller tile");
+    if (failures == 0) std::printf("ok\n");
+    return failures == 0 ? 0 : 1;
+}
