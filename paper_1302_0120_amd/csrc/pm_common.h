@@ -11,8 +11,10 @@ namespace pm {
 // contiguous [H][kC] block, so element (y, x) sits at
 //     ((x / kC) * H + y) * kC + (x % kC).
 // A column pass reads one strip as one contiguous block; a row pass that
-// owns kGR adjacent rows reads kGR*kC contiguous elements (128 bytes) per
-// strip.  The rescaled target uses the same layout.
+// owns G adjacent rows reads G*kC contiguous elements per strip (128 bytes
+// for 4 rows; with 2-row work-groups the two halves of each 128-byte line
+// are read by two work-groups placed on one XCD, row_pass_tile).  The
+// rescaled target uses the same layout.
 // Reduction groups of a work-group of NT threads: the largest power of two
 // that divides NT, at most one wave.  A group is a run of whole lanes, so
 // in-group shuffles never read an inactive lane (a work-group of 80 threads

@@ -98,6 +98,28 @@ __device__ __forceinline__ float block_max(float v, float* redf) {
     return v;
 }
 
+// Whether row tiles of G rows can take the cross-lane last stage of (W, P):
+// a lane group must hold whole rows of whole strips (lane_group times G
+// divides 16).
+__host__ __device__ constexpr bool row_lanes_ok(int W, int P, int G) {
+    return lane_swap_plan(W, P) && 16 % (lane_group(W, P) * G) == 0;
+}
+
+// Row tile (of G rows) that row-pass work-group `wg` of `nwg` works on.
+// Work-groups are dealt to the 8 XCDs of the GPU in turn (wg mod 8), so with
+// 2-row tiles the two halves 2g and 2g + 1 of a 4-row group are given to
+// work-groups wg and wg + 8 (same XCD): the lines one half loads are then in
+// that XCD's L2 for the other.  Work-groups past the last multiple of 16
+// keep their own index, so the map is a bijection of [0, nwg) for any nwg;
+// other tile heights use the identity.
+template <int G>
+__host__ __device__ __forceinline__ int row_pass_tile(int wg, int nwg) {
+    if constexpr (G == 2) {
+        if (wg < (nwg & ~15)) return 2 * ((wg / 16) * 8 + (wg & 7)) + ((wg / 8) & 1);
+    }
+    return wg;
+}
+
 template <int L, int PP = points_per_thread(L)>
 struct LineShape {
     static constexpr int P = PP;                    // points per thread (radix schedule)
@@ -257,9 +279,10 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
 // c), c fastest: row row0 + rho, thread index within the row j = jhi kC + c.
 // For a fixed t the element (row, j + T t) lies in strip jhi + (T / kC) t at
 // column c, so a wave's loads are runs of G kC contiguous elements; a.tw is
-// the staged twiddle table of (W, P).  SW (G = 4): with Q = lane_group(W, P),
-// lanes i + 64 k / Q (k < Q) of a wave hold threads j + k T / Q of one row
-// (jhi + k T / (4 Q)), so the plan runs its last FFT stage across lanes.
+// the staged twiddle table of (W, P).  SW (row_lanes_ok): with Q =
+// lane_group(W, P), lanes i + 64 k / Q (k < Q) of a wave hold threads
+// j + k T / Q of one row (jhi + k T / (4 Q)), 16 / (Q G) strips per lane
+// group, so the plan runs its last FFT stage across lanes.
 template <int W, int P, int G, int MODE, bool SW = false, int NBMAX = 2>
 __device__ __forceinline__ void row_body(const RowParams& a, int row0, const float* phase_in,
                                          float* phase_out, double* part_slot, float2* lds,
@@ -274,11 +297,13 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
     int c, rho, jhi;
     if constexpr (SW) {
         constexpr int Q = lane_group(W, P);
-        static_assert(Q != 0 && G == 4 && kC == 4 && T % 16 == 0, "4 rows, whole lane groups");
+        constexpr int JG = 16 / (Q * G);  // strips per lane group
+        static_assert(Q != 0 && kC == 4 && T % 16 == 0 && JG >= 1 && JG * Q * G == 16,
+                      "whole rows and strips per lane group");
         const int lane = tid & 63;
         c = lane & 3;
-        rho = (lane >> 2) & 3;
-        jhi = (tid >> 6) * (4 / Q) + ((lane >> 4) % (4 / Q)) + (lane / (64 / Q)) * (T / (4 * Q));
+        rho = (lane >> 2) % G;
+        jhi = (tid >> 6) * JG + ((lane / (4 * G)) % JG) + (lane / (64 / Q)) * (T / (4 * Q));
     } else {
         c = tid & (kC - 1);
         rho = (tid / kC) % G;
@@ -456,8 +481,8 @@ k_row(RowParams a) {
     float* pout = nullptr;
     if constexpr ((MODE & RIN_PHASE) != 0) pin = a.io->phase_in;
     if constexpr ((MODE & ROUT_PHASE) != 0) pout = a.io->phase_out;
-    row_body<W, LineShape<W>::P, G, MODE, lane_swap_plan(W, LineShape<W>::P) && G == 4>(
-        a, blockIdx.x * G, pin, pout, a.part + blockIdx.x * red_slots(NT), lds, red);
+    row_body<W, LineShape<W>::P, G, MODE, row_lanes_ok(W, LineShape<W>::P, G)>(
+        a, row_pass_tile<G>(blockIdx.x, gridDim.x) * G, pin, pout, a.part + blockIdx.x * red_slots(NT), lds, red);
 }
 
 // Intensity-loss kernels over a batch of same-size phases, sample = blockIdx.y.
@@ -480,8 +505,9 @@ k_row_adj(AdjParams p) {
         a.gscale = (float)(4.0 * p.grad_loss[b] / (double)n);
         out = p.grad + b * n;
     }
-    row_body<W, LineShape<W>::P, row_lines(W), MODE, lane_swap_plan(W, LineShape<W>::P) && row_lines(W) == 4>(
-        a, blockIdx.x * row_lines(W), p.phase + b * n, out, nullptr, lds, red);
+    row_body<W, LineShape<W>::P, row_lines(W), MODE, row_lanes_ok(W, LineShape<W>::P, row_lines(W))>(
+        a, row_pass_tile<row_lines(W)>(blockIdx.x, gridDim.x) * row_lines(W), p.phase + b * n, out, nullptr, lds,
+        red);
 }
 
 template <int H>

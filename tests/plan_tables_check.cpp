@@ -6,13 +6,15 @@
 //   * the staged twiddle table blocks tile [0, twiddle_entries) exactly, and
 //     every entry's exponent q k L / (NS R) lies in [0, L);
 //   * the batched table offsets add up schedule by schedule;
-// and the cross-lane and row-tile choices are checked on known plans.
+// the cross-lane and row-tile choices are checked on known plans, and the
+// row-pass work-group to tile map on a range of grid sizes.
 // Prints "ok" and exits 0, or prints the first violation and exits 1.
 #include <cstdio>
 #include <vector>
 
 #include "pm_common.h"
 #include "pm_fft.hpp"
+#include "pm_kernels.hpp"
 
 namespace {
 
@@ -79,6 +81,24 @@ int main() {
     check(pm::rows_for_plan(600, 1920, 256) == 4, "600 rows of 1920 fit one round with 4-row tiles");
     check(pm::rows_for_plan(1080, 1920, 304) == 4, "270 tiles fit 304 CUs");
     check(pm::rows_for_plan(1080, 1024, 256) == pm::row_lines(1024), "only 1920-point rows have a taller tile");
+    // 2-row tiles: the work-group -> tile map is a bijection, and the two
+    // halves of every whole group of 16 work-groups sit on one XCD (wg mod 8)
+    for (int nwg : {1, 8, 16, 30, 128, 150, 256, 300, 512, 540, 1024, 2048}) {
+        std::vector<int> seen(nwg, 0), where(nwg, -1);
+        for (int wg = 0; wg < nwg; ++wg) {
+            const int t = pm::row_pass_tile<2>(wg, nwg);
+            check(t >= 0 && t < nwg, "row tile in range", nwg, wg, t);
+            if (t < 0 || t >= nwg) continue;
+            ++seen[t];
+            where[t] = wg;
+        }
+        for (int t = 0; t < nwg; ++t) check(seen[t] == 1, "row tiles are a bijection", nwg, t);
+        for (int g = 0; 2 * g + 1 < (nwg & ~15); ++g)
+            check(where[2 * g] % 8 == where[2 * g + 1] % 8, "row tile halves share an XCD", nwg, g);
+        check(pm::row_pass_tile<4>(7, nwg) == 7, "4-row tiles keep their index", nwg);
+    }
+    check(pm::row_lines(1024) == 2 && pm::row_lines(4096) == 4 && pm::row_lines(1920) == 4,
+          "row tile heights");
     if (failures == 0) std::printf("ok\n");
     return failures == 0 ? 0 : 1;
 }

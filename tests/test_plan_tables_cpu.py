@@ -2,8 +2,9 @@
 (tests/plan_tables_check.cpp, built with hipcc for the host; no GPU): the
 stage radices of every plan multiply to its length, the staged twiddle
 table blocks tile the table with exponents below the length, the batched
-table offsets add up, and the cross-lane and row-tile choices hold on known
-plans."""
+table offsets add up, the cross-lane and row-tile choices hold on known
+plans, and the XCD pairing of 2-row tiles is a bijection that pairs halves
+on one XCD."""
 import os
 import shutil
 import subprocess
