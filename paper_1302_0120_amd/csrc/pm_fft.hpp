@@ -840,12 +840,13 @@ __host__ __device__ constexpr int points_per_thread(int L) {
 }
 
 // Rows per work-group of the one-mask row pass for rows of W points.  Rows
-// of 256 .. 2048 points take 2-row work-groups, twice as many as 4-row ones,
-// paired on XCDs (row_pass_tile) so that the two work-groups reading the two
-// halves of the same 128-byte lines share one L2: measured per iteration,
-// 256^2 -1%, 512^2 -4%, 1024^2 -1.4%, 2048^2 -4.6% against 4-row work-groups
-// (without the pairing, 2-row work-groups were 9-17% slower: each XCD then
-// fetched whole lines for half their bytes).
+// of 128 .. 4096 points (powers of two) take 2-row work-groups, twice as
+// many as 4-row ones, paired on XCDs (row_pass_tile) so that the two
+// work-groups reading the two halves of the same 128-byte lines share one
+// L2: measured per iteration, 256^2 -1%, 512^2 -4%, 1024^2 -1.4%, 2048^2
+// -4.6%, 4096^2 -2.8%, 128^2 even, against 4-row work-groups (without the
+// pairing, 2-row work-groups were 9-17% slower: each XCD then fetched whole
+// lines for half their bytes).  The mixed-radix lengths keep 4 rows.
 #ifndef PM_ROWS_800
 #define PM_ROWS_800 4
 #endif
@@ -853,7 +854,10 @@ __host__ __device__ constexpr int points_per_thread(int L) {
 #define PM_ROWS_1920 4
 #endif
 __host__ __device__ constexpr int row_lines(int W) {
-    return W == 800 ? PM_ROWS_800 : (W == 1920 ? PM_ROWS_1920 : ((W >= 256 && W <= 2048) ? 2 : kGR));
+    return W == 800 ? PM_ROWS_800
+         : W == 1920 ? PM_ROWS_1920
+         : ((W & (W - 1)) == 0 && W >= 128 && W <= 4096) ? 2
+                                                           : kGR;
 }
 
 // A second, taller row tile for 1920-point rows (0: none).  A 1920-point

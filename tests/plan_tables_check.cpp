@@ -97,7 +97,8 @@ int main() {
             check(where[2 * g] % 8 == where[2 * g + 1] % 8, "row tile halves share an XCD", nwg, g);
         check(pm::row_pass_tile<4>(7, nwg) == 7, "4-row tiles keep their index", nwg);
     }
-    check(pm::row_lines(1024) == 2 && pm::row_lines(4096) == 4 && pm::row_lines(1920) == 4,
+    check(pm::row_lines(1024) == 2 && pm::row_lines(4096) == 2 && pm::row_lines(64) == 4 &&
+              pm::row_lines(1920) == 4 && pm::row_lines(600) == 4 && pm::row_lines(1080) == 4,
           "row tile heights");
     if (failures == 0) std::printf("ok\n");
     return failures == 0 ? 0 : 1;
