@@ -761,10 +761,10 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
         return bail(e, "hipDeviceGetAttribute");
     h->rows = pm::rows_for_plan(height, width, h->num_cu);
     h->nwg_row = height / h->rows;
-    h->nwg_col = width / pm::kC;
+    h->nwg_col = width / pm::col_lines(height);
     // Threads per work-group: lines x (length / points per thread).
     h->slots_row = h->nwg_row * pm::red_slots(h->rows * (width / pm::points_per_thread(width)));
-    h->slots_col = h->nwg_col * pm::red_slots(pm::kC * (height / pm::points_per_thread(height)));
+    h->slots_col = h->nwg_col * pm::red_slots(pm::col_lines(height) * (height / pm::points_per_thread(height)));
     h->stride = h->slots_row > h->slots_col ? h->slots_row : h->slots_col;
     if (h->stride < kNormGrid) h->stride = kNormGrid;
     const size_t n = (size_t)h->N;

@@ -13,7 +13,7 @@ namespace pm {
 // A column pass reads one strip as one contiguous block; a row pass that
 // owns G adjacent rows reads G*kC contiguous elements per strip (128 bytes
 // for 4 rows; with 2-row work-groups the two halves of each 128-byte line
-// are read by two work-groups placed on one XCD, row_pass_tile).  The
+// are read by two work-groups placed on one XCD, pass_tile).  The
 // rescaled target uses the same layout.
 // Reduction groups of a work-group of NT threads: the largest power of two
 // that divides NT, at most one wave.  A group is a run of whole lanes, so

@@ -841,7 +841,7 @@ __host__ __device__ constexpr int points_per_thread(int L) {
 
 // Rows per work-group of the one-mask row pass for rows of W points.  Rows
 // of 128 .. 4096 points (powers of two) take 2-row work-groups, twice as
-// many as 4-row ones, paired on XCDs (row_pass_tile) so that the two
+// many as 4-row ones, paired on XCDs (pass_tile) so that the two
 // work-groups reading the two halves of the same 128-byte lines share one
 // L2: measured per iteration, 256^2 -1%, 512^2 -4%, 1024^2 -1.4%, 2048^2
 // -4.6%, 4096^2 -2.8%, 128^2 even, against 4-row work-groups (without the
@@ -858,6 +858,17 @@ __host__ __device__ constexpr int row_lines(int W) {
          : W == 1920 ? PM_ROWS_1920
          : ((W & (W - 1)) == 0 && W >= 128 && W <= 4096) ? 2
                                                            : kGR;
+}
+
+// Columns per work-group of the one-mask column pass for columns of H
+// points: a whole strip (kC columns), or half a strip with the two halves
+// paired on one XCD (pass_tile) as for the rows.  A half strip reads 16
+// bytes of each 32-byte strip row, against 64 of each 128-byte line for a
+// half row tile; measured per iteration against whole strips: 4096^2 -3%
+// (two work-groups per CU instead of one), 128^2 -1.7%, 256^2 -1%, but 512^2
+// +4.5%, 1024^2 +6%, 2048^2 +4%, so only 128, 256 and 4096 take half strips.
+__host__ __device__ constexpr int col_lines(int H) {
+    return (H == 128 || H == 256 || H == 4096) ? 2 : kC;
 }
 
 // A second, taller row tile for 1920-point rows (0: none).  A 1920-point

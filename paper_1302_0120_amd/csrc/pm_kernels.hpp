@@ -105,15 +105,21 @@ __host__ __device__ constexpr bool row_lanes_ok(int W, int P, int G) {
     return lane_swap_plan(W, P) && 16 % (lane_group(W, P) * G) == 0;
 }
 
-// Row tile (of G rows) that row-pass work-group `wg` of `nwg` works on.
-// Work-groups are dealt to the 8 XCDs of the GPU in turn (wg mod 8), so with
-// 2-row tiles the two halves 2g and 2g + 1 of a 4-row group are given to
-// work-groups wg and wg + 8 (same XCD): the lines one half loads are then in
-// that XCD's L2 for the other.  Work-groups past the last multiple of 16
-// keep their own index, so the map is a bijection of [0, nwg) for any nwg;
-// other tile heights use the identity.
+// The same for column tiles of G columns: whole strips, or half a strip with
+// a lane group of 32 / Q rows per column (T a multiple of 32).
+__host__ __device__ constexpr bool col_lanes_ok(int H, int P, int G) {
+    return lane_swap_plan(H, P) && (G % kC == 0 || (G == 2 && (H / P) % 32 == 0));
+}
+
+// Tile (of G rows, or of G columns) that pass work-group `wg` of `nwg` works
+// on.  Work-groups are dealt to the 8 XCDs of the GPU in turn (wg mod 8), so
+// with 2-line tiles the two halves 2g and 2g + 1 of a 4-row group (a strip)
+// are given to work-groups wg and wg + 8 (same XCD): the lines one half
+// loads are then in that XCD's L2 for the other.  Work-groups past the last
+// multiple of 16 keep their own index, so the map is a bijection of
+// [0, nwg) for any nwg; other tile sizes use the identity.
 template <int G>
-__host__ __device__ __forceinline__ int row_pass_tile(int wg, int nwg) {
+__host__ __device__ __forceinline__ int pass_tile(int wg, int nwg) {
     if constexpr (G == 2) {
         if (wg < (nwg & ~15)) return 2 * ((wg / 16) * 8 + (wg & 7)) + ((wg / 8) & 1);
     }
@@ -127,10 +133,12 @@ struct LineShape {
     static constexpr int LP = lds_line_len(L);      // padded LDS line
 };
 
-// Column pass over G columns = G / kC adjacent strips, starting at strip
-// `strip0` (G a multiple of kC).  Thread tid = (sl, j, c), c fastest: strip
-// strip0 + sl, column c of that strip, rows j + T t.  For a fixed t a wave's
-// loads are 64 / kC consecutive rows of one strip: one contiguous run.
+// Column pass over G columns: G / kC adjacent strips starting at strip
+// `first` (G a multiple of kC), or (G = 2) half `first` mod 2 of strip
+// `first` / 2.  Thread tid = (sl, j, c), c fastest: strip strip0 + sl,
+// column c of that strip, rows j + T t.  For a fixed t a wave's loads are
+// 64 / kC consecutive rows of one strip (one contiguous run), or with half
+// strips 32 rows of its two columns.
 // `lds` holds LdsPlan<H, G, NBMAX>::FLOATS2 elements, `red` red_slots(G T) doubles;
 // the FP64 partials go to part_slot[0 .. red_slots(G T)); a.tw is the staged
 // twiddle table of (H, P).  SW (one strip, G = kC): with Q = lane_group(H, P),
@@ -138,22 +146,36 @@ struct LineShape {
 // 16 / Q rows per lane group and column, so the plan runs its last FFT stage
 // across lanes.
 template <int H, int P, int G, int MODE, bool SW = false, int NBMAX = 2>
-__device__ __forceinline__ void col_body(const ColParams& a, int strip0, double* part_slot,
+__device__ __forceinline__ void col_body(const ColParams& a, int first, double* part_slot,
                                          float2* lds, double* red) {
     constexpr int T = LineShape<H, P>::T;
     constexpr int NT = G * T;
     constexpr int LP = LineShape<H, P>::LP;
     using LD = LdsPlan<H, G, NBMAX>;
-    static_assert(G % kC == 0, "whole strips per work-group");
+    static_assert(G % kC == 0 || G == 2, "whole strips, or half a strip, per work-group");
 
     const int tid = threadIdx.x;
+    constexpr bool HALF = G < kC;
+    const int strip0 = HALF ? first >> 1 : first;
+    const int c0 = HALF ? (first & 1) * 2 : 0;  // first column of the tile in its strip
     int c, j, sl;
     if constexpr (SW) {
         constexpr int Q = lane_group(H, P);
-        static_assert(Q != 0 && G == kC && kC == 4 && T % 16 == 0, "one strip, whole lane groups");
         const int lane = tid & 63;
-        c = lane & 3;
-        j = (tid >> 6) * (16 / Q) + ((lane >> 2) % (16 / Q)) + (lane / (64 / Q)) * (T / Q);
+        if constexpr (HALF) {
+            static_assert(Q != 0 && T % 32 == 0, "half strips: whole lane groups");
+            c = c0 + (lane & 1);
+            j = (tid >> 6) * (32 / Q) + ((lane >> 1) % (32 / Q)) + (lane / (64 / Q)) * (T / Q);
+            sl = 0;
+        } else {
+            static_assert(Q != 0 && G == kC && kC == 4 && T % 16 == 0, "one strip, whole lane groups");
+            c = lane & 3;
+            j = (tid >> 6) * (16 / Q) + ((lane >> 2) % (16 / Q)) + (lane / (64 / Q)) * (T / Q);
+            sl = 0;
+        }
+    } else if constexpr (HALF) {
+        c = c0 + (tid & 1);
+        j = (tid >> 1) % T;
         sl = 0;
     } else {
         c = tid & (kC - 1);
@@ -198,7 +220,7 @@ __device__ __forceinline__ void col_body(const ColParams& a, int strip0, double*
 #pragma unroll
         for (int t = 0; t < P; ++t) v[t] = *tiled(a.X, t);
     }
-    float2* line = lds + (sl * kC + c) * LP;
+    float2* line = lds + (sl * kC + c - c0) * LP;
 
     constexpr int PAR1 = (MODE & C_FWD) != 0 ? fft_parity_after<H, P, 0, SW>() : 0;
     if constexpr ((MODE & C_FWD) != 0) fft_line<H, P, false, LD::NBUF, 0, SW>(v, j, line, LD::STRIDE, tw);
@@ -461,14 +483,14 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
 
 // One-mask kernels: kC columns (one strip) or G rows per work-group
 // (row_lines(W), or row_lines_alt(W) where the plan takes it).
-template <int H, int MODE>
-__global__ void __launch_bounds__(kC * LineShape<H>::T)
+template <int H, int MODE, int G = col_lines(H)>
+__global__ void __launch_bounds__(G * LineShape<H>::T)
 k_col(ColParams a) {
-    constexpr int NT = kC * LineShape<H>::T;
-    __shared__ float2 lds[LdsPlan<H, kC>::FLOATS2];
+    constexpr int NT = G * LineShape<H>::T;
+    __shared__ float2 lds[LdsPlan<H, G>::FLOATS2];
     __shared__ double red[red_slots(NT)];
-    col_body<H, LineShape<H>::P, kC, MODE, lane_swap_plan(H, LineShape<H>::P)>(
-        a, blockIdx.x, a.part + blockIdx.x * red_slots(NT), lds, red);
+    col_body<H, LineShape<H>::P, G, MODE, col_lanes_ok(H, LineShape<H>::P, G)>(
+        a, pass_tile<G>(blockIdx.x, gridDim.x), a.part + blockIdx.x * red_slots(NT), lds, red);
 }
 
 template <int W, int MODE, int G = row_lines(W)>
@@ -482,7 +504,7 @@ k_row(RowParams a) {
     if constexpr ((MODE & RIN_PHASE) != 0) pin = a.io->phase_in;
     if constexpr ((MODE & ROUT_PHASE) != 0) pout = a.io->phase_out;
     row_body<W, LineShape<W>::P, G, MODE, row_lanes_ok(W, LineShape<W>::P, G)>(
-        a, row_pass_tile<G>(blockIdx.x, gridDim.x) * G, pin, pout, a.part + blockIdx.x * red_slots(NT), lds, red);
+        a, pass_tile<G>(blockIdx.x, gridDim.x) * G, pin, pout, a.part + blockIdx.x * red_slots(NT), lds, red);
 }
 
 // Intensity-loss kernels over a batch of same-size phases, sample = blockIdx.y.
@@ -506,7 +528,7 @@ k_row_adj(AdjParams p) {
         out = p.grad + b * n;
     }
     row_body<W, LineShape<W>::P, row_lines(W), MODE, row_lanes_ok(W, LineShape<W>::P, row_lines(W))>(
-        a, row_pass_tile<row_lines(W)>(blockIdx.x, gridDim.x) * row_lines(W), p.phase + b * n, out, nullptr, lds,
+        a, pass_tile<row_lines(W)>(blockIdx.x, gridDim.x) * row_lines(W), p.phase + b * n, out, nullptr, lds,
         red);
 }
 
@@ -524,7 +546,7 @@ k_col_adj(AdjParams p) {
     a.W = p.W;
     a.invN = 1.0 / (double)n;
     a.inten = p.inten + b * n;
-    col_body<H, LineShape<H>::P, kC, COL_LOSS, lane_swap_plan(H, LineShape<H>::P)>(
+    col_body<H, LineShape<H>::P, kC, COL_LOSS, col_lanes_ok(H, LineShape<H>::P, kC)>(
         a, blockIdx.x, p.part + b * p.nwg + blockIdx.x * red_slots(NT), lds, red);
 }
 

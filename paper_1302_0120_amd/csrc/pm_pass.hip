@@ -85,9 +85,11 @@ hipError_t PM_CAT(launch_row_, PM_L)(int mode, const RowParams& p, int grid, hip
     return hipErrorInvalidValue;
 }
 
+// The column tile is p.W / grid columns, which must be col_lines(PM_L).
 hipError_t PM_CAT(launch_col_, PM_L)(int mode, const ColParams& p, int grid, hipStream_t s,
                                      hipEvent_t ev0, hipEvent_t ev1) {
-    const int block = kC * LineShape<PM_L>::T;
+    if (grid <= 0 || p.W != grid * col_lines(PM_L)) return hipErrorInvalidValue;
+    const int block = col_lines(PM_L) * LineShape<PM_L>::T;
     switch (mode) {
         case COL_ITER: return launch(k_col<PM_L, COL_ITER>, grid, block, s, ev0, ev1, p);
         case COL_ERR: return launch(k_col<PM_L, COL_ERR>, grid, block, s, ev0, ev1, p);

@@ -86,7 +86,7 @@ int main() {
     for (int nwg : {1, 8, 16, 30, 128, 150, 256, 300, 512, 540, 1024, 2048}) {
         std::vector<int> seen(nwg, 0), where(nwg, -1);
         for (int wg = 0; wg < nwg; ++wg) {
-            const int t = pm::row_pass_tile<2>(wg, nwg);
+            const int t = pm::pass_tile<2>(wg, nwg);
             check(t >= 0 && t < nwg, "row tile in range", nwg, wg, t);
             if (t < 0 || t >= nwg) continue;
             ++seen[t];
@@ -95,8 +95,14 @@ int main() {
         for (int t = 0; t < nwg; ++t) check(seen[t] == 1, "row tiles are a bijection", nwg, t);
         for (int g = 0; 2 * g + 1 < (nwg & ~15); ++g)
             check(where[2 * g] % 8 == where[2 * g + 1] % 8, "row tile halves share an XCD", nwg, g);
-        check(pm::row_pass_tile<4>(7, nwg) == 7, "4-row tiles keep their index", nwg);
+        check(pm::pass_tile<4>(7, nwg) == 7, "4-row tiles keep their index", nwg);
     }
+    check(pm::col_lines(1024) == pm::kC && pm::col_lines(4096) == 2 && pm::col_lines(600) == pm::kC,
+          "column tile widths");
+    for (int H : {128, 256, 4096})
+        check(pm::col_lines(H) != 2 || pm::col_lanes_ok(H, pm::points_per_thread(H), 2) ==
+                                           pm::lane_swap_plan(H, pm::points_per_thread(H)),
+              "half-strip column tiles keep the cross-lane stage", H);
     check(pm::row_lines(1024) == 2 && pm::row_lines(4096) == 2 && pm::row_lines(64) == 4 &&
               pm::row_lines(1920) == 4 && pm::row_lines(600) == 4 && pm::row_lines(1080) == 4,
           "row tile heights");
