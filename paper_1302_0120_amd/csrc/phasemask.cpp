@@ -131,6 +131,7 @@ struct pm_plan {
     int rows = 0;                      // rows per row-pass work-group (rows_for_plan)
     int nwg_row = 0, nwg_col = 0, stride = 0;
     int slots_row = 0, slots_col = 0;  // FP64 partials per row / column pass (one per reduction group)
+    int slots_adj = 0;                 // per sample of the loss column pass (whole-strip work-groups)
     int num_cu = 0;                    // compute units of the device
     float2* X = nullptr;
     float* mhat = nullptr;
@@ -765,7 +766,9 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
     // Threads per work-group: lines x (length / points per thread).
     h->slots_row = h->nwg_row * pm::red_slots(h->rows * (width / pm::points_per_thread(width)));
     h->slots_col = h->nwg_col * pm::red_slots(pm::col_lines(height) * (height / pm::points_per_thread(height)));
+    h->slots_adj = (width / pm::kC) * pm::red_slots(pm::kC * (height / pm::points_per_thread(height)));
     h->stride = h->slots_row > h->slots_col ? h->slots_row : h->slots_col;
+    if (h->stride < h->slots_adj) h->stride = h->slots_adj;
     if (h->stride < kNormGrid) h->stride = kNormGrid;
     const size_t n = (size_t)h->N;
     if ((e = hipMalloc(&h->X, n * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(iterate)");
@@ -1123,11 +1126,11 @@ pm_status phasemask_intensity_loss_fwd(pm_handle h, int batch, const float* phas
     p.twH = h->twH;
     p.H = h->H;
     p.W = h->W;
-    p.nwg = h->slots_col;
+    p.nwg = h->slots_adj;
     hipStream_t s = h->stream;
     PM_TRY(kAdjRow[len_slot(h->W)](pm::ROW_INIT, p, batch, s), "loss row pass");
     PM_TRY(kAdjCol[len_slot(h->H)](p, batch, s), "loss column pass");
-    PM_TRY(pm::launch_sum_rows(h->part, h->slots_col, loss, batch, s), "loss sum");
+    PM_TRY(pm::launch_sum_rows(h->part, h->slots_adj, loss, batch, s), "loss sum");
     return PM_OK;
 }
 
@@ -1148,7 +1151,7 @@ pm_status phasemask_intensity_loss_bwd(pm_handle h, int batch, const float* phas
     p.twH = h->twH;
     p.H = h->H;
     p.W = h->W;
-    p.nwg = h->slots_col;
+    p.nwg = h->slots_adj;
     PM_TRY(kAdjRow[len_slot(h->W)](pm::ROW_GRAD, p, batch, h->stream), "gradient row pass");
     return PM_OK;
 }
