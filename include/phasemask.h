@@ -84,9 +84,10 @@ typedef enum {
  * Create a plan for masks of height x width pixels (Sec. II: n_y = height,
  * n_x = width).  Allocates the plan's device workspace (the iterate, the
  * rescaled target, twiddle tables and reduction partials: about 12 bytes per
- * pixel plus 16 bytes per pixel-iteration-row of partials) on the current
- * device.  `stream` is a hipStream_t (NULL = the null stream) used by every
- * later call until phasemask_set_stream changes it.
+ * pixel, plus FP64 partial sums of N / 128 to N / 16 bytes (N = height x
+ * width) per error-history entry, grown on demand) on the current device.
+ * `stream` is a hipStream_t (NULL = the null stream) used by every later
+ * call until phasemask_set_stream changes it.
  * With the environment variable PHASEMASK_LOG set, the plan's transform
  * schemes and work-group counts are printed to stderr.
  * Errors: PM_EINVAL if out is NULL; PM_EUNSUPPORTED for sizes outside the
