@@ -25,22 +25,25 @@ def pmb():
     return binding
 
 
-def _targets(batch, n, seed):
+def _targets(batch, n, seed, w=None):
+    w = n if w is None else w
     ts, ps = [], []
     for b in range(batch):
         rng = np.random.default_rng(seed + b)
-        m = synth.spot_amplitude(n, n, 20, 2.0, 0.5, 1.0, rng).astype(np.float64)
+        m = synth.spot_amplitude(n, w, 20, 2.0, 0.5, 1.0, rng).astype(np.float64)
         it = m * m
-        ts.append((it * (n * n / it.sum())).astype(np.float32))
-        ps.append(synth.uniform_phase(n, n, rng))
+        ts.append((it * (n * w / it.sum())).astype(np.float32))
+        ps.append(synth.uniform_phase(n, w, rng))
     return np.stack(ts), np.stack(ps)
 
 
-@pytest.mark.parametrize("n,batch", [(64, 1), (128, 3), (512, 2)])
-def test_loss_and_gradient_vs_oracle(pmb, n, batch):
-    print(f"adjoint {n}x{n} batch {batch}", flush=True)
-    it, ph = _targets(batch, n, 50 + n)
-    plan = pmb.PhaseMask(n, n)
+# (256, 128): 256-point columns, whose GS column pass takes half-strip
+# work-groups while the loss column pass takes whole strips.
+@pytest.mark.parametrize("n,w,batch", [(64, 64, 1), (128, 128, 3), (256, 128, 2), (512, 512, 2)])
+def test_loss_and_gradient_vs_oracle(pmb, n, w, batch):
+    print(f"adjoint {n}x{w} batch {batch}", flush=True)
+    it, ph = _targets(batch, n, 50 + n, w)
+    plan = pmb.PhaseMask(n, w)
     ph_d = torch.from_numpy(ph).cuda()
     it_d = torch.from_numpy(it).cuda()
     loss, saved = plan.intensity_loss_fwd(ph_d, it_d)
