@@ -302,29 +302,40 @@ __device__ __forceinline__ void dft(float2 (&x)[R]) {
     }
 }
 
-// LDS index of element i of a line.  PM_LDS_PAD selects a padding scheme (a
-// tuning knob; every scheme is a bijection onto a line of lds_line_len
-// elements, so results do not depend on it):
+// LDS index of element i of a line of L points.  The padding scheme is a
+// tuning knob per length (every scheme is a bijection onto a line of
+// lds_line_len elements, so results do not depend on it):
 //   0: one spare element after every 16;  1: after every 32;  2: none;
 //   3: after every 16 and another after every 256.
+// PM_LDS_PAD applies up to 1024 points, PM_LDS_PAD_LONG to 2048 and 4096.
 // Lines of one work-group are PM_LDS_LINE_EXTRA elements further apart, so
 // the lines that share a wave fall on different banks.  Measured on MI355X
 // (1024^2 and 800 x 600 solves, 11 layouts): no padding with lines 4
 // elements apart (any extra of 4 mod 8) is fastest, 5.5% faster than one
 // spare per 16 with lines 8 apart at 1024^2 and 8% faster at 800 x 600.
+// For 2048 and 4096 points (16 points per thread, so the first exchange
+// writes each wave's outputs 16 elements apart), one spare per 32 is
+// fastest: 2048^2 -3.8%, 4096^2 -9.6% per solve against no padding (one
+// spare per 16: -3.3% and -7.8%); at 1024^2 it costs 1-3%.
 #ifndef PM_LDS_PAD
 #define PM_LDS_PAD 2
+#endif
+#ifndef PM_LDS_PAD_LONG
+#define PM_LDS_PAD_LONG 1
 #endif
 #ifndef PM_LDS_LINE_EXTRA
 #define PM_LDS_LINE_EXTRA 4
 #endif
-__host__ __device__ constexpr int lds_pad(int i) {
-    return PM_LDS_PAD == 0 ? i + (i >> 4)
-         : PM_LDS_PAD == 1 ? i + (i >> 5)
-         : PM_LDS_PAD == 2 ? i
-                           : i + (i >> 4) + (i >> 8);
+__host__ __device__ constexpr int lds_pad_scheme(int L) {
+    return (L == 2048 || L == 4096) ? PM_LDS_PAD_LONG : PM_LDS_PAD;
 }
-__host__ __device__ constexpr int lds_line_len(int L) { return lds_pad(L) + PM_LDS_LINE_EXTRA; }
+__host__ __device__ constexpr int lds_pad(int L, int i) {
+    return lds_pad_scheme(L) == 0 ? i + (i >> 4)
+         : lds_pad_scheme(L) == 1 ? i + (i >> 5)
+         : lds_pad_scheme(L) == 2 ? i
+                                  : i + (i >> 4) + (i >> 8);
+}
+__host__ __device__ constexpr int lds_line_len(int L) { return lds_pad(L, L) + PM_LDS_LINE_EXTRA; }
 
 // LDS-resident transforms.  For lengths whose register plan would need too
 // many points per thread (1920 needs P = 60 and spills), every stage reads
@@ -712,7 +723,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, i
         } else {
             const int base = (b - k) * R + k;
 #pragma unroll
-            for (int q = 0; q < R; ++q) buf[lds_pad(base + q * NS)] = x[q];
+            for (int q = 0; q < R; ++q) buf[lds_pad(L, base + q * NS)] = x[q];
         }
     }
     if constexpr (LANES_NEXT) {
@@ -725,7 +736,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, i
     } else if constexpr (!LAST) {
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < P; ++t) v[t] = buf[lds_pad(j + T * t)];
+        for (int t = 0; t < P; ++t) v[t] = buf[lds_pad(L, j + T * t)];
         // With one buffer the next stage's writes must wait for every read;
         // with two they go to the other buffer, whose last reads finished
         // before the barrier above.
