@@ -6,8 +6,9 @@
 //   * the staged twiddle table blocks tile [0, twiddle_entries) exactly, and
 //     every entry's exponent q k L / (NS R) lies in [0, L);
 //   * the batched table offsets add up schedule by schedule;
-// the cross-lane and row-tile choices are checked on known plans, and the
-// row-pass work-group to tile map on a range of grid sizes.
+// the cross-lane and row-tile choices are checked on known plans, the
+// row-pass work-group to tile map on a range of grid sizes, the padded LDS
+// index of every length, and the one-mask kernels' static LDS.
 // Prints "ok" and exits 0, or prints the first violation and exits 1.
 #include <cstdio>
 #include <vector>
@@ -46,6 +47,33 @@ void walk(int L, int P) {
     check(prod == L, "radices multiply to L", L, P, (int)prod);
     check(pm::twiddle_entries(L, P) == next_block, "twiddle_entries is the last block end", L, P, next_block);
     check(pm::twiddle_entries(L, P) < L, "staged table shorter than L", L, P);
+}
+
+// LDS layout of a line: the padded index maps [0, L) one to one into the
+// line's lds_line_len slots.
+void lds_line(int L) {
+    const int LP = pm::lds_line_len(L);
+    std::vector<int> hit(LP, 0);
+    for (int i = 0; i < L; ++i) {
+        const int a = pm::lds_pad(L, i);
+        check(a >= 0 && a < LP, "padded LDS index inside the line", L, i, a);
+        if (a >= 0 && a < LP) check(++hit[a] == 1, "padded LDS index one to one", L, i, a);
+    }
+}
+
+// Static LDS of the one-mask pass kernels (exchange buffers and FP64
+// reduction slots) within the 160 KiB of a CU.
+template <int L>
+void lds_budget() {
+    constexpr int T = pm::LineShape<L>::T;
+    constexpr int budget = 160 * 1024;
+    constexpr int gc = pm::col_lines(L), gr = pm::row_lines(L);
+    check(pm::LdsPlan<L, gc>::FLOATS2 * 8 + pm::red_slots(gc * T) * 8 <= budget, "column pass LDS", L, gc);
+    check(pm::LdsPlan<L, gr>::FLOATS2 * 8 + pm::red_slots(gr * T) * 8 <= budget, "row pass LDS", L, gr);
+    if constexpr (pm::row_lines_alt(L) != 0) {
+        constexpr int ga = pm::row_lines_alt(L);
+        check(pm::LdsPlan<L, ga>::FLOATS2 * 8 + pm::red_slots(ga * T) * 8 <= budget, "taller row tile LDS", L, ga);
+    }
 }
 
 }  // namespace
@@ -106,6 +134,10 @@ int main() {
     check(pm::row_lines(1024) == 2 && pm::row_lines(4096) == 2 && pm::row_lines(64) == 4 &&
               pm::row_lines(1920) == 4 && pm::row_lines(600) == 4 && pm::row_lines(1080) == 4,
           "row tile heights");
+    for (int L : lengths) lds_line(L);
+    lds_budget<16>(); lds_budget<32>(); lds_budget<64>(); lds_budget<128>(); lds_budget<256>();
+    lds_budget<512>(); lds_budget<1024>(); lds_budget<2048>(); lds_budget<4096>();
+    lds_budget<600>(); lds_budget<800>(); lds_budget<1080>(); lds_budget<1920>();
     if (failures == 0) std::printf("ok\n");
     return failures == 0 ? 0 : 1;
 }

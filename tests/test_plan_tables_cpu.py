@@ -3,8 +3,9 @@
 stage radices of every plan multiply to its length, the staged twiddle
 table blocks tile the table with exponents below the length, the batched
 table offsets add up, the cross-lane and row-tile choices hold on known
-plans, and the XCD pairing of 2-row tiles is a bijection that pairs halves
-on one XCD."""
+plans, the XCD pairing of 2-row tiles is a bijection that pairs halves
+on one XCD, the padded LDS index of every length is one to one inside its
+line, and the one-mask pass kernels' static LDS fits a CU."""
 import os
 import shutil
 import subprocess
