@@ -163,13 +163,15 @@ def bench_paper_slm(torch, binding, synth, steps=20):
 
 
 def bench_other_configs(torch, binding, synth, steps=20):
-    """The two other one-mask spot workloads: 64 x 64 (5 spots, 100
-    iterations) and 512 x 512 (20 spots, 50 iterations), each one
-    graph-replayed solve with the FP64 history, inputs resident; ms per mask
-    and the final Fourier error."""
+    """The other one-mask spot workloads: 64 x 64 (5 spots, 100 iterations),
+    512 x 512 (20 spots, 50 iterations) and the larger 2048 x 2048 (100
+    spots, 50 iterations) and 4096 x 4096 (100 spots, 20 iterations), each
+    one graph-replayed solve with the FP64 history, inputs resident; ms per
+    mask and the final Fourier error."""
     dev = torch.device("cuda", 0)
     res = {}
-    for name, spec in (("spots64x100", synth.SPOTS_64), ("spots512x50", synth.SPOTS_512)):
+    for name, spec in (("spots64x100", synth.SPOTS_64), ("spots512x50", synth.SPOTS_512),
+                       ("spots2048x50", synth.SPOTS_2048), ("spots4096x20", synth.SPOTS_4096)):
         m, phi0 = synth.spot_problem(spec)
         md = torch.from_numpy(m).to(dev)
         pd = torch.from_numpy(phi0).to(dev)

@@ -37,6 +37,8 @@ __all__ = [
     "SPOTS_512",
     "SPOTS_1024",
     "SPOTS_800x600",
+    "SPOTS_2048",
+    "SPOTS_4096",
     "spot_problem",
     "batched_problems",
     "intensity_problems",
@@ -108,6 +110,10 @@ SPOTS_1024 = SpotSpec(1024, 1024, 100, 2.0, 0.5, 1.0, 100, 3)
 # The SLM panel of the paper's timing (800 x 600 pixels: 600 rows of 800),
 # 25 iterations; 20 spots of sigma 2 px with amplitudes in [0.5, 1].
 SPOTS_800x600 = SpotSpec(600, 800, 20, 2.0, 0.5, 1.0, 25, 6)
+# Larger masks: 2048 x 2048 (50 iterations) and 4096 x 4096 (20 iterations),
+# 100 spots of sigma 2 px with amplitudes in [0.5, 1].
+SPOTS_2048 = SpotSpec(2048, 2048, 100, 2.0, 0.5, 1.0, 50, 7)
+SPOTS_4096 = SpotSpec(4096, 4096, 100, 2.0, 0.5, 1.0, 20, 8)
 
 
 def spot_problem(spec: SpotSpec, seed: int | None = None):
