@@ -86,7 +86,7 @@ def _one_iteration_case(pmb, h, w, m, phi0):
 
 
 @pytest.mark.parametrize("shape", [(16, 16), (64, 64), (32, 128), (256, 64), (512, 512),
-                                   (1024, 1024), (2048, 256), (256, 4096)])
+                                   (1024, 1024), (2048, 256), (256, 2048), (256, 4096), (2048, 2048)])
 def test_one_iteration_parity(pmb, shape):
     h, w = shape
     print(f"one iteration {shape}", flush=True)
