@@ -310,6 +310,46 @@ def test_physical_error_closed_form():
     assert gs.physical_error(m2, u, t_l, t_d) == (0.0, 0.0)
 
 
+def test_physical_error_intensity_reading():
+    """Eq. 8 compares intensities (squared moduli), each normalised to its
+    peak; the lit set is where the target intensity exceeds t_d.  A
+    non-degenerate closed form tells intensities from amplitudes apart:
+
+    * target amplitudes 1 at k1, 1/2 at k2, 1/100 at k4, 0 elsewhere, so the
+      normalised target intensities are 1, 1/4 and 1e-4 (k4 is dark, since
+      1e-4 < t_d, although its amplitude ratio 1e-2 exceeds t_d);
+    * mask u = a e1 + b e2 + c e3 of plane waves at k1, k2, k3 (k3 dark),
+      whose unitary transform is sqrt(N) (a, b, c) at (k1, k2, k3), so the
+      normalised reconstructed intensities are 1, (b/a)^2, (c/a)^2, 0.
+
+    Lit k1 matches exactly; lit k2 deviates by rel = |1/4 - (b/a)^2| / (1/4)
+    and costs t_d rel / t_l - t_d; dark k3 costs (c/a)^2 - t_d; dark k4 has
+    no reconstructed light.  An amplitude reading (|F u| and m) gives other
+    numbers for every one of these terms."""
+    tol = _golden_tolerances()
+    t_l, t_d = tol["t_lit"], tol["t_dark"]
+    h, w = 8, 16
+    k1, k2, k3, k4 = (1, 2), (3, 7), (6, 11), (4, 0)
+    a, b, c = 2.0, 1.6, 0.2          # b/a = 0.8, c/a = 0.1
+    ys = np.arange(h)[:, None]
+    xs = np.arange(w)[None, :]
+
+    def wave(k):
+        return np.exp(2j * math.pi * (k[0] * ys / h + k[1] * xs / w))
+
+    u = a * wave(k1) + b * wave(k2) + c * wave(k3)
+    m = np.zeros((h, w))
+    m[k1], m[k2], m[k4] = 1.0, 0.5, 0.01
+    e_lit, e_dark = gs.physical_error(m, u, t_l, t_d)
+    rel = abs(0.25 - 0.64) / 0.25
+    assert abs(e_lit - (t_d * rel / t_l - t_d)) <= 1e-14
+    assert abs(e_dark - (0.01 - t_d)) <= 1e-14
+    # the amplitude reading would give these instead (far outside the bounds)
+    rel_amp = abs(0.5 - 0.8) / 0.5
+    assert abs(e_lit - (t_d * rel_amp / t_l - t_d)) > 1e-4
+    assert abs(e_dark - (0.1 - t_d)) > 1e-2
+
+
 # --------------------------------------------------------------------------
 # Intensity-loss gradient (the differentiable form beside the projections)
 # --------------------------------------------------------------------------
@@ -425,6 +465,32 @@ def test_paper_initial_phase():
     want = np.exp(2j * np.pi * (a * ys / h + b * xs / w))
     assert np.max(np.abs(np.exp(1j * phi) - want)) <= 1e-12
     assert np.max(np.abs(gs.paper_initial_phase(np.ones((h, w))))) == 0.0
+
+
+def test_paper_initial_phase_thresholds_intensity():
+    """The 1-bit target is lit where the normalised INTENSITY m^2 / max m^2
+    exceeds t_d.  A second pixel whose amplitude ratio r lies between t_d
+    and sqrt(t_d) is dark under that reading (r^2 < t_d) although r > t_d:
+    the initial mask stays the single plane wave of the first pixel.  With
+    r above sqrt(t_d) the pixel is lit, and the back-propagated pattern is
+    the sum of two plane waves, whose phase differs."""
+    t_d = 3e-4
+    h, w = 16, 32
+    a, b = (3, 5), (7, 2)
+    ys = np.arange(h)[:, None]
+    xs = np.arange(w)[None, :]
+    want = np.exp(2j * np.pi * (a[0] * ys / h + a[1] * xs / w))
+    m = np.zeros((h, w))
+    m[a] = 1.0
+    m[b] = 0.005                      # t_d < 0.005 < sqrt(t_d) = 0.0173
+    phi = gs.paper_initial_phase(m, t_d)
+    assert np.max(np.abs(np.exp(1j * phi) - want)) <= 1e-12
+    m[b] = 0.02                       # 0.02^2 = 4e-4 > t_d: lit
+    two = want + np.exp(2j * np.pi * (b[0] * ys / h + b[1] * xs / w))
+    phi2 = gs.paper_initial_phase(m, t_d)
+    nz = np.abs(two) > 1e-3
+    assert np.max(np.abs(np.exp(1j * phi2[nz]) - two[nz] / np.abs(two[nz]))) <= 1e-9
+    assert np.max(np.abs(np.exp(1j * phi2) - want)) > 0.5
 
 
 def test_one_iteration_sensitivity_rule():
