@@ -100,7 +100,16 @@ pm_status phasemask_create(pm_handle* out, int height, int width,
  * first.  Destroying NULL returns PM_EINVAL. */
 pm_status phasemask_destroy(pm_handle h);
 
-/* Use `stream` (a hipStream_t, NULL = null stream) for subsequent calls. */
+/*
+ * Use `stream` (a hipStream_t, NULL = null stream) for subsequent calls.
+ * Every call of a handle shares its device buffers (pointer block, iterate,
+ * rescaled target, partial sums), so the handle's calls are ordered: when
+ * the stream changes, an event recorded on the previous stream makes the new
+ * stream wait for everything the handle enqueued before the switch (work of
+ * the caller on either stream is not otherwise ordered).  Switching to the
+ * current stream does nothing.
+ * Errors: PM_EINVAL (NULL handle), PM_EDEVICE.
+ */
 pm_status phasemask_set_stream(pm_handle h, void* stream);
 
 /*
@@ -110,9 +119,10 @@ pm_status phasemask_set_stream(pm_handle h, void* stream);
  * are relative to ||p|| with the target energy-matched to ||p||:
  *     E_F = || |F u| - m ||p|| / ||m|| || / ||p||,
  *     G   = || |P_M u| - p || / ||p||.
- * Applies to phasemask_solve, phasemask_solve_raar, phasemask_error,
- * phasemask_physical_error (whose field is u = p exp(i phase)) and
- * phasemask_time_passes until changed; the output phase is that of the
+ * Applies to phasemask_solve, phasemask_solve_field (whose P_S then gives
+ * modulus p; its init_field is taken as given), phasemask_solve_raar,
+ * phasemask_error, phasemask_physical_error (whose field is
+ * u = p exp(i phase)) and phasemask_time_passes until changed; the output phase is that of the
  * projected field before the factor p (also defined where p = 0).  Not
  * applied by phasemask_initial_phase, phasemask_fft2 or the intensity-loss
  * entry points.
@@ -157,6 +167,27 @@ pm_status phasemask_set_illumination(pm_handle h, const float* illumination);
 pm_status phasemask_solve(pm_handle h, const float* target_amplitude,
                           const float* init_phase, int n_iter,
                           float* out_phase, double* err_history);
+
+/*
+ * The iteration of phasemask_solve on complex fields: the state of the
+ * method is the SLM field u (Eq. 6), so a solve that hands it back exactly
+ * can be resumed exactly.  u^0 = init_field as given (a point of S, Eq. 1,
+ * normally: unit modulus, or modulus p with an illumination; a field off S
+ * is used as it is, so E_F^0 is then || |F u^0| - m~ || / ||p||), and
+ * out_field receives u^{n_iter}: with n_iter >= 1 the FP32 result of the last
+ * P_S (Eq. 4a), bitwise the value the next iteration would transform, so
+ *   solve_field(a + b, u0)  ==  solve_field(b, solve_field(a, u0))
+ * bitwise in the field and in the history entries they share.
+ *   init_field   complex float[height*width] (interleaved re, im), natural
+ *                layout, 8-byte aligned; finite.
+ *   n_iter       >= 0 (0: out_field = init_field, history [E_F^0]).
+ *   out_field    complex float[height*width]; may alias init_field; must not
+ *                overlap the target or the history.
+ *   target_amplitude, err_history   as for phasemask_solve.
+ * Errors: as phasemask_solve.
+ */
+pm_status phasemask_solve_field(pm_handle h, const float* target_amplitude, const void* init_field,
+                                int n_iter, void* out_field, double* err_history);
 
 /*
  * Relaxed averaged alternating reflections (RAAR), the algorithm the paper
@@ -338,8 +369,40 @@ pm_status phasemask_time_passes(pm_handle h, const float* target_amplitude,
                                 const float* phase, int reps,
                                 float* col_ms, float* row_ms);
 
-/* Plan facts.  Bytes of device workspace currently held by the plan. */
+/* Plan facts.  Bytes of device memory the plan currently owns (a workspace
+ * set by phasemask_set_workspace is the caller's and not counted). */
 size_t phasemask_workspace_bytes(pm_handle h);
+
+/*
+ * Caller-owned workspace, e.g. from the PyTorch caching allocator.  The
+ * workspace of a one-mask plan holds the iterate (complex, 8 bytes per
+ * pixel), the rescaled target (4 bytes per pixel) and the FP64 partial sums
+ * of the error norms (a fixed number of doubles per error-history entry),
+ * each part 256-byte aligned.
+ *
+ * phasemask_workspace_size: bytes a workspace needs for solves of up to
+ * n_iter iterations with a history (2 n_iter + 1 entries; every other entry
+ * point needs at most the size for n_iter = 0, except an intensity-loss call
+ * of `batch` phases, which needs batch entries: the size for n_iter =
+ * batch / 2).  0 for a NULL or batched handle or n_iter < 0.
+ *
+ * phasemask_set_workspace: the plan releases its own iterate, target and
+ * partial-sum buffers and works in [dev_ptr, dev_ptr + bytes) from then on;
+ * dev_ptr = NULL returns to plan-owned buffers (allocated here, partials
+ * grown on demand).  Synchronises the handle's stream first and drops the
+ * captured graphs (they hold the old buffers).  The caller keeps the memory
+ * allocated, on the plan's device, until the plan is destroyed or another
+ * workspace is set, and must not touch it while the plan's work runs.  Its
+ * contents need no initialisation.  A later call that needs more partial
+ * sums than the workspace holds returns PM_EINVAL instead of growing them.
+ * Buffers created on first use (RAAR state, illumination, power image of the
+ * physical error) stay plan-owned.
+ * Errors: PM_EINVAL for a workspace not 256-byte aligned or smaller than
+ * phasemask_workspace_size(h, 0); PM_ESTATE for a batched handle;
+ * PM_ENOMEM (returning to plan-owned buffers); PM_EDEVICE.
+ */
+size_t phasemask_workspace_size(pm_handle h, int n_iter);
+pm_status phasemask_set_workspace(pm_handle h, void* dev_ptr, size_t bytes);
 
 /* Static text for a status code. */
 const char* phasemask_status_string(pm_status s);

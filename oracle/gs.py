@@ -134,10 +134,13 @@ def mask_errors(m: np.ndarray, phi: np.ndarray) -> tuple[float, float]:
     return fourier_error(u, m), gap(P_M(u, mt))
 
 
-def gs_solve(m: np.ndarray, phi0: np.ndarray, n_iter: int, p: np.ndarray | None = None) -> dict:
+def gs_solve(m: np.ndarray, phi0: np.ndarray | None, n_iter: int, p: np.ndarray | None = None,
+             u0: np.ndarray | None = None) -> dict:
     """Method of alternating projections, Eq. 6 (p = 1 unless given).
 
-    u^0 = p exp(i phi0) (a point of S, Eq. 1); for nu = 0 .. n_iter-1:
+    u^0 = p exp(i phi0) (a point of S, Eq. 1), or the complex field ``u0``
+    as given when ``phi0`` is None (Eq. 6 starts from any point; the state
+    of the method is the field); for nu = 0 .. n_iter-1:
         U      = F u^nu                          (Eq. 2 / Eq. 4b)
         E_F^nu = || |U| - m~ || / ||p||           (error before projecting)
         V      = M_hat(U)                         (Eq. 5)
@@ -153,13 +156,18 @@ def gs_solve(m: np.ndarray, phi0: np.ndarray, n_iter: int, p: np.ndarray | None 
     if n_iter < 0:
         raise ValueError("n_iter must be >= 0")
     m = np.asarray(m, dtype=np.float64)
-    phi0 = np.asarray(phi0, dtype=np.float64)
-    if m.shape != phi0.shape or m.ndim != 2:
-        raise ValueError("target and phase must be 2-D arrays of one shape")
+    if (phi0 is None) == (u0 is None):
+        raise ValueError("give exactly one of phi0 and u0")
+    start = np.asarray(phi0 if u0 is None else u0)
+    if m.shape != start.shape or m.ndim != 2:
+        raise ValueError("target and initial point must be 2-D arrays of one shape")
     pp = np.ones_like(m) if p is None else np.asarray(p, dtype=np.float64)
     p_norm = np.linalg.norm(pp)
     mt = matched_target(m, pp)
-    u = pp * np.exp(1j * phi0)
+    if u0 is None:
+        u = pp * np.exp(1j * np.asarray(phi0, dtype=np.float64))
+    else:
+        u = np.asarray(u0, dtype=np.complex128)
     hist = []
     for _ in range(n_iter):
         U = F(u)

@@ -25,6 +25,10 @@ _SIGNATURES = {
     "phasemask_set_illumination": (ctypes.c_int, [_c_handle, ctypes.c_void_p]),
     "phasemask_solve": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "phasemask_solve_field": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "phasemask_workspace_size": (ctypes.c_size_t, [_c_handle, ctypes.c_int]),
+    "phasemask_set_workspace": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_size_t]),
     "phasemask_solve_raar": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                             ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_error": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -145,6 +149,47 @@ class PhaseMask:
         self._stream()
         _check(lib.phasemask_solve(self._h, tp, pp, int(n_iter), op, hp or None), "phasemask_solve")
         return out, hist
+
+    def solve_field(self, target: torch.Tensor, init_field: torch.Tensor, n_iter: int,
+                    out: torch.Tensor | None = None, history: bool | torch.Tensor = True):
+        """n_iter GS iterations from the complex field init_field (complex64
+        [height, width]); returns (u^n as complex64, history or None)."""
+        tp = _dev_ptr(target, torch.float32, self.shape, "target")
+        fp = _dev_ptr(init_field, torch.complex64, self.shape, "init_field")
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.complex64, device=self.device)
+        op = _dev_ptr(out, torch.complex64, self.shape, "out")
+        hist = None
+        if isinstance(history, torch.Tensor):
+            hist = history
+        elif history:
+            hist = torch.empty(2 * int(n_iter) + 1, dtype=torch.float64, device=self.device)
+        hp = 0 if hist is None else _dev_ptr(hist, torch.float64, (2 * int(n_iter) + 1,), "history")
+        self._stream()
+        _check(lib.phasemask_solve_field(self._h, tp, fp, int(n_iter), op, hp or None), "phasemask_solve_field")
+        return out, hist
+
+    def workspace_size(self, n_iter: int) -> int:
+        """Bytes a caller-owned workspace needs for solves of up to n_iter iterations."""
+        if self._h is None:
+            raise PhaseMaskError(-5, "use after close")
+        return int(lib.phasemask_workspace_size(self._h, int(n_iter)))
+
+    def set_workspace(self, buf: torch.Tensor | None):
+        """Work in the caller's device buffer `buf` (a contiguous uint8 tensor,
+        256-byte aligned, at least workspace_size(n) bytes) from now on, or in
+        plan-owned buffers again with None.  The tensor is kept referenced here
+        while the plan uses it."""
+        if self._h is None:
+            raise PhaseMaskError(-5, "use after close")
+        self._stream()
+        if buf is None:
+            _check(lib.phasemask_set_workspace(self._h, None, 0), "phasemask_set_workspace")
+        else:
+            if not (buf.is_cuda and buf.dtype == torch.uint8 and buf.is_contiguous()):
+                raise ValueError("workspace must be a contiguous uint8 device tensor")
+            _check(lib.phasemask_set_workspace(self._h, buf.data_ptr(), buf.numel()), "phasemask_set_workspace")
+        self._ws = buf
 
     def solve_raar(self, target: torch.Tensor, init_phase: torch.Tensor, n_iter: int, beta: float,
                    out: torch.Tensor | None = None, history: bool = True):

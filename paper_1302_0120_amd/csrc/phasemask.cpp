@@ -149,6 +149,10 @@ struct pm_plan {
     size_t part_entries = 0;           // capacity of `part` in history entries
     pm::PmIo* io = nullptr;
     size_t ws_bytes = 0;
+    // A caller-owned workspace (phasemask_set_workspace) holding X, mhat and
+    // the partials; the plan then owns none of the three.
+    bool ws_borrowed = false;
+    hipEvent_t order_ev = nullptr;     // orders the handle's work across a stream switch
     std::list<GraphEntry> graphs;      // most recently used first
     bool dead = false;
 
@@ -196,8 +200,12 @@ void free_plan(pm_plan* h) {
     (void)hipFree(h->mask_prep0);
     (void)hipFree(h->bio);
     (void)hipFree(h->tw_batch);
-    (void)hipFree(h->X);
-    (void)hipFree(h->mhat);
+    if (!h->ws_borrowed) {
+        (void)hipFree(h->X);
+        (void)hipFree(h->mhat);
+        (void)hipFree(h->part);
+    }
+    if (h->order_ev) (void)hipEventDestroy(h->order_ev);
     (void)hipFree(h->twW);
     (void)hipFree(h->twH);
     (void)hipFree(h->part_m);
@@ -207,7 +215,6 @@ void free_plan(pm_plan* h) {
     (void)hipFree(h->illum);
     (void)hipFree(h->pn2);
     (void)hipFree(h->vflags);
-    (void)hipFree(h->part);
     (void)hipFree(h->io);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
@@ -243,9 +250,34 @@ std::vector<float2> staged_twiddles(int L, int P) {
     return t;
 }
 
+// Layout of a caller-owned workspace (phasemask_set_workspace): the iterate,
+// the rescaled target and the partial sums, each 256-byte aligned.
+struct WsLayout {
+    size_t mhat_off, part_off;
+};
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+WsLayout ws_layout(const pm_plan* h) {
+    const size_t x = align256((size_t)h->N * sizeof(float2));
+    return WsLayout{x, x + align256((size_t)h->N * sizeof(float))};
+}
+
+// History entries of partials the calls other than the solves need: two
+// (phasemask_error, phasemask_time_passes), or the physical error's
+// per-block pairs.
+size_t min_partial_entries(const pm_plan* h) {
+    const size_t nblk = ((size_t)h->N / 4 + 255) / 256;
+    return std::max<size_t>(2, 1 + (2 * nblk + h->stride - 1) / h->stride);
+}
+
 // Makes sure `part` holds `entries` history entries of partials.
 pm_status ensure_partials(pm_plan* h, size_t entries) {
     if (entries <= h->part_entries) return PM_OK;
+    if (h->ws_borrowed) {
+        std::ostringstream os;
+        os << "the workspace set by phasemask_set_workspace holds partial sums for " << h->part_entries
+           << " error-history entries; this call needs " << entries << " (see phasemask_workspace_size)";
+        return fail(PM_EINVAL, os.str());
+    }
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
     drop_graphs(h);  // captured graphs hold the old pointer
@@ -300,10 +332,11 @@ pm::ColParams col_params(pm_plan* h, double* part) {
 // PM_FLAG_VALIDATE: checks `n` floats at x on the device (sign only when
 // `nonneg`; all zero is an error only when `need_nonzero`) and waits for the
 // result.  `what` names the argument in the error message.
-pm_status validate_input(pm_plan* h, const float* x, bool nonneg, bool need_nonzero, const char* what) {
+pm_status validate_input(pm_plan* h, const float* x, bool nonneg, bool need_nonzero, const char* what,
+                         int floats_per_pixel = 1) {
     if ((h->flags & PM_FLAG_VALIDATE) == 0 || x == nullptr) return PM_OK;
     PM_TRY(hipMemsetAsync(h->vflags, 0, 2 * sizeof(int), h->stream), "hipMemsetAsync(check)");
-    PM_TRY(pm::launch_validate(x, h->N, nonneg, h->vflags, h->stream), "input check");
+    PM_TRY(pm::launch_validate(x, h->N * floats_per_pixel, nonneg, h->vflags, h->stream), "input check");
     int f[2] = {0, 0};
     PM_TRY(hipMemcpyAsync(f, h->vflags, sizeof(f), hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync(check)");
     PM_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize(check)");
@@ -321,20 +354,34 @@ pm_status enqueue_target(pm_plan* h, hipStream_t s) {
     return PM_OK;
 }
 
+// Solve algorithms (one captured graph per algorithm, n_iter and history).
+enum : int {
+    kAlgoGS = 0,       // alternating projections, phases in and out
+    kAlgoRAAR = 1,     // RAAR, phases in and out
+    kAlgoGSField = 2,  // alternating projections, complex fields in and out
+};
+
 // The whole solve after the pointer block is set: target preparation,
 // u^0, n_iter iterations, final error and history finalisation.
-pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int algo = 0, float beta = 0.0f) {
+pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int algo = kAlgoGS, float beta = 0.0f) {
     const int lw = len_slot(h->W), lh = len_slot(h->H);
     const RowLauncher row = kRowLaunch[lw];
     const ColLauncher col = kColLaunch[lh];
     auto pe = [&](int e) { return h->part + (size_t)e * h->stride; };
+    const bool field = algo == kAlgoGSField;
+    // u^0: exp(i phi0) (times p), or the caller's field as given.
+    const int init_mode = field ? pm::ROW_INIT_FIELD : rmode(h, pm::ROW_INIT);
 
     if (n_iter == 0) {
-        PM_TRY(pm::launch_wrap_phase(h->io, h->N, s), "wrap phase");
+        if (field) {
+            PM_TRY(row(pm::ROW_COPY_FIELD, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "field copy");
+        } else {
+            PM_TRY(pm::launch_wrap_phase(h->io, h->N, s), "wrap phase");
+        }
         if (!hist) return PM_OK;
         pm_status st = enqueue_target(h, s);
         if (st != PM_OK) return st;
-        PM_TRY(row(rmode(h, pm::ROW_INIT), row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+        PM_TRY(row(init_mode, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
         PM_TRY(col(pm::COL_ERR, col_params(h, pe(0)), h->nwg_col, s, nullptr, nullptr), "column error");
         PM_TRY(pm::launch_finalize(h->part, h->stride, h->slots_col, h->slots_row, 1.0 / h->N, h->io, 0, 1, s, 1, pnorm2(h)),
                "finalize");
@@ -342,7 +389,7 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int al
     }
     pm_status st = enqueue_target(h, s);
     if (st != PM_OK) return st;
-    if (algo == 1) {
+    if (algo == kAlgoRAAR) {
         // RAAR: x^0 = exp(i phi0) kept in Z; history = E_F(x^nu) at entries
         // 2 nu and E_F(P_S x^n) at entry 2 n, finalised with step 2.
         pm::RowParams rp = row_params(h, nullptr);
@@ -365,14 +412,16 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int al
         }
         return PM_OK;
     }
-    PM_TRY(row(rmode(h, pm::ROW_INIT), row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+    PM_TRY(row(init_mode, row_params(h, nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
     // Without a history the passes skip their error partial sums.
     const int col_mode = hist ? pm::COL_ITER : pm::COL_ITER_NE;
     const int row_mode = hist ? pm::ROW_ITER : pm::ROW_ITER_NE;
+    const int last_mode = field ? (hist ? pm::ROW_LAST_FIELD_FWD : pm::ROW_LAST_FIELD_NE)
+                                : (hist ? pm::ROW_LAST_FWD : pm::ROW_LAST_NE);
     for (int nu = 0; nu < n_iter; ++nu) {
         PM_TRY(col(col_mode, col_params(h, pe(2 * nu)), h->nwg_col, s, nullptr, nullptr), "column pass");
         const bool last = nu == n_iter - 1;
-        const int mode = !last ? row_mode : (hist ? pm::ROW_LAST_FWD : pm::ROW_LAST_NE);
+        const int mode = !last ? row_mode : last_mode;
         PM_TRY(row(rmode(h, mode), row_params(h, pe(2 * nu + 1)), h->nwg_row, s, nullptr, nullptr), "row pass");
     }
     if (hist) {
@@ -387,7 +436,7 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int al
 pm_status enqueue_batch(pm_plan* h, hipStream_t s, int n_iter, bool err);
 
 // Replays (capturing on first use) the graph of one solve shape.
-pm_status launch_graph(pm_plan* h, int n_iter, bool hist, int algo = 0, float beta = 0.0f) {
+pm_status launch_graph(pm_plan* h, int n_iter, bool hist, int algo = kAlgoGS, float beta = 0.0f) {
     for (auto it = h->graphs.begin(); it != h->graphs.end(); ++it) {
         if (it->n_iter == n_iter && it->hist == hist && it->algo == algo && it->beta == beta) {
             h->graphs.splice(h->graphs.begin(), h->graphs, it);
@@ -815,7 +864,21 @@ pm_status phasemask_destroy(pm_handle h) {
 pm_status phasemask_set_stream(pm_handle h, void* stream) {
     pm_status st = check_handle(h, h != nullptr && h->batched);
     if (st != PM_OK) return st;
-    h->stream = (hipStream_t)stream;
+    const hipStream_t ns = (hipStream_t)stream;
+    if (ns == h->stream) return PM_OK;
+    // The handle's buffers (pointer block, iterate, target, partials) serve
+    // every call, so work enqueued on the new stream waits for everything the
+    // handle enqueued on the old one.
+    if (h->order_ev == nullptr) {
+        hipError_t e = hipEventCreateWithFlags(&h->order_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            h->order_ev = nullptr;
+            return fail_hip(e, "hipEventCreate(stream order)");
+        }
+    }
+    PM_TRY(hipEventRecord(h->order_ev, h->stream), "hipEventRecord(stream order)");
+    PM_TRY(hipStreamWaitEvent(ns, h->order_ev, 0), "hipStreamWaitEvent(stream order)");
+    h->stream = ns;
     return PM_OK;
 }
 
@@ -855,6 +918,64 @@ pm_status phasemask_set_illumination(pm_handle h, const float* illumination) {
 
 size_t phasemask_workspace_bytes(pm_handle h) { return h ? h->ws_bytes : 0; }
 
+size_t phasemask_workspace_size(pm_handle h, int n_iter) {
+    if (h == nullptr || h->dead || h->batched || n_iter < 0) return 0;
+    return ws_layout(h).part_off + std::max(min_partial_entries(h), 2 * (size_t)n_iter + 1) * (size_t)h->stride *
+                                       sizeof(double);
+}
+
+pm_status phasemask_set_workspace(pm_handle h, void* dev_ptr, size_t bytes) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    const WsLayout l = ws_layout(h);
+    const size_t min_bytes = phasemask_workspace_size(h, 0);
+    if (dev_ptr != nullptr) {
+        if (misaligned(dev_ptr, 256)) return fail(PM_EINVAL, "workspace must be 256-byte aligned");
+        if (bytes < min_bytes) {
+            std::ostringstream os;
+            os << "workspace of " << bytes << " bytes is below the minimum of " << min_bytes
+               << " (phasemask_workspace_size(h, 0))";
+            return fail(PM_EINVAL, os.str());
+        }
+    }
+    // Captured graphs and queued work refer to the current buffers.
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+    drop_graphs(h);
+    const size_t own = (size_t)h->N * (sizeof(float2) + sizeof(float)) + h->part_entries * (size_t)h->stride * sizeof(double);
+    if (dev_ptr == nullptr) {
+        if (!h->ws_borrowed) return PM_OK;
+        float2* x = nullptr;
+        float* m = nullptr;
+        e = hipMalloc(&x, (size_t)h->N * sizeof(float2));
+        if (e == hipSuccess) e = hipMalloc(&m, (size_t)h->N * sizeof(float));
+        if (e != hipSuccess) {
+            (void)hipFree(x);
+            return fail_hip(e, "hipMalloc(workspace)");
+        }
+        h->X = x;
+        h->mhat = m;
+        h->part = nullptr;
+        h->part_entries = 0;
+        h->ws_borrowed = false;
+        h->ws_bytes += (size_t)h->N * (sizeof(float2) + sizeof(float));
+        return PM_OK;
+    }
+    if (!h->ws_borrowed) {
+        (void)hipFree(h->X);
+        (void)hipFree(h->mhat);
+        (void)hipFree(h->part);
+        h->ws_bytes -= own;
+    }
+    char* base = (char*)dev_ptr;
+    h->X = (float2*)base;
+    h->mhat = (float*)(base + l.mhat_off);
+    h->part = (double*)(base + l.part_off);
+    h->part_entries = (bytes - l.part_off) / ((size_t)h->stride * sizeof(double));
+    h->ws_borrowed = true;
+    return PM_OK;
+}
+
 pm_status phasemask_solve(pm_handle h, const float* target_amplitude, const float* init_phase, int n_iter,
                           float* out_phase, double* err_history) {
     pm_status st = check_handle(h);
@@ -877,6 +998,34 @@ pm_status phasemask_solve(pm_handle h, const float* target_amplitude, const floa
     PM_TRY(pm::launch_set_io(h->io, io, h->stream), "set io");
     if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_solve(h, h->stream, n_iter, hist);
     return launch_graph(h, n_iter, hist);
+}
+
+pm_status phasemask_solve_field(pm_handle h, const float* target_amplitude, const void* init_field, int n_iter,
+                                void* out_field, double* err_history) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    if (!target_amplitude || !init_field || !out_field) return fail(PM_EINVAL, "null array argument");
+    if (n_iter < 0) return fail(PM_EINVAL, "n_iter must be >= 0");
+    if (misaligned(target_amplitude, 16)) return fail(PM_EINVAL, "target must be 16-byte aligned");
+    if (misaligned(init_field, 8) || misaligned(out_field, 8) || misaligned(err_history, 8))
+        return fail(PM_EINVAL, "misaligned array argument");
+    const size_t nb = (size_t)h->N * sizeof(float);
+    const size_t nf = (size_t)h->N * sizeof(float2);
+    if (overlaps(out_field, nf, target_amplitude, nb)) return fail(PM_EINVAL, "out_field overlaps the target");
+    const bool hist = err_history != nullptr;
+    if (hist && overlaps(err_history, (2 * (size_t)n_iter + 1) * sizeof(double), target_amplitude, nb))
+        return fail(PM_EINVAL, "err_history overlaps the target");
+    if (hist && (overlaps(err_history, (2 * (size_t)n_iter + 1) * sizeof(double), out_field, nf) ||
+                 overlaps(err_history, (2 * (size_t)n_iter + 1) * sizeof(double), init_field, nf)))
+        return fail(PM_EINVAL, "err_history overlaps a field");
+    if ((st = validate_input(h, target_amplitude, true, true, "target")) != PM_OK) return st;
+    if ((st = validate_input(h, (const float*)init_field, false, false, "init_field", 2)) != PM_OK) return st;
+    st = ensure_partials(h, 2 * (size_t)n_iter + 1);
+    if (st != PM_OK) return st;
+    pm::PmIo io{target_amplitude, nullptr, nullptr, err_history, (const float2*)init_field, (float2*)out_field};
+    PM_TRY(pm::launch_set_io(h->io, io, h->stream), "set io");
+    if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_solve(h, h->stream, n_iter, hist, kAlgoGSField);
+    return launch_graph(h, n_iter, hist, kAlgoGSField);
 }
 
 pm_status phasemask_solve_raar(pm_handle h, const float* target_amplitude, const float* init_phase, int n_iter,
@@ -908,8 +1057,8 @@ pm_status phasemask_solve_raar(pm_handle h, const float* target_amplitude, const
     }
     pm::PmIo io{target_amplitude, init_phase, out_phase, err_history};
     PM_TRY(pm::launch_set_io(h->io, io, h->stream), "set io");
-    if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_solve(h, h->stream, n_iter, hist, 1, (float)beta);
-    return launch_graph(h, n_iter, hist, 1, (float)beta);
+    if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_solve(h, h->stream, n_iter, hist, kAlgoRAAR, (float)beta);
+    return launch_graph(h, n_iter, hist, kAlgoRAAR, (float)beta);
 }
 
 pm_status phasemask_error(pm_handle h, const float* target_amplitude, const float* phase, double* errors) {
@@ -1191,8 +1340,7 @@ pm_status phasemask_physical_error(pm_handle h, const float* target_amplitude, c
     if (!(t_lit > 0.0) || !(t_dark >= 0.0 && t_dark < 1.0)) return fail(PM_EINVAL, "need t_lit > 0, 0 <= t_dark < 1");
     if ((st = validate_input(h, target_amplitude, true, true, "target")) != PM_OK) return st;
     if ((st = validate_input(h, phase, false, false, "phase")) != PM_OK) return st;
-    const size_t nblk = ((size_t)h->N / 4 + 255) / 256;
-    st = ensure_partials(h, 1 + (2 * nblk + h->stride - 1) / h->stride);
+    st = ensure_partials(h, min_partial_entries(h));
     if (st != PM_OK) return st;
     if (h->pw == nullptr) {
         hipError_t e = hipMalloc(&h->pw, (size_t)h->N * sizeof(float));

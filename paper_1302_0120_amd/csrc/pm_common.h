@@ -38,6 +38,8 @@ struct PmIo {
     const float* phase_in; // [H][W] initial phase
     float* phase_out;      // [H][W] output phase
     double* hist;          // error history (or the two errors of a mask), may be null
+    const float2* field_in;  // [H][W] complex initial field u^0 (field solves)
+    float2* field_out;       // [H][W] complex output field u^n (field solves)
 };
 
 // Row-pass modes (bit sets).
@@ -55,6 +57,8 @@ enum : int {
     R_RAAR = 1024,    // RAAR update of the SLM-plane point x (kept in Z) from w = P_M x
     R_STOREZ = 2048,  // store the initial field to Z (RAAR start)
     R_ILLUM = 4096,   // illumination amplitude p of Eq. 1 on S (else p = 1)
+    RIN_FIELD = 8192,   // read the natural-layout complex field io->field_in (as RIN_NAT)
+    ROUT_FIELD = 16384, // write the natural-layout complex field to io->field_out (as ROUT_NAT)
 };
 constexpr int ROW_INIT = RIN_PHASE | R_FWD;
 constexpr int ROW_ITER = RIN_TILED | R_INV | R_PS | R_FWD;
@@ -73,6 +77,13 @@ constexpr int ROW_RAAR = RIN_TILED | R_INV | R_RAAR | R_FWD;
 // for the final Fourier error.
 constexpr int ROW_RAAR_LAST = RIN_TILED | R_INV | R_RAAR | ROUT_PHASE;
 constexpr int ROW_RAAR_LAST_FWD = RIN_TILED | R_INV | R_RAAR | ROUT_PHASE | R_FWD;
+// Field solves: u^0 given as a complex field, u^n returned as one (the row
+// pass's field after P_S, before the next forward transform).
+constexpr int ROW_INIT_FIELD = RIN_FIELD | R_FWD;
+constexpr int ROW_LAST_FIELD = RIN_TILED | R_INV | R_PS | ROUT_FIELD;
+constexpr int ROW_LAST_FIELD_FWD = RIN_TILED | R_INV | R_PS | ROUT_FIELD | R_FWD;
+constexpr int ROW_LAST_FIELD_NE = ROW_LAST_FIELD | R_NOERR;
+constexpr int ROW_COPY_FIELD = RIN_FIELD | ROUT_FIELD;  // u^n = u^0 (no iterations)
 
 // Column-pass modes (bit sets).
 enum : int {

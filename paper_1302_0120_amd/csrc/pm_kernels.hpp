@@ -493,6 +493,14 @@ k_col(ColParams a) {
         a, pass_tile<G>(blockIdx.x, gridDim.x), a.part + blockIdx.x * red_slots(NT), lds, red);
 }
 
+// Field modes read / write the caller's complex fields through the pointer
+// block (so a captured graph serves any buffers) and otherwise run as the
+// natural-layout modes.
+__host__ __device__ constexpr int field_as_nat(int mode) {
+    return (mode & ~(RIN_FIELD | ROUT_FIELD)) | ((mode & RIN_FIELD) != 0 ? RIN_NAT : 0) |
+           ((mode & ROUT_FIELD) != 0 ? ROUT_NAT : 0);
+}
+
 template <int W, int MODE, int G = row_lines(W)>
 __global__ void __launch_bounds__(G * LineShape<W>::T)
 k_row(RowParams a) {
@@ -503,7 +511,9 @@ k_row(RowParams a) {
     float* pout = nullptr;
     if constexpr ((MODE & RIN_PHASE) != 0) pin = a.io->phase_in;
     if constexpr ((MODE & ROUT_PHASE) != 0) pout = a.io->phase_out;
-    row_body<W, LineShape<W>::P, G, MODE, row_lanes_ok(W, LineShape<W>::P, G)>(
+    if constexpr ((MODE & RIN_FIELD) != 0) a.nat_in = a.io->field_in;
+    if constexpr ((MODE & ROUT_FIELD) != 0) a.nat_out = a.io->field_out;
+    row_body<W, LineShape<W>::P, G, field_as_nat(MODE), row_lanes_ok(W, LineShape<W>::P, G)>(
         a, pass_tile<G>(blockIdx.x, gridDim.x) * G, pin, pout, a.part + blockIdx.x * red_slots(NT), lds, red);
 }
 

@@ -49,7 +49,8 @@ hipError_t launch(void (*kern)(Params), int grid, int block, hipStream_t s, hipE
 // Row modes of the solves, each also built with R_ILLUM (illumination p).
 #define PM_ROW_SOLVE_MODES(X) \
     X(ROW_INIT) X(ROW_ITER) X(ROW_LAST) X(ROW_LAST_FWD) X(ROW_GAP) X(ROW_ITER_NE) X(ROW_LAST_NE) \
-    X(ROW_INIT_Z) X(ROW_RAAR) X(ROW_RAAR_LAST) X(ROW_RAAR_LAST_FWD)
+    X(ROW_INIT_Z) X(ROW_RAAR) X(ROW_RAAR_LAST) X(ROW_RAAR_LAST_FWD) \
+    X(ROW_LAST_FIELD) X(ROW_LAST_FIELD_FWD) X(ROW_LAST_FIELD_NE)
 #define PM_ROW_CASE(M)                                                                         \
     case M: return launch(k_row<PM_L, M, G>, grid, block, s, ev0, ev1, p);                     \
     case M | R_ILLUM: return launch(k_row<PM_L, M | R_ILLUM, G>, grid, block, s, ev0, ev1, p);
@@ -63,6 +64,8 @@ hipError_t launch_rows(int mode, const RowParams& p, int grid, hipStream_t s, hi
         PM_ROW_SOLVE_MODES(PM_ROW_CASE)
         case ROW_FFT_FWD: return launch(k_row<PM_L, ROW_FFT_FWD, G>, grid, block, s, ev0, ev1, p);
         case ROW_FFT_INV: return launch(k_row<PM_L, ROW_FFT_INV, G>, grid, block, s, ev0, ev1, p);
+        case ROW_INIT_FIELD: return launch(k_row<PM_L, ROW_INIT_FIELD, G>, grid, block, s, ev0, ev1, p);
+        case ROW_COPY_FIELD: return launch(k_row<PM_L, ROW_COPY_FIELD, G>, grid, block, s, ev0, ev1, p);
         default: return hipErrorInvalidValue;
     }
 }

@@ -2,15 +2,18 @@
 
 The stated bound on one iteration is a relative L2 error of 1e-5 between the
 GPU iterate and the FP64 oracle's.  An FP32 computation is, at best, the
-exact result for inputs perturbed at FP32 rounding level (~6e-8 relative),
-so where the problem itself amplifies such perturbations beyond 1e-6 (a
-lit Fourier pixel on which |F u| nearly vanishes makes the phase that M-hat
-keeps ill-conditioned; see the design notes) no FP32 pipeline can meet 1e-5.
-The rule therefore measures that amplification with the oracle alone: the
-FP64 one-iteration result from the initial phase perturbed by uniform
-+-6e-8 rad (three draws, the largest change kept), and allows ten times it
-when that exceeds 1e-5 (the FP32 pipeline rounds at about five stages:
-sincos, row and column transforms both ways, the projections).
+exact result for inputs perturbed at FP32 rounding level (~6e-8 relative).
+Where the problem itself amplifies such perturbations beyond 1e-6, no FP32
+pipeline can meet 1e-5: with few spots on a large frame, M-hat (Eq. 5) keeps
+the phase of Fourier coefficients whose modulus nearly vanishes, and P_S
+(Eq. 4a) keeps the phase of SLM pixels where |P_M u| nearly vanishes; both
+phases move by O(1) under O(eps) changes of the input.  The rule measures
+that amplification with the oracle alone: the FP64 one-iteration result from
+the initial phase perturbed by uniform +-6e-8 rad (three draws, the largest
+change kept), and allows ten times it when that exceeds 1e-5 (the FP32
+pipeline rounds at about five stages: sincos, row and column transforms both
+ways, the projections).  Every shape that needs the rule also runs at the
+literal 1e-5 on a well-conditioned target.
 """
 import numpy as np
 

@@ -128,19 +128,44 @@ def test_batched_graph_and_eager_identical(pmb):
 
 def test_batched_workload_64_mixed_masks(pmb):
     """The 64-mask uneven batch (sizes from {256, 512, 1024}^2, 1-200 spots
-    each), 100 iterations in one graph launch; final errors of sampled masks
-    against the oracle, and every mask's error is that of its returned phase
-    in the monotone-chain sense (below the error of its initial phase)."""
+    each), in one graph launch.  Every mask: one iteration against the
+    oracle (bound of the one-mask tests: 1e-5, or the conditioning rule for
+    the few-spot masks), and the 100-iteration final error against a
+    one-mask GPU solve of the same inputs (whose history the one-mask tests
+    hold to the oracle; the plans differ, so they agree to FP32 rounding).
+    Sampled masks: the 100-iteration final error against the oracle."""
+    from parity_util import one_iteration_tolerance
     probs = synth.batched_problems()
     shapes = [m.shape for m, _ in probs]
     print(f"batched workload: {len(shapes)} masks, sum N = {sum(h * w for h, w in shapes)}", flush=True)
     bp = pmb.BatchedPhaseMask(shapes)
     targets = [_dev(m) for m, _ in probs]
     phases = [_dev(p) for _, p in probs]
+    outs1, _ = bp.solve(targets, phases, 1)
+    outs1 = [o.cpu().numpy() for o in outs1]
     outs, err = bp.solve(targets, phases, 100)
     err = err.cpu().numpy()
     assert np.all(np.isfinite(err))
-    for i in (0, 17, 63):  # sampled masks: the oracle runs 100 iterations on each
+    worst = 0.0
+    for i, (m, p) in enumerate(probs):
+        ref1 = gs.gs_solve(m, p, 1)["u"]
+        u1 = np.exp(1j * outs1[i].astype(np.float64))
+        e1 = np.linalg.norm(u1 - ref1) / np.linalg.norm(ref1)
+        tol = 1e-5 if e1 <= 1e-5 else one_iteration_tolerance(m, p)[0]
+        worst = max(worst, e1 / tol)
+        assert e1 <= tol, (i, shapes[i], e1, tol)
+    print(f"batched workload: one iteration, worst err/tol over 64 masks {worst:.3f}", flush=True)
+    plans = {}
+    worst = 0.0
+    for i, shp in enumerate(shapes):
+        if shp not in plans:
+            plans[shp] = pmb.PhaseMask(*shp)
+        _, hist = plans[shp].solve(targets[i], phases[i], 100)
+        ef = hist[-1].item()
+        worst = max(worst, abs(err[i] - ef) / ef)
+    print(f"batched workload: final E_F vs one-mask solves, worst rel diff {worst:.3e}", flush=True)
+    assert worst <= 1e-4
+    for i in (0, 17, 40, 63):  # sampled masks: the oracle runs 100 iterations on each
         m, p = probs[i]
         ref = gs.gs_solve(m, p, 100)["history"][-1]
         assert abs(err[i] - ref) / ref <= 1e-3, (i, shapes[i], err[i], ref)

@@ -1,0 +1,197 @@
+"""GPU tests of the remaining boundary calls: complex-field solves (exact
+resume, the state of Eq. 6 being the field), a caller-owned workspace, and
+the ordering of one handle's work across a stream switch."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import gs
+from paper_1302_0120_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pmb():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1302_0120_amd import binding
+    return binding
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _problem(h, w, spots, seed):
+    rng = np.random.default_rng(seed)
+    m = synth.spot_amplitude(h, w, spots, 2.0, 0.5, 1.0, rng)
+    phi0 = synth.uniform_phase(h, w, rng)
+    u0 = np.exp(1j * phi0.astype(np.float64)).astype(np.complex64)
+    return m, phi0, u0
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (256, 128), (1024, 1024), (600, 800)])
+def test_solve_field_one_iteration_vs_oracle(pmb, shape):
+    """u^1 from a given field against the oracle started from the same
+    (complex64) field: relative L2 <= 1e-5, history entries <= 1e-5."""
+    h, w = shape
+    print(f"solve_field one iteration {shape}", flush=True)
+    m, _, u0 = _problem(h, w, 30, 11 + h + w)
+    plan = pmb.PhaseMask(h, w)
+    u1, hist = plan.solve_field(_dev(m), _dev(u0), 1)
+    ref = gs.gs_solve(m, None, 1, u0=u0)
+    err = _rel_l2(u1.cpu().numpy().astype(np.complex128), ref["u"])
+    print(f"solve_field one iteration {shape}: err {err:.3e}", flush=True)
+    assert err <= 1e-5, err
+    rel_h = np.abs(hist.cpu().numpy() - ref["history"]) / ref["history"]
+    assert rel_h.max() <= 1e-5, rel_h
+
+
+def test_solve_field_off_S_start(pmb):
+    """A field off S (modulus 2) is used as given: E_F^0 measures it, and
+    the iterates from the first projection on are those of the unit field
+    (the oracle's field start)."""
+    h = w = 128
+    m, _, u0 = _problem(h, w, 12, 5)
+    u2 = (2.0 * u0).astype(np.complex64)  # exact: power of two
+    plan = pmb.PhaseMask(h, w)
+    out, hist = plan.solve_field(_dev(m), _dev(u2), 3)
+    ref = gs.gs_solve(m, None, 3, u0=u2)
+    hg = hist.cpu().numpy()
+    assert np.max(np.abs(hg - ref["history"]) / ref["history"]) <= 1e-5
+    assert _rel_l2(out.cpu().numpy().astype(np.complex128), ref["u"]) <= 1e-5
+
+
+def test_solve_field_resume_is_bitwise(pmb):
+    """solve_field(a + b) == solve_field(b, init = solve_field(a)): fields
+    and the history entries both runs hold, bitwise; also in place (output
+    aliasing the input) and without graphs."""
+    h = w = 256
+    m, _, u0 = _problem(h, w, 20, 41)
+    md = _dev(m)
+    for flags in (0, pmb.PM_FLAG_NO_GRAPH):
+        plan = pmb.PhaseMask(h, w, flags=flags)
+        full, hf = plan.solve_field(md, _dev(u0), 12)
+        full, hf = full.clone(), hf.clone()
+        mid, ha = plan.solve_field(md, _dev(u0), 5)
+        ha = ha.clone()
+        rest, hr = plan.solve_field(md, mid.clone(), 7)
+        assert torch.equal(rest, full)
+        assert torch.equal(hr, hf[10:])
+        assert torch.equal(ha[:10], hf[:10])
+        buf = mid.clone()
+        same, _ = plan.solve_field(md, buf, 7, out=buf, history=False)
+        assert same.data_ptr() == buf.data_ptr() and torch.equal(buf, full)
+
+
+def test_solve_field_zero_iterations_and_phase_agreement(pmb):
+    h, w = 64, 128
+    m, phi0, u0 = _problem(h, w, 6, 23)
+    plan = pmb.PhaseMask(h, w)
+    out, hist = plan.solve_field(_dev(m), _dev(u0), 0)
+    assert torch.equal(out, _dev(u0))
+    ef = gs.gs_solve(m, None, 0, u0=u0)["history"][0]
+    assert hist.shape == (1,) and abs(hist.item() - ef) / ef <= 1e-5
+    # the phase of the field solve's u^n is the phase solve's output (the
+    # device forms exp(i phi0) with sincosf, the host field with exp: they
+    # differ by rounding only)
+    uf, _ = plan.solve_field(_dev(m), _dev(u0), 6)
+    ph, _ = plan.solve(_dev(m), _dev(phi0), 6)
+    d = np.angle(uf.cpu().numpy().astype(np.complex128) * np.exp(-1j * ph.cpu().numpy().astype(np.float64)))
+    assert np.abs(d).max() <= 1e-4
+    assert np.max(np.abs(np.abs(uf.cpu().numpy()) - 1.0)) <= 1e-6
+
+
+def test_solve_field_with_illumination(pmb):
+    """With an illumination p, P_S gives modulus p: the returned field is
+    p e^{i theta}, and one iteration matches the oracle's field start."""
+    h = w = 128
+    m, _, u0 = _problem(h, w, 12, 31)
+    p = synth.gaussian_illumination(h, w, waist=0.45)
+    plan = pmb.PhaseMask(h, w)
+    plan.set_illumination(_dev(p))
+    start = (p.astype(np.float64) * u0).astype(np.complex64)
+    u1, hist = plan.solve_field(_dev(m), _dev(start), 1)
+    ref = gs.gs_solve(m, None, 1, p=p, u0=start)
+    assert _rel_l2(u1.cpu().numpy().astype(np.complex128), ref["u"]) <= 1e-5
+    assert np.max(np.abs(hist.cpu().numpy() - ref["history"]) / ref["history"]) <= 1e-5
+
+
+def test_caller_workspace(pmb):
+    """A caller-owned workspace (torch allocation) gives bitwise the results
+    of the plan's own buffers; too small, misaligned, or too few partial
+    sums for a later call are PM_EINVAL; None returns to plan-owned
+    buffers."""
+    h = w = 512
+    m, phi0, _ = _problem(h, w, 20, 51)
+    md, pd = _dev(m), _dev(phi0)
+    plan = pmb.PhaseMask(h, w)
+    ref, href = plan.solve(md, pd, 10)
+    ref, href = ref.clone(), href.clone()
+    own = plan.workspace_bytes
+    need = plan.workspace_size(10)
+    assert need > plan.workspace_size(0) > 12 * h * w
+    buf = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    off = (-buf.data_ptr()) % 256
+    ws = buf[off:off + need]
+    plan.set_workspace(ws)
+    assert plan.workspace_bytes < own - 12 * h * w + 1
+    a, ha = plan.solve(md, pd, 10)
+    assert torch.equal(a, ref) and torch.equal(ha, href)
+    with pytest.raises(pmb.PhaseMaskError) as ei:
+        plan.solve(md, pd, 11)  # 23 history entries > what the workspace holds
+    assert ei.value.status == -1 and b"workspace" in pmb.lib.phasemask_last_error()
+    b, _ = plan.solve(md, pd, 10)  # still usable
+    assert torch.equal(b, ref)
+    small = torch.empty(plan.workspace_size(0) - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(pmb.PhaseMaskError):
+        plan.set_workspace(small)
+    st = pmb.lib.phasemask_set_workspace(plan._h, ctypes.c_void_p(ws.data_ptr() + 8), need - 8)
+    assert st == -1
+    plan.set_workspace(None)
+    c, hc = plan.solve(md, pd, 10)
+    assert torch.equal(c, ref) and torch.equal(hc, href)
+    assert plan.workspace_bytes >= own
+    bp = pmb.BatchedPhaseMask([(64, 64)])
+    assert pmb.lib.phasemask_set_workspace(bp._h, ctypes.c_void_p(ws.data_ptr()), need) == -5
+    assert pmb.lib.phasemask_workspace_size(bp._h, 1) == 0
+
+
+def test_stream_switch_orders_the_handles_work(pmb):
+    """One handle, a 4096^2 x 20 solve enqueued on stream A and at once a
+    solve of other inputs on stream B: the handle's shared buffers would be
+    overwritten mid-solve unless B waits for A's work.  Both outputs equal
+    single-stream runs bitwise."""
+    n, iters = 4096, 20
+    print("stream switch 4096^2", flush=True)
+    m1, p1, _ = _problem(n, n, 60, 61)
+    m2, p2, _ = _problem(n, n, 40, 62)
+    md1, pd1, md2, pd2 = _dev(m1), _dev(p1), _dev(m2), _dev(p2)
+    plan = pmb.PhaseMask(n, n)
+    r1, h1 = plan.solve(md1, pd1, iters)
+    r1, h1 = r1.clone(), h1.clone()
+    r2, h2 = plan.solve(md2, pd2, iters)
+    r2, h2 = r2.clone(), h2.clone()
+    torch.cuda.synchronize()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    out1 = torch.empty_like(pd1)
+    out2 = torch.empty_like(pd2)
+    hist1 = torch.empty_like(h1)
+    hist2 = torch.empty_like(h2)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        with torch.cuda.stream(sa):
+            plan.solve(md1, pd1, iters, out=out1, history=hist1)
+        with torch.cuda.stream(sb):
+            plan.solve(md2, pd2, iters, out=out2, history=hist2)
+        torch.cuda.synchronize()
+        assert torch.equal(out1, r1) and torch.equal(hist1, h1)
+        assert torch.equal(out2, r2) and torch.equal(hist2, h2)

@@ -512,3 +512,21 @@ def test_one_iteration_sensitivity_rule():
         assert parity_util.oracle_sensitivity(m, phi0) == 0.0
     finally:
         parity_util.EPS32 = old
+
+
+def test_start_from_a_field():
+    """Eq. 6 from a given field u^0.  P_M keeps only the phase of F u
+    (Eq. 5), so it is unchanged when u is scaled by c > 0: from u^0 =
+    2 exp(i phi) the iterates u^1, u^2, ... are those from exp(i phi) and
+    G^0 is unchanged, while E_F^0 measures |F u^0| = 2 |F exp(i phi)|."""
+    m, phi = _spots(16, 32, 8)
+    n = m.size
+    a = gs.gs_solve(m, phi, 4)
+    b = gs.gs_solve(m, None, 4, u0=2.0 * np.exp(1j * phi.astype(np.float64)))
+    assert np.max(np.abs(a["u"] - b["u"])) <= 1e-12
+    assert np.max(np.abs(a["history"][1:] - b["history"][1:])) <= 1e-12
+    mt = gs.matched_target(m)
+    U = gs.F(np.exp(1j * phi.astype(np.float64)))
+    assert abs(b["history"][0] - np.linalg.norm(2.0 * np.abs(U) - mt) / math.sqrt(n)) <= 1e-12
+    with pytest.raises(ValueError):
+        gs.gs_solve(m, phi, 1, u0=np.exp(1j * phi))
