@@ -6,14 +6,22 @@
 
 namespace pm {
 
-// Rewrites the per-call pointer block (4 pointers), one lane per pointer.
-__global__ void k_set_io(PmIo* io, PmIo val) {
-    const unsigned long long vals[4] = {
-        (unsigned long long)val.target, (unsigned long long)val.phase_in,
-        (unsigned long long)val.phase_out, (unsigned long long)val.hist};
+// Rewrites a device-resident pointer block (PmIo, BatchIo: pointers only),
+// one lane per 8-byte word, every word of the struct.
+template <class Block>
+__device__ __forceinline__ void set_words(Block* dst, const Block& val) {
+    constexpr int kWords = (int)(sizeof(Block) / sizeof(unsigned long long));
+    static_assert(sizeof(Block) == kWords * sizeof(unsigned long long), "pointer blocks hold pointers only");
+    static_assert(kWords <= 64, "one lane per word");
+    unsigned long long w[kWords];
+    __builtin_memcpy(w, &val, sizeof(val));
     const int i = threadIdx.x;
-    if (i < 4) reinterpret_cast<unsigned long long*>(io)[i] = vals[i];
+#pragma unroll
+    for (int k = 0; k < kWords; ++k)
+        if (i == k) reinterpret_cast<unsigned long long*>(dst)[k] = w[k];
 }
+
+__global__ void k_set_io(PmIo* io, PmIo val) { set_words(io, val); }
 
 constexpr int kAuxThreads = 256;
 
@@ -153,13 +161,7 @@ __global__ void __launch_bounds__(kAuxThreads) k_wrap_phase(const PmIo* io, int 
 
 // ----- batched preparation ---------------------------------------------------
 
-__global__ void k_set_batch_io(BatchIo* io, BatchIo val) {
-    const unsigned long long vals[4] = {
-        (unsigned long long)val.targets, (unsigned long long)val.phases_in,
-        (unsigned long long)val.phases_out, (unsigned long long)val.final_err};
-    const int i = threadIdx.x;
-    if (i < 4) reinterpret_cast<unsigned long long*>(io)[i] = vals[i];
-}
+__global__ void k_set_batch_io(BatchIo* io, BatchIo val) { set_words(io, val); }
 
 // Sum of m^2 over one task's kPrepPixels pixels (4 float4 per thread).
 __global__ void __launch_bounds__(kAuxThreads)
