@@ -169,6 +169,33 @@ pm_status phasemask_solve(pm_handle h, const float* target_amplitude,
                           float* out_phase, double* err_history);
 
 /*
+ * For callers that cannot allocate device memory when they solve (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * phasemask_solve without any allocation.  Same arguments, results (bitwise)
+ * and errors as phasemask_solve, except:
+ *   - the iterate, the rescaled target, the pointer block and the FP64
+ *     partial sums live in a scratch array the library holds on every GPU
+ *     it runs on (32 MiB each, until the process ends; its device address is
+ *     looked up once per device, at phasemask_create), not in the plan;
+ *   - it enqueues the solve's kernels on the handle's stream one by one (no
+ *     graph, no synchronisation, no allocation, no memset), so a caller may
+ *     capture it;
+ *   - PM_FLAG_VALIDATE is not honoured (its check would synchronise);
+ *   - the solve must fit in the array: 12 bytes per pixel plus, with a
+ *     history, 2 n_iter + 1 entries of FP64 partial sums (16 KiB per entry
+ *     at 1024 x 1024, so 1024 x 1024 fits with histories of up to 639
+ *     iterations; 2048 x 2048 does not fit); else PM_EINVAL stating the
+ *     bytes needed.
+ * Nothing in the array needs to start at zero (each call writes every byte
+ * it reads before reading it), but every call on one GPU shares that GPU's
+ * array: calls whose work can overlap on one GPU (other streams, plans or
+ * host threads) race on it and give undefined results, so order them.
+ */
+pm_status phasemask_solve_noalloc(pm_handle h, const float* target_amplitude,
+                                  const float* init_phase, int n_iter,
+                                  float* out_phase, double* err_history);
+
+/*
  * The iteration of phasemask_solve on complex fields: the state of the
  * method is the SLM field u (Eq. 6), so a solve that hands it back exactly
  * can be resumed exactly.  u^0 = init_field as given (a point of S, Eq. 1,

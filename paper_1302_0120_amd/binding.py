@@ -27,6 +27,8 @@ _SIGNATURES = {
                                        ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_solve_field": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                              ctypes.c_void_p, ctypes.c_void_p]),
+    "phasemask_solve_noalloc": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                               ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_workspace_size": (ctypes.c_size_t, [_c_handle, ctypes.c_int]),
     "phasemask_set_workspace": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_size_t]),
     "phasemask_solve_raar": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
@@ -149,6 +151,19 @@ class PhaseMask:
         self._stream()
         _check(lib.phasemask_solve(self._h, tp, pp, int(n_iter), op, hp or None), "phasemask_solve")
         return out, hist
+
+    def solve_noalloc(self, target: torch.Tensor, init_phase: torch.Tensor, n_iter: int,
+                      out: torch.Tensor, history: torch.Tensor | None = None):
+        """phasemask_solve in the library's per-GPU scratch array: the library
+        allocates nothing, so the caller passes the output (and history)
+        buffers.  Returns (out, history)."""
+        tp = _dev_ptr(target, torch.float32, self.shape, "target")
+        pp = _dev_ptr(init_phase, torch.float32, self.shape, "init_phase")
+        op = _dev_ptr(out, torch.float32, self.shape, "out")
+        hp = 0 if history is None else _dev_ptr(history, torch.float64, (2 * int(n_iter) + 1,), "history")
+        self._stream()
+        _check(lib.phasemask_solve_noalloc(self._h, tp, pp, int(n_iter), op, hp or None), "phasemask_solve_noalloc")
+        return out, history
 
     def solve_field(self, target: torch.Tensor, init_field: torch.Tensor, n_iter: int,
                     out: torch.Tensor | None = None, history: bool | torch.Tensor = True):

@@ -153,6 +153,10 @@ struct pm_plan {
     // the partials; the plan then owns none of the three.
     bool ws_borrowed = false;
     hipEvent_t order_ev = nullptr;     // orders the handle's work across a stream switch
+    // Device address of the allocation-free solve's scratch array on the
+    // plan's device (looked up at create), or null with the lookup's error.
+    unsigned char* scratch = nullptr;
+    hipError_t scratch_err = hipSuccess;
     std::list<GraphEntry> graphs;      // most recently used first
     bool dead = false;
 
@@ -786,6 +790,10 @@ const char* phasemask_status_string(pm_status s) {
 
 const char* phasemask_last_error(void) { return g_last_error.c_str(); }
 
+namespace {
+hipError_t scratch_address(int device, unsigned char** out);  // allocation-free solve (below)
+}  // namespace
+
 pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags, void* stream) {
     if (out == nullptr) return fail(PM_EINVAL, "out is NULL");
     *out = nullptr;
@@ -837,6 +845,9 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
         return bail(e, "hipMemcpy(twiddles)");
     if ((e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess)
         return bail(e, "hipStreamCreate");
+    // Set-up of the allocation-free solve on this device (the plan's device
+    // is current here); a failed lookup only disables that entry point.
+    h->scratch_err = scratch_address(h->device, &h->scratch);
     if ((flags & PM_FLAG_VALIDATE) != 0 && (e = hipMalloc(&h->vflags, 2 * sizeof(int))) != hipSuccess)
         return bail(e, "hipMalloc(check)");
     if (std::getenv("PHASEMASK_LOG") != nullptr) {
@@ -976,8 +987,11 @@ pm_status phasemask_set_workspace(pm_handle h, void* dev_ptr, size_t bytes) {
     return PM_OK;
 }
 
-pm_status phasemask_solve(pm_handle h, const float* target_amplitude, const float* init_phase, int n_iter,
-                          float* out_phase, double* err_history) {
+namespace {
+
+// Argument checks shared by phasemask_solve and phasemask_solve_noalloc.
+pm_status check_solve_args(pm_plan* h, const float* target_amplitude, const float* init_phase, int n_iter,
+                           const float* out_phase, const double* err_history) {
     pm_status st = check_handle(h);
     if (st != PM_OK) return st;
     if (!target_amplitude || !init_phase || !out_phase) return fail(PM_EINVAL, "null array argument");
@@ -987,9 +1001,18 @@ pm_status phasemask_solve(pm_handle h, const float* target_amplitude, const floa
         return fail(PM_EINVAL, "misaligned array argument");
     const size_t nb = (size_t)h->N * sizeof(float);
     if (overlaps(out_phase, nb, target_amplitude, nb)) return fail(PM_EINVAL, "out_phase overlaps the target");
-    const bool hist = err_history != nullptr;
-    if (hist && overlaps(err_history, (2 * (size_t)n_iter + 1) * sizeof(double), target_amplitude, nb))
+    if (err_history && overlaps(err_history, (2 * (size_t)n_iter + 1) * sizeof(double), target_amplitude, nb))
         return fail(PM_EINVAL, "err_history overlaps the target");
+    return PM_OK;
+}
+
+}  // namespace
+
+pm_status phasemask_solve(pm_handle h, const float* target_amplitude, const float* init_phase, int n_iter,
+                          float* out_phase, double* err_history) {
+    pm_status st = check_solve_args(h, target_amplitude, init_phase, n_iter, out_phase, err_history);
+    if (st != PM_OK) return st;
+    const bool hist = err_history != nullptr;
     if ((st = validate_input(h, target_amplitude, true, true, "target")) != PM_OK) return st;
     if ((st = validate_input(h, init_phase, false, false, "init_phase")) != PM_OK) return st;
     st = ensure_partials(h, 2 * (size_t)n_iter + 1);
@@ -998,6 +1021,119 @@ pm_status phasemask_solve(pm_handle h, const float* target_amplitude, const floa
     PM_TRY(pm::launch_set_io(h->io, io, h->stream), "set io");
     if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_solve(h, h->stream, n_iter, hist);
     return launch_graph(h, n_iter, hist);
+}
+
+// ----- allocation-free solve ----------------------------------------------------
+
+// Scratch of phasemask_solve_noalloc: the iterate, the rescaled target, the
+// target-norm partials, the pointer block and the FP64 error partials of one
+// solve.  A file-scope device array: every GPU the library runs on holds its
+// own copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, never a device address; the kernels get the per-device address
+// that hipGetSymbolAddress returns (scratch_address).
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+struct ScratchSlot {
+    std::once_flag once;
+    void* ptr = nullptr;
+    hipError_t err = hipSuccess;
+};
+ScratchSlot g_scratch[kMaxScratchDevices];
+
+// Address of `scratch` on `device`, which must be the current device; looked
+// up once per device and kept.
+hipError_t scratch_address(int device, unsigned char** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    ScratchSlot& slot = g_scratch[device];
+    std::call_once(slot.once, [&slot] { slot.err = hipGetSymbolAddress(&slot.ptr, HIP_SYMBOL(scratch)); });
+    if (slot.err == hipSuccess) *out = static_cast<unsigned char*>(slot.ptr);
+    return slot.err;
+}
+
+// Where one solve's buffers sit in the scratch array (each part 256-byte
+// aligned); `end` is the bytes the solve needs.
+struct NoAllocLayout {
+    size_t x, mhat, part_m, io, part, end;
+};
+NoAllocLayout noalloc_layout(const pm_plan* h, size_t entries) {
+    NoAllocLayout l{};
+    size_t o = 0;
+    l.x = o;
+    o += align256((size_t)h->N * sizeof(float2));
+    l.mhat = o;
+    o += align256((size_t)h->N * sizeof(float));
+    l.part_m = o;
+    o += align256(kNormGrid * sizeof(double));
+    l.io = o;
+    o += align256(sizeof(pm::PmIo));
+    l.part = o;
+    o += entries * (size_t)h->stride * sizeof(double);
+    l.end = o;
+    return l;
+}
+
+// Points the plan's solve buffers at other memory for the lifetime of the
+// object (the kernels take the pointers as launch arguments, so restoring
+// them after the launches are enqueued is safe).
+class BufferSwap {
+  public:
+    BufferSwap(pm_plan* h, float2* x, float* mhat, double* part_m, pm::PmIo* io, double* part)
+        : h_(h), x_(h->X), mhat_(h->mhat), part_m_(h->part_m), io_(h->io), part_(h->part) {
+        h->X = x;
+        h->mhat = mhat;
+        h->part_m = part_m;
+        h->io = io;
+        h->part = part;
+    }
+    ~BufferSwap() {
+        h_->X = x_;
+        h_->mhat = mhat_;
+        h_->part_m = part_m_;
+        h_->io = io_;
+        h_->part = part_;
+    }
+    BufferSwap(const BufferSwap&) = delete;
+    BufferSwap& operator=(const BufferSwap&) = delete;
+
+  private:
+    pm_plan* h_;
+    float2* x_;
+    float* mhat_;
+    double* part_m_;
+    pm::PmIo* io_;
+    double* part_;
+};
+
+}  // namespace
+
+pm_status phasemask_solve_noalloc(pm_handle h, const float* target_amplitude, const float* init_phase, int n_iter,
+                                  float* out_phase, double* err_history) {
+    pm_status st = check_solve_args(h, target_amplitude, init_phase, n_iter, out_phase, err_history);
+    if (st != PM_OK) return st;
+    if (h->scratch == nullptr)
+        return fail(PM_EDEVICE, std::string("no address for the scratch array on this device: ") +
+                                    hipGetErrorString(h->scratch_err));
+    const bool hist = err_history != nullptr;
+    const NoAllocLayout l = noalloc_layout(h, hist ? 2 * (size_t)n_iter + 1 : 1);
+    if (l.end > kNoAllocScratchBytes) {
+        std::ostringstream os;
+        os << "a " << h->H << "x" << h->W << " solve of " << n_iter << " iterations"
+           << (hist ? " with a history" : "") << " needs " << l.end
+           << " bytes of scratch; the allocation-free solve has " << kNoAllocScratchBytes;
+        return fail(PM_EINVAL, os.str());
+    }
+    unsigned char* base = h->scratch;
+    BufferSwap swap(h, reinterpret_cast<float2*>(base + l.x), reinterpret_cast<float*>(base + l.mhat),
+                    reinterpret_cast<double*>(base + l.part_m), reinterpret_cast<pm::PmIo*>(base + l.io),
+                    reinterpret_cast<double*>(base + l.part));
+    pm::PmIo io{target_amplitude, init_phase, out_phase, err_history};
+    PM_TRY(pm::launch_set_io(h->io, io, h->stream), "set io");
+    return enqueue_solve(h, h->stream, n_iter, hist);
 }
 
 pm_status phasemask_solve_field(pm_handle h, const float* target_amplitude, const void* init_field, int n_iter,
