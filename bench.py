@@ -59,13 +59,95 @@ def environment(torch):
             "torch": torch.__version__, "host_cpu": cpu, "host_threads": os.cpu_count()}
 
 
-def cpu_baseline(m, phi0, n_iter_sample):
-    """The FP64 oracle, as it stands, on a bounded sample of the workload."""
+def _median_of_reps(fn, reps=3):
+    """1 warm-up call, then `reps` timed calls; the median duration in s."""
+    import statistics
+    fn()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        times.append(time.perf_counter() - t0)
+    return statistics.median(times)
+
+
+def cpu_baseline(m, phi0, n_iter_sample, reps=3):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload
+    (its first n_iter_sample iterations): 1 warm-up (2 iterations: FFT
+    set-up) + `reps` timed runs, median."""
     from oracle import gs
-    t0 = time.perf_counter()
-    gs.gs_solve(m, phi0, n_iter_sample)
-    dt = time.perf_counter() - t0
+    import statistics
+    gs.gs_solve(m, phi0, 2)
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        gs.gs_solve(m, phi0, n_iter_sample)
+        times.append(time.perf_counter() - t0)
+    dt = statistics.median(times)
     return n_iter_sample / dt, dt
+
+
+def cpu_fp32_gs(m, phi0, n_iter, workers):
+    """A multithreaded FP32 CPU run of the same iteration, the analogue of the
+    paper's multithreaded CPU comparison (Sec. IV.A: FFTW on 12 threads):
+    complex64 2-D FFTs by scipy.fft on `workers` threads, the projections of
+    Eq. 4a and Eq. 5 in NumPy, no error history.  A timing baseline only:
+    nothing here is used as a reference for results."""
+    import numpy as np
+    import scipy.fft as sfft
+    mm = m.astype(np.float32)
+    ones = np.ones_like(mm)
+
+    def project(z, modulus):
+        # modulus * z / |z|; modulus (phase 0) where z = 0
+        a = np.abs(z)
+        nz = a > 0
+        np.divide(modulus, a, out=a, where=nz)
+        out = z * a
+        if not nz.all():
+            out[~nz] = modulus[~nz]
+        return out
+
+    def run():
+        u = np.exp(1j * phi0.astype(np.float32)).astype(np.complex64)
+        for _ in range(n_iter):
+            U = sfft.fft2(u, workers=workers, overwrite_x=True)
+            w = sfft.ifft2(project(U, mm), workers=workers, overwrite_x=True)
+            u = project(w, ones)
+        return u
+    return _median_of_reps(run)
+
+
+def host_cpu_model():
+    """CPU model as lscpu reports it (else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10)
+        for line in r.stdout.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return "unknown"
+
+
+def copy_bandwidth(torch, nbytes, reps=200):
+    """Device-to-device copy of `nbytes` (the iterate of the workload) back to
+    back on torch's current stream, the bandwidth a pass moving the same
+    working set could reach: read + write bytes over the mean copy time
+    (events on the stream the copies run on)."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(20):
+        b.copy_(a)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    us = ev0.elapsed_time(ev1) * 1e3 / reps
+    return 2 * nbytes / (us * 1e-6) / 1e9, us
 
 
 def bench_batched(torch, binding, synth, steps):
@@ -314,8 +396,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--cpu-iters", type=int, default=64,
-                    help="iterations of the FP64 oracle timed for the CPU baseline")
+    ap.add_argument("--cpu-iters", type=int, default=32,
+                    help="iterations of the FP64 oracle timed for the CPU baseline (per rep)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-versus-plain measurement")
@@ -408,6 +490,7 @@ def main():
     achieved = kbytes / (kms * 1e-3) / 1e9
     traffic = TRAFFIC_BYTES[kname] if kernel_source_hash() == TRAFFIC_SOURCE_HASH else None
     solve_gbs = (COL_BYTES_PER_PX + ROW_BYTES_PER_PX) * npx * n_iter / (ms_per_step * 1e-3) / 1e9
+    copy_gbs, copy_us = copy_bandwidth(torch, npx * 8)
 
     line = {
         "metric": METRIC,
@@ -429,7 +512,10 @@ def main():
                    "history": "fp64 E_F/G per iteration", "launch": "hip graph"},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel_us": kms * 1e3, "bytes_per_launch": kbytes},
+                     "kernel_us": kms * 1e3, "bytes_per_launch": kbytes,
+                     # measured copy of the same working set (the 8 MiB iterate
+                     # read and written), and the kernel's fraction of it
+                     "copy_gbs": copy_gbs, "copy_us": copy_us, "frac_of_copy": achieved / copy_gbs},
         # per-launch durations in the timed solves (per-iteration device
         # time split by the eager launch-event ratio), and the eager ones
         "passes_us": {"column": col_us, "row": row_us},
@@ -450,10 +536,22 @@ def main():
         line["other_configs"] = bench_other_configs(torch, binding, synth)
     if not args.no_cpu_baseline:
         rate, cdt = cpu_baseline(m, phi0, args.cpu_iters)
+        threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        t32 = cpu_fp32_gs(m, phi0, n_iter, threads)
         line["cpu_baseline"] = {
             "value": rate, "unit": "GS it/s (1024x1024 mask)", "cores": 1, "kind": "oracle",
             "sample": f"FP64 NumPy oracle, first {args.cpu_iters} of the {n_iter} iterations of "
-                      f"the same 1024x1024 spot workload, single thread, {cdt:.1f} s"}
+                      f"the same 1024x1024 spot workload, single thread; median of 3 runs after "
+                      f"a warm-up, {cdt:.2f} s per run",
+            "cpu_model": host_cpu_model(),
+            "gpu_over_cpu": line["value"] / rate,
+            # the analogue of the paper's multithreaded CPU comparison
+            "fp32_multithreaded": {
+                "value": n_iter / t32, "unit": "GS it/s (1024x1024 mask)", "cores": threads,
+                "ms_per_mask": t32 * 1e3,
+                "sample": f"scipy.fft complex64 on {threads} threads, all {n_iter} iterations, "
+                          f"no history; median of 3 runs after a warm-up",
+                "gpu_over_cpu": line["value"] / (n_iter / t32)}}
     print(json.dumps(line), flush=True)
 
 

@@ -329,13 +329,51 @@ __device__ __forceinline__ void dft(float2 (&x)[R]) {
 __host__ __device__ constexpr int lds_pad_scheme(int L) {
     return (L == 2048 || L == 4096) ? PM_LDS_PAD_LONG : PM_LDS_PAD;
 }
-__host__ __device__ constexpr int lds_pad(int L, int i) {
-    return lds_pad_scheme(L) == 0 ? i + (i >> 4)
-         : lds_pad_scheme(L) == 1 ? i + (i >> 5)
-         : lds_pad_scheme(L) == 2 ? i
-                                  : i + (i >> 4) + (i >> 8);
+// A layout code LAY = scheme * 64 + extra names a padding scheme (as above)
+// and the extra elements between consecutive lines (< 64).  Each pass
+// type takes its layout as a template argument; lds_layout(L) is the
+// default, row_lds_layout(L) the one-mask row pass's (PM_ROW_LDS_LAYOUT
+// overrides it at every power-of-two length up to 1024).
+__host__ __device__ constexpr int lds_layout(int L) { return lds_pad_scheme(L) * 64 + PM_LDS_LINE_EXTRA; }
+#ifndef PM_ROW_LDS_LAYOUT
+#define PM_ROW_LDS_LAYOUT -1
+#endif
+__host__ __device__ constexpr int row_lds_layout(int L) {
+    return (PM_ROW_LDS_LAYOUT >= 0 && L <= 1024 && (L & (L - 1)) == 0) ? PM_ROW_LDS_LAYOUT
+         : L == 1024 ? 4 * 64 + 8
+                     : lds_layout(L);
 }
-__host__ __device__ constexpr int lds_line_len(int L) { return lds_pad(L, L) + PM_LDS_LINE_EXTRA; }
+// Schemes 4 and 5 are swizzles without spare slots: element i of a line
+// sits at i ^ mask(i), mask(i) = (bit 4 of i) << 2 ^ key (scheme 4) or
+// (bits 3-4 of i) << 1 ^ key (scheme 5), where `key` (0, 2, 4 or 6) is a
+// per-line constant the pass chooses.  The mask only flips bits 1-2 and is
+// steered by bits 3-4, which it never flips, so each map is a bijection of
+// [0, L) that keeps 16-byte pairs together, and adding a multiple of 32 to
+// i adds it to the slot (one base address serves a thread's strided reads).
+__host__ __device__ constexpr int lds_pad_lay(int lay, int i) {
+    return lay / 64 == 0 ? i + (i >> 4)
+         : lay / 64 == 1 ? i + (i >> 5)
+         : lay / 64 == 2 ? i
+         : lay / 64 == 3 ? i + (i >> 4) + (i >> 8)
+                         : i;
+}
+__host__ __device__ constexpr int lds_swizzle_mask(int lay, int i, int key) {
+    return lay / 64 == 4 ? ((((i >> 4) & 1) << 2) ^ key) : lay / 64 == 5 ? ((((i >> 3) & 3) << 1) ^ key) : 0;
+}
+__host__ __device__ constexpr bool lds_swizzled(int lay) { return lay / 64 == 4 || lay / 64 == 5; }
+__host__ __device__ constexpr int lds_index(int lay, int i, int key) {
+    return lds_swizzled(lay) ? (i ^ lds_swizzle_mask(lay, i, key)) : lds_pad_lay(lay, i);
+}
+#ifndef PM_COL_LDS_LAYOUT
+#define PM_COL_LDS_LAYOUT -1
+#endif
+// Layout of the one-mask column pass (PM_COL_LDS_LAYOUT overrides it at 1024).
+__host__ __device__ constexpr int col_lds_layout(int L) {
+    return (PM_COL_LDS_LAYOUT >= 0 && L == 1024) ? PM_COL_LDS_LAYOUT : lds_layout(L);
+}
+__host__ __device__ constexpr int lds_line_len_lay(int L, int lay) { return lds_pad_lay(lay, L) + lay % 64; }
+__host__ __device__ constexpr int lds_pad(int L, int i) { return lds_pad_lay(lds_layout(L), i); }
+__host__ __device__ constexpr int lds_line_len(int L) { return lds_line_len_lay(L, lds_layout(L)); }
 
 // LDS-resident transforms.  For lengths whose register plan would need too
 // many points per thread (1920 needs P = 60 and spills), every stage reads
@@ -543,9 +581,9 @@ __device__ __forceinline__ void load_twiddles(LineTwiddles<L, P>& tw, int j, con
 // they lose to the second barrier (64-mask workload: 2970 -> 3570 masks/s;
 // the one-mask 1024^2 solve, one work-group per CU, is 1% slower that way).
 // `stride` is the distance between the buffers.
-template <int L, int G, int NBMAX = 2>
+template <int L, int G, int NBMAX = 2, int LAY = lds_layout(L)>
 struct LdsPlan {
-    static constexpr int LP = lds_line_len(L);
+    static constexpr int LP = lds_line_len_lay(L, LAY);
     static constexpr int NBUF = (lds_mode(L) || (NBMAX == 2 && 2 * G * LP * 8 <= 80 * 1024)) ? 2 : 1;
     static constexpr int FLOATS2 = NBUF * G * LP;  // float2 elements per work-group
     static constexpr int STRIDE = G * LP;
@@ -686,9 +724,9 @@ __device__ __forceinline__ void fft_last_radix4_lanes(float2 (&v)[P], int j, con
 // buffer this stage's exchange uses when NBUF == 2.  SW: the lanes hold
 // their threads as fft_last_radix2_lanes needs, so a lane_swap_plan runs its
 // last stage across lanes.
-template <int L, int P, int NS, int OFF, bool INV, int NBUF, int PAR, bool SW>
+template <int L, int P, int NS, int OFF, bool INV, int NBUF, int PAR, bool SW, int LAY = lds_layout(L)>
 __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, int stride,
-                                          const LineTwiddles<L, P>& tw) {
+                                          const LineTwiddles<L, P>& tw, int key = 0) {
     constexpr int T = L / P;
     constexpr int R = stage_radix(L, P, NS);
     constexpr int M = P / R;
@@ -720,10 +758,24 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, i
         if constexpr (LAST || LANES_NEXT) {
 #pragma unroll
             for (int q = 0; q < R; ++q) v[m + q * M] = x[q];
+        } else if constexpr (lds_swizzled(LAY) && NS == 1 && R % 2 == 0 && R >= 8) {
+            // R contiguous outputs from base = R b: bits 3-4 of base + q equal
+            // those of base (q < R, R a multiple of 8), so one mask permutes the
+            // 16-byte pairs of the group.
+            const int base = b * R;
+            const int msk = lds_swizzle_mask(LAY, base, key);
+#pragma unroll
+            for (int q = 0; q < R; q += 2)
+                *reinterpret_cast<float4*>(buf + base + (q ^ msk)) = make_float4(x[q].x, x[q].y, x[q + 1].x, x[q + 1].y);
+        } else if constexpr (lds_swizzled(LAY) && NS % 8 == 0) {
+            // q NS leaves bits 1-2 alone, so slot(base + q NS) = (base ^ mask) + q NS
+            const int base = (b - k) * R + k;
+#pragma unroll
+            for (int q = 0; q < R; ++q) buf[(base ^ lds_swizzle_mask(LAY, base + q * NS, key)) + q * NS] = x[q];
         } else {
             const int base = (b - k) * R + k;
 #pragma unroll
-            for (int q = 0; q < R; ++q) buf[lds_pad(L, base + q * NS)] = x[q];
+            for (int q = 0; q < R; ++q) buf[lds_index(LAY, base + q * NS, key)] = x[q];
         }
     }
     if constexpr (LANES_NEXT) {
@@ -735,14 +787,21 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int j, float2* line, i
         }
     } else if constexpr (!LAST) {
         __syncthreads();
+        if constexpr (lds_swizzled(LAY) && T % 32 == 0) {
+            // T t is a multiple of 32: one swizzled base, constant offsets
+            const int rb = lds_index(LAY, j, key);
 #pragma unroll
-        for (int t = 0; t < P; ++t) v[t] = buf[lds_pad(L, j + T * t)];
+            for (int t = 0; t < P; ++t) v[t] = buf[rb + T * t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < P; ++t) v[t] = buf[lds_index(LAY, j + T * t, key)];
+        }
         // With one buffer the next stage's writes must wait for every read;
         // with two they go to the other buffer, whose last reads finished
         // before the barrier above.
         if constexpr (NBUF == 1) __syncthreads();
-        fft_stage<L, P, NS * R, (NS > 1 ? OFF + M * (R - 1) : OFF), INV, NBUF, PAR ^ 1, SW>(v, j, line,
-                                                                                         stride, tw);
+        fft_stage<L, P, NS * R, (NS > 1 ? OFF + M * (R - 1) : OFF), INV, NBUF, PAR ^ 1, SW, LAY>(v, j, line,
+                                                                                              stride, tw, key);
     }
 }
 
@@ -813,14 +872,14 @@ __device__ __forceinline__ void fft_line_lds(float2 (&v)[P], int j, float2* a, f
 // kernel must pass PAR = the parity after the previous one
 // (fft_parity_after, with the same SW) so that the buffers keep alternating.
 // SW: see fft_stage.
-template <int L, int P, bool INV, int NBUF, int PAR, bool SW = false>
+template <int L, int P, bool INV, int NBUF, int PAR, bool SW = false, int LAY = lds_layout(L)>
 __device__ __forceinline__ void fft_line(float2 (&v)[P], int j, float2* line, int stride,
-                                         const LineTwiddles<L, P>& tw) {
+                                         const LineTwiddles<L, P>& tw, int key = 0) {
     if constexpr (lds_mode(L)) {
         static_assert(NBUF == 2, "LDS mode ping-pongs between two buffers");
         fft_line_lds<L, P, INV>(v, j, line, line + stride, tw);
     } else {
-        fft_stage<L, P, 1, 0, INV, NBUF, PAR, SW>(v, j, line, stride, tw);
+        fft_stage<L, P, 1, 0, INV, NBUF, PAR, SW, LAY>(v, j, line, stride, tw, key);
     }
 }
 

@@ -130,7 +130,6 @@ template <int L, int PP = points_per_thread(L)>
 struct LineShape {
     static constexpr int P = PP;                    // points per thread (radix schedule)
     static constexpr int T = L / P;                 // threads per line
-    static constexpr int LP = lds_line_len(L);      // padded LDS line
 };
 
 // Column pass over G columns: G / kC adjacent strips starting at strip
@@ -145,13 +144,13 @@ struct LineShape {
 // lanes i + 64 k / Q (k < Q) of a wave hold rows j + k T / Q of one column,
 // 16 / Q rows per lane group and column, so the plan runs its last FFT stage
 // across lanes.
-template <int H, int P, int G, int MODE, bool SW = false, int NBMAX = 2>
+template <int H, int P, int G, int MODE, bool SW = false, int NBMAX = 2, int LAY = lds_layout(H)>
 __device__ __forceinline__ void col_body(const ColParams& a, int first, double* part_slot,
                                          float2* lds, double* red) {
     constexpr int T = LineShape<H, P>::T;
     constexpr int NT = G * T;
-    constexpr int LP = LineShape<H, P>::LP;
-    using LD = LdsPlan<H, G, NBMAX>;
+    using LD = LdsPlan<H, G, NBMAX, LAY>;
+    constexpr int LP = LD::LP;
     static_assert(G % kC == 0 || G == 2, "whole strips, or half a strip, per work-group");
 
     const int tid = threadIdx.x;
@@ -221,9 +220,15 @@ __device__ __forceinline__ void col_body(const ColParams& a, int first, double* 
         for (int t = 0; t < P; ++t) v[t] = *tiled(a.X, t);
     }
     float2* line = lds + (sl * kC + c - c0) * LP;
+    // Layout scheme 5 (whole strips, lines 4 mod 16 elements apart) needs no
+    // per-column key: the swizzle alone puts the four columns' accesses of a
+    // wave on disjoint banks in each exchange.
+    constexpr int key = 0;
+    static_assert(LAY / 64 != 5 || (G == kC && LP % 16 == 4), "swizzled columns: whole strips, lines 4 mod 16 apart");
 
     constexpr int PAR1 = (MODE & C_FWD) != 0 ? fft_parity_after<H, P, 0, SW>() : 0;
-    if constexpr ((MODE & C_FWD) != 0) fft_line<H, P, false, LD::NBUF, 0, SW>(v, j, line, LD::STRIDE, tw);
+    if constexpr ((MODE & C_FWD) != 0)
+        fft_line<H, P, false, LD::NBUF, 0, SW, LAY>(v, j, line, LD::STRIDE, tw, key);
 
     // Per-thread partial of this pass's FP64 sum (Fourier error or loss);
     // reduced at the very end, after the stores, into one partial per
@@ -281,7 +286,8 @@ __device__ __forceinline__ void col_body(const ColParams& a, int first, double* 
         }
     }
 
-    if constexpr ((MODE & C_INV) != 0) fft_line<H, P, true, LD::NBUF, PAR1, SW>(v, j, line, LD::STRIDE, tw);
+    if constexpr ((MODE & C_INV) != 0)
+        fft_line<H, P, true, LD::NBUF, PAR1, SW, LAY>(v, j, line, LD::STRIDE, tw, key);
 
     if constexpr ((MODE & COUT_TILED) != 0) {
 #pragma unroll
@@ -305,15 +311,15 @@ __device__ __forceinline__ void col_body(const ColParams& a, int first, double* 
 // lane_group(W, P), lanes i + 64 k / Q (k < Q) of a wave hold threads
 // j + k T / Q of one row (jhi + k T / (4 Q)), 16 / (Q G) strips per lane
 // group, so the plan runs its last FFT stage across lanes.
-template <int W, int P, int G, int MODE, bool SW = false, int NBMAX = 2>
+template <int W, int P, int G, int MODE, bool SW = false, int NBMAX = 2, int LAY = lds_layout(W)>
 __device__ __forceinline__ void row_body(const RowParams& a, int row0, const float* phase_in,
                                          float* phase_out, double* part_slot, float2* lds,
                                          double* red) {
     constexpr int T = LineShape<W, P>::T;
     constexpr int NT = G * T;
-    constexpr int LP = LineShape<W, P>::LP;
     static_assert(T % kC == 0, "row threads must cover whole strips");
-    using LD = LdsPlan<W, G, NBMAX>;
+    using LD = LdsPlan<W, G, NBMAX, LAY>;
+    constexpr int LP = LD::LP;
 
     const int tid = threadIdx.x;
     int c, rho, jhi;
@@ -384,9 +390,16 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
         for (int t = 0; t < P; ++t) *tiled(a.Z, t) = v[t];
     }
     float2* line = lds + rho * LP;
+    // Swizzle key of this row's LDS line (layout scheme 4, two-row tiles:
+    // the second row lies 8 mod 16 elements further and flips bit 1 of every
+    // index, so in each exchange the two rows' accesses of a wave fall on
+    // disjoint banks).
+    const int key = (LAY / 64 == 4 && rho != 0) ? 2 : 0;
+    static_assert(LAY / 64 != 4 || (G == 2 && LP % 16 == 8), "swizzled rows: two-row tiles, lines 8 mod 16 apart");
 
     constexpr int PAR1 = (MODE & R_INV) != 0 ? fft_parity_after<W, P, 0, SW>() : 0;
-    if constexpr ((MODE & R_INV) != 0) fft_line<W, P, true, LD::NBUF, 0, SW>(v, j, line, LD::STRIDE, tw);
+    if constexpr ((MODE & R_INV) != 0)
+        fft_line<W, P, true, LD::NBUF, 0, SW, LAY>(v, j, line, LD::STRIDE, tw, key);
 
     // Per-thread gap partial; reduced at the very end (see col_body).
     double acc = 0.0;
@@ -474,7 +487,7 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
         }
     }
     if constexpr ((MODE & R_FWD) != 0) {
-        fft_line<W, P, false, LD::NBUF, PAR1, SW>(v, j, line, LD::STRIDE, tw);
+        fft_line<W, P, false, LD::NBUF, PAR1, SW, LAY>(v, j, line, LD::STRIDE, tw, key);
 #pragma unroll
         for (int t = 0; t < P; ++t) store_shared(tiled(a.X, t), v[t]);
     }
@@ -487,9 +500,9 @@ template <int H, int MODE, int G = col_lines(H)>
 __global__ void __launch_bounds__(G * LineShape<H>::T)
 k_col(ColParams a) {
     constexpr int NT = G * LineShape<H>::T;
-    __shared__ float2 lds[LdsPlan<H, G>::FLOATS2];
+    __shared__ __align__(16) float2 lds[LdsPlan<H, G, 2, col_lds_layout(H)>::FLOATS2];
     __shared__ double red[red_slots(NT)];
-    col_body<H, LineShape<H>::P, G, MODE, col_lanes_ok(H, LineShape<H>::P, G)>(
+    col_body<H, LineShape<H>::P, G, MODE, col_lanes_ok(H, LineShape<H>::P, G), 2, col_lds_layout(H)>(
         a, pass_tile<G>(blockIdx.x, gridDim.x), a.part + blockIdx.x * red_slots(NT), lds, red);
 }
 
@@ -505,7 +518,7 @@ template <int W, int MODE, int G = row_lines(W)>
 __global__ void __launch_bounds__(G * LineShape<W>::T)
 k_row(RowParams a) {
     constexpr int NT = G * LineShape<W>::T;
-    __shared__ float2 lds[LdsPlan<W, G>::FLOATS2];
+    __shared__ __align__(16) float2 lds[LdsPlan<W, G, 2, row_lds_layout(W)>::FLOATS2];
     __shared__ double red[red_slots(NT)];
     const float* pin = nullptr;
     float* pout = nullptr;
@@ -513,7 +526,7 @@ k_row(RowParams a) {
     if constexpr ((MODE & ROUT_PHASE) != 0) pout = a.io->phase_out;
     if constexpr ((MODE & RIN_FIELD) != 0) a.nat_in = a.io->field_in;
     if constexpr ((MODE & ROUT_FIELD) != 0) a.nat_out = a.io->field_out;
-    row_body<W, LineShape<W>::P, G, field_as_nat(MODE), row_lanes_ok(W, LineShape<W>::P, G)>(
+    row_body<W, LineShape<W>::P, G, field_as_nat(MODE), row_lanes_ok(W, LineShape<W>::P, G), 2, row_lds_layout(W)>(
         a, pass_tile<G>(blockIdx.x, gridDim.x) * G, pin, pout, a.part + blockIdx.x * red_slots(NT), lds, red);
 }
 
@@ -524,7 +537,7 @@ template <int W, int MODE>
 __global__ void __launch_bounds__(row_lines(W) * LineShape<W>::T)
 k_row_adj(AdjParams p) {
     constexpr int NT = row_lines(W) * LineShape<W>::T;
-    __shared__ float2 lds[LdsPlan<W, row_lines(W)>::FLOATS2];
+    __shared__ __align__(16) float2 lds[LdsPlan<W, row_lines(W), 2, row_lds_layout(W)>::FLOATS2];
     __shared__ double red[red_slots(NT)];
     const size_t n = (size_t)p.H * W;
     const size_t b = blockIdx.y;
@@ -537,9 +550,9 @@ k_row_adj(AdjParams p) {
         a.gscale = (float)(4.0 * p.grad_loss[b] / (double)n);
         out = p.grad + b * n;
     }
-    row_body<W, LineShape<W>::P, row_lines(W), MODE, row_lanes_ok(W, LineShape<W>::P, row_lines(W))>(
-        a, pass_tile<row_lines(W)>(blockIdx.x, gridDim.x) * row_lines(W), p.phase + b * n, out, nullptr, lds,
-        red);
+    row_body<W, LineShape<W>::P, row_lines(W), MODE, row_lanes_ok(W, LineShape<W>::P, row_lines(W)), 2,
+             row_lds_layout(W)>(a, pass_tile<row_lines(W)>(blockIdx.x, gridDim.x) * row_lines(W), p.phase + b * n,
+                                out, nullptr, lds, red);
 }
 
 template <int H>

@@ -61,6 +61,24 @@ void lds_line(int L) {
     }
 }
 
+// The one-mask passes' layouts (row_lds_layout, col_lds_layout; schemes 4
+// and 5 swizzle each line with a per-line key): one to one into the line,
+// 16-byte pairs kept together, for every key a pass can use (0, 2, 4, 6).
+void pass_lds_line(int L, int lay) {
+    const int LP = pm::lds_line_len_lay(L, lay);
+    const int keys[] = {0, 2, 4, 6};
+    for (int key : keys) {
+        if (key != 0 && lay / 64 < 4) continue;
+        std::vector<int> hit(LP, 0);
+        for (int i = 0; i < L; ++i) {
+            const int a = pm::lds_index(lay, i, key);
+            check(a >= 0 && a < LP, "pass LDS index inside the line", L, i, a);
+            if (a >= 0 && a < LP) check(++hit[a] == 1, "pass LDS index one to one", L, i, a);
+            if ((i & 1) == 0) check(pm::lds_index(lay, i + 1, key) == a + 1, "16-byte pairs kept together", L, i);
+        }
+    }
+}
+
 // Static LDS of the one-mask pass kernels (exchange buffers and FP64
 // reduction slots) within the 160 KiB of a CU.
 template <int L>
@@ -68,8 +86,10 @@ void lds_budget() {
     constexpr int T = pm::LineShape<L>::T;
     constexpr int budget = 160 * 1024;
     constexpr int gc = pm::col_lines(L), gr = pm::row_lines(L);
-    check(pm::LdsPlan<L, gc>::FLOATS2 * 8 + pm::red_slots(gc * T) * 8 <= budget, "column pass LDS", L, gc);
-    check(pm::LdsPlan<L, gr>::FLOATS2 * 8 + pm::red_slots(gr * T) * 8 <= budget, "row pass LDS", L, gr);
+    check(pm::LdsPlan<L, gc, 2, pm::col_lds_layout(L)>::FLOATS2 * 8 + pm::red_slots(gc * T) * 8 <= budget,
+          "column pass LDS", L, gc);
+    check(pm::LdsPlan<L, gr, 2, pm::row_lds_layout(L)>::FLOATS2 * 8 + pm::red_slots(gr * T) * 8 <= budget,
+          "row pass LDS", L, gr);
     if constexpr (pm::row_lines_alt(L) != 0) {
         constexpr int ga = pm::row_lines_alt(L);
         check(pm::LdsPlan<L, ga>::FLOATS2 * 8 + pm::red_slots(ga * T) * 8 <= budget, "taller row tile LDS", L, ga);
@@ -134,7 +154,12 @@ int main() {
     check(pm::row_lines(1024) == 2 && pm::row_lines(4096) == 2 && pm::row_lines(64) == 4 &&
               pm::row_lines(1920) == 4 && pm::row_lines(600) == 4 && pm::row_lines(1080) == 4,
           "row tile heights");
-    for (int L : lengths) lds_line(L);
+    for (int L : lengths) {
+        lds_line(L);
+        pass_lds_line(L, pm::row_lds_layout(L));
+        pass_lds_line(L, pm::col_lds_layout(L));
+        if (L == 1024) pass_lds_line(L, 5 * 64 + 4);  // the column swizzle the build knob selects
+    }
     lds_budget<16>(); lds_budget<32>(); lds_budget<64>(); lds_budget<128>(); lds_budget<256>();
     lds_budget<512>(); lds_budget<1024>(); lds_budget<2048>(); lds_budget<4096>();
     lds_budget<600>(); lds_budget<800>(); lds_budget<1080>(); lds_budget<1920>();
