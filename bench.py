@@ -23,6 +23,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # Algorithmic bytes per pixel of one launch (see the design notes):
 COL_BYTES_PER_PX = 8 + 8 + 4   # read iterate, write iterate, read rescaled target
 ROW_BYTES_PER_PX = 8 + 8       # read iterate, write iterate
+# One Adam step on the intensity loss: loss row pass (phase 4, saved 8),
+# loss column pass (saved 8 + 8, intensity 4), gradient row pass (saved 8,
+# phase 4, gradient 4), fused Adam (phase, gradient, two moments read, phase
+# and moments written: 28).
+ADAM_STEP_BYTES_PER_PX = 12 + 20 + 16 + 28
+# The library's Adam solve, per step: loss column pass (transform 8 + 8,
+# tiled intensity 4) and the Adam row pass (transform 8 in and out, phase
+# and both moments in and out: 8 + 8 + 24).
+ADAM_FUSED_BYTES_PER_PX = 20 + 40
 
 # Measured HBM/MALL traffic per launch (rocprofv3 FETCH_SIZE x 1.9992 +
 # WRITE_SIZE x 1.0, factors from a plain 64 MiB copy; summary under profiles/),
@@ -320,9 +329,9 @@ def bench_next_rows(torch, binding, synth, m, phi0, plan_steps=10, reps=100):
 
 def bench_adjoint(torch, binding, synth, lr, steps=200):
     """16 x 512^2 phases, 50-spot intensity targets I = m^2 scaled to sum N:
-    200 Adam steps on the intensity loss (forward and adjoint kernels) versus
-    200 GS iterations on the amplitude m = sqrt(I), compared by the
-    Fourier-plane error E_F of the resulting masks."""
+    200 Adam steps on the intensity loss versus 200 GS iterations on the
+    amplitude m = sqrt(I), compared by the Fourier-plane error E_F of the
+    resulting masks."""
     import numpy as np
     batch, n = 16, 512
     it_np, ph_np = synth.intensity_problems(batch=batch, size=n, n_spots=50)
@@ -339,28 +348,33 @@ def bench_adjoint(torch, binding, synth, lr, steps=200):
         _, e = bp.solve(m_list, [phases[b] for b in range(batch)], 0)
         return e
 
-    # Adam on the intensity loss (PyTorch's fused single-kernel Adam update;
-    # the step is bound by launches from the host)
-    p = ph0.clone().requires_grad_(True)
-    opt = torch.optim.Adam([p], lr=lr, fused=True)
-
-    def adam_step():
-        opt.zero_grad(set_to_none=True)
-        loss = binding.intensity_loss(p, it_d).sum()
-        loss.backward()
-        opt.step()
-    adam_step()  # warm-up (plan creation, optimizer state)
-    with torch.no_grad():
-        p.copy_(ph0)
-    opt = torch.optim.Adam([p], lr=lr, fused=True)
+    # Adam on the intensity loss, three ways: the library's Adam solve (two
+    # fused passes per step, the whole run one graph replay), and PyTorch's
+    # fused Adam on the library's loss and adjoint kernels, recorded into a
+    # graph per step and run eagerly.
+    plan_a = binding.PhaseMask(n, n, device=dev)
+    out_a = torch.empty_like(ph0)
+    plan_a.solve_adam(it_d, ph0, steps, lr, out=out_a)  # capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        adam_step()
+    _, loss_hist = plan_a.solve_adam(it_d, ph0, steps, lr, out=out_a)
     torch.cuda.synchronize()
     t_adam = time.perf_counter() - t0
-    ef_adam = ef_of(p.detach()).mean().item()
 
+    def torch_adam_run(capture):
+        p = ph0.clone().requires_grad_(True)
+        st = binding.AdamIntensityStep(p, it_d, lr=lr, capture=capture)  # warms up, then resets
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st.step()
+        torch.cuda.synchronize()
+        return p, time.perf_counter() - t0
+    p_eager, t_torch_eager = torch_adam_run(False)
+    p_graph, t_torch_graph = torch_adam_run(True)
+    assert torch.equal(p_graph, p_eager), "captured and eager Adam runs differ"
+    ef_adam = ef_of(out_a).mean().item()
+    ef_torch = ef_of(p_graph.detach()).mean().item()
     # GS on the amplitudes, same initial phases, batched
     outs = [torch.empty((n, n), dtype=torch.float32, device=dev) for _ in range(batch)]
     phs = [ph0[b] for b in range(batch)]
@@ -383,7 +397,15 @@ def bench_adjoint(torch, binding, synth, lr, steps=200):
     return {
         "workload": "16 x 512^2 phases, 50-spot intensity targets (seeds 500+b), sum I = N",
         "adam": {"steps": steps, "lr": lr, "ms_per_step": t_adam * 1e3 / steps,
-                 "total_ms": t_adam * 1e3, "final_fourier_error_mean": ef_adam},
+                 "total_ms": t_adam * 1e3, "final_fourier_error_mean": ef_adam,
+                 "final_loss_mean": float(loss_hist[-1].mean().item()),
+                 "launch": "phasemask_solve_adam: one graph, 2 fused passes per step",
+                 "algorithmic_gbs": ADAM_FUSED_BYTES_PER_PX * batch * n * n / (t_adam / steps) / 1e9,
+                 "torch_adam": {"graph_ms_per_step": t_torch_graph * 1e3 / steps,
+                                "eager_ms_per_step": t_torch_eager * 1e3 / steps,
+                                "final_fourier_error_mean": ef_torch,
+                                "algorithmic_gbs": ADAM_STEP_BYTES_PER_PX * batch * n * n
+                                / (t_torch_graph / steps) / 1e9}},
         "gs": {"iterations": steps, "total_ms": t_gs * 1e3, "final_fourier_error_mean": ef_gs},
         "gs_iterations_to_adam_error": nu_equal,
         "gs_ms_to_adam_error": (t_gs * 1e3 * nu_equal / steps) if nu_equal is not None else None,

@@ -380,6 +380,48 @@ pm_status phasemask_intensity_loss_bwd(pm_handle h, int batch, const float* phas
                                        float* grad_phase);
 
 /*
+ * Gradient-based phase optimisation beside GS (not in the paper; its Sec. V
+ * notes that other reconstruction methods plug into the same framework):
+ * n_steps of Adam (Kingma and Ba 2015, Algorithm 1) on the intensity loss
+ * of phasemask_intensity_loss_fwd, for `batch` phases of height x width at
+ * once.  From m = v = 0, step k = 1 .. n_steps on each sample:
+ *   g   = d loss / d phi at phi^{k-1}  (the intensity-loss adjoint),
+ *   m   = beta1 m + (1 - beta1) g,   v = beta2 v + (1 - beta2) g^2,
+ *   phi^k = phi^{k-1} - (lr / (1 - beta1^k)) m / (sqrt(v) / sqrt(1 - beta2^k) + eps),
+ * elementwise in FP32 (bias corrections in double, rounded once).  Each step
+ * is two fused passes: the loss column pass (forward column transform,
+ * residual, loss partials, inverse column transform) and a row pass that
+ * runs the inverse row transform, the gradient, the update and the forward
+ * row transform of exp(i phi^k).
+ *   target_intensity  float[batch][height][width], I >= 0, natural DFT order,
+ *                     on the scale of |F e^{i phi}|^2 with unitary F (sums
+ *                     to N when matched in energy).
+ *   init_phase        float[batch][height][width], radians.
+ *   n_steps           >= 0.
+ *   lr, beta1, beta2, eps   lr > 0 and finite; beta1, beta2 in [0, 1);
+ *                     eps > 0 and finite.
+ *   out_phase         float[batch][height][width] receiving phi^{n_steps};
+ *                     may alias init_phase; must not overlap the target.
+ *   loss_history      NULL, or double[(n_steps + 1) * batch]: entry
+ *                     k * batch + b = loss of sample b at phi^k (FP64,
+ *                     deterministic).
+ * The three float arrays must be 16-byte aligned (history 8).  The plan
+ * keeps the Adam state (24 bytes per pixel and sample, allocated on first
+ * use for the largest batch seen, which synchronises the stream and drops
+ * the captured graphs).  The illumination of phasemask_set_illumination does
+ * not apply (the loss is that of exp(i phi)).  Without PM_FLAG_NO_GRAPH the
+ * solve is one captured graph per (n_steps, batch, history, lr, beta1,
+ * beta2, eps), like phasemask_solve.
+ * Errors: PM_EINVAL for a NULL array, batch outside [1, 65535], n_steps < 0,
+ * a hyper-parameter out of range, misalignment or overlapping arrays;
+ * PM_ENOMEM; PM_EDEVICE.
+ */
+pm_status phasemask_solve_adam(pm_handle h, int batch, const float* target_intensity,
+                               const float* init_phase, int n_steps, double lr,
+                               double beta1, double beta2, double eps,
+                               float* out_phase, double* loss_history);
+
+/*
  * Measurement (roofline accounting of the two passes that run n_iter times,
  * Eq. 6): average device duration in milliseconds of one column pass
  * (forward column FFT, Eq. 5 projection, inverse column FFT) and of one row

@@ -266,3 +266,30 @@ def intensity_loss_grad(phi: np.ndarray, target_intensity: np.ndarray) -> np.nda
     r = np.abs(U) ** 2 - np.asarray(target_intensity, dtype=np.float64)
     g = F_inv(r * U)
     return 4.0 * np.imag(np.conj(u) * g)
+
+
+def adam_intensity(phi0: np.ndarray, target_intensity: np.ndarray, n_steps: int, lr: float,
+                   beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> dict:
+    """n_steps of Adam on intensity_loss from phi0, in FP64.
+
+    Not in the paper: gradient-based phase optimisation beside the
+    projection method.  Adam as published by Kingma and Ba (2015,
+    Algorithm 1): from m = v = 0, at step t = 1, 2, ...
+        g = grad L(theta),  m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+        m_hat = m / (1 - beta1^t),  v_hat = v / (1 - beta2^t),
+        theta = theta - lr m_hat / (sqrt(v_hat) + eps).
+    Returns the final phase and the losses [L(phi^0), ..., L(phi^n)]."""
+    phi = np.asarray(phi0, dtype=np.float64).copy()
+    it = np.asarray(target_intensity, dtype=np.float64)
+    m = np.zeros_like(phi)
+    v = np.zeros_like(phi)
+    losses = [intensity_loss(phi, it)]
+    for t in range(1, n_steps + 1):
+        g = intensity_loss_grad(phi, it)
+        m = beta1 * m + (1.0 - beta1) * g
+        v = beta2 * v + (1.0 - beta2) * g * g
+        m_hat = m / (1.0 - beta1 ** t)
+        v_hat = v / (1.0 - beta2 ** t)
+        phi = phi - lr * m_hat / (np.sqrt(v_hat) + eps)
+        losses.append(intensity_loss(phi, it))
+    return {"phi": phi, "losses": np.array(losses)}

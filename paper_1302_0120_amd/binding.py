@@ -45,6 +45,9 @@ _SIGNATURES = {
     "phasemask_intensity_loss_bwd": (ctypes.c_int, [_c_handle, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                                     ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_batch_schedule": (ctypes.c_int, [_c_handle]),
+    "phasemask_solve_adam": (ctypes.c_int, [_c_handle, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_initial_phase": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
     "phasemask_physical_error": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                                 ctypes.c_double, ctypes.c_void_p]),
@@ -291,6 +294,25 @@ class PhaseMask:
                "phasemask_intensity_loss_bwd")
         return grad
 
+    def solve_adam(self, target_intensity: torch.Tensor, init_phase: torch.Tensor, n_steps: int, lr: float,
+                   betas=(0.9, 0.999), eps: float = 1e-8, out: torch.Tensor | None = None,
+                   history: bool = True):
+        """n_steps of Adam on the intensity loss for phases [B][H][W] (or
+        [H][W]); returns (phase, losses [n_steps + 1][B] float64 or None)."""
+        b = init_phase.shape[0] if init_phase.dim() == 3 else 1
+        shp = (b, *self.shape) if init_phase.dim() == 3 else self.shape
+        ip = _dev_ptr(target_intensity, torch.float32, shp, "target_intensity")
+        pp = _dev_ptr(init_phase, torch.float32, shp, "init_phase")
+        if out is None:
+            out = torch.empty(shp, dtype=torch.float32, device=self.device)
+        op = _dev_ptr(out, torch.float32, shp, "out")
+        hist = torch.empty((int(n_steps) + 1, b), dtype=torch.float64, device=self.device) if history else None
+        self._stream()
+        _check(lib.phasemask_solve_adam(self._h, b, ip, pp, int(n_steps), float(lr), float(betas[0]),
+                                        float(betas[1]), float(eps), op, 0 if hist is None else hist.data_ptr()),
+               "phasemask_solve_adam")
+        return out, hist
+
     def time_passes(self, target: torch.Tensor, phase: torch.Tensor, reps: int = 100):
         """(column-pass ms, row-pass ms): average kernel durations over `reps`
         iterations, from events recorded by the launches themselves."""
@@ -431,6 +453,72 @@ class IntensityLoss(torch.autograd.Function):
 
 def intensity_loss(phase: torch.Tensor, target_intensity: torch.Tensor) -> torch.Tensor:
     return IntensityLoss.apply(phase, target_intensity)
+
+
+class AdamIntensityStep:
+    """Gradient-based phase optimisation on the intensity loss: one step is
+    the per-sample losses loss_b = intensity_loss(phase_b, I_b), the
+    gradient of sum_b loss_b (the adjoint kernel with unit upstream
+    gradients, as autograd would pass them) and a fused Adam update of
+    `phase` (a leaf float32 tensor with requires_grad, [B][H][W] or [H][W]).
+
+    The step runs on a plan of its own, so nothing else can regrow the
+    buffers it uses.  `warmup` eager steps first size the plan's partial
+    sums and create the optimizer state; they are then undone (phase and
+    optimizer state restored).  With capture=True they run on the step's own
+    stream (so nothing inside the graph allocates through the library or
+    switches streams), and the whole step (loss, gradient, Adam) is then
+    recorded once into a graph on that stream: every step() replays it, so a
+    step costs device time only.  Step k of a captured run equals step k of
+    an eager one, bitwise.  step() returns the step's per-sample losses (a tensor the
+    graph rewrites on each replay); phase.grad holds the step's gradient."""
+
+    def __init__(self, phase: torch.Tensor, target_intensity: torch.Tensor, lr: float,
+                 betas=(0.9, 0.999), eps: float = 1e-8, capture: bool = True, warmup: int = 2):
+        if not (phase.is_leaf and phase.requires_grad and phase.is_cuda and phase.dtype == torch.float32):
+            raise ValueError("phase must be a float32 device leaf tensor with requires_grad")
+        if not phase.is_contiguous():
+            raise ValueError("phase must be contiguous")
+        self.phase = phase
+        self.target = target_intensity.contiguous()
+        batch = phase.shape[0] if phase.dim() == 3 else 1
+        self.plan = PhaseMask(phase.shape[-2], phase.shape[-1], device=phase.device)
+        self.ones = torch.ones(batch, dtype=torch.float64, device=phase.device)
+        self.opt = torch.optim.Adam([phase], lr=lr, betas=betas, eps=eps, fused=True, capturable=True)
+        self.graph = None
+        self.loss = None
+        cur = torch.cuda.current_stream(phase.device)
+        self.stream = torch.cuda.Stream(device=phase.device) if capture else cur
+        start = phase.detach().clone()
+        self.stream.wait_stream(cur)
+        with torch.cuda.stream(self.stream):
+            for _ in range(warmup):
+                self._eager()
+            with torch.no_grad():
+                phase.copy_(start)
+            for st in self.opt.state.values():
+                for v in st.values():
+                    if isinstance(v, torch.Tensor):
+                        v.zero_()
+        cur.wait_stream(self.stream)
+        if capture:
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph, stream=self.stream):
+                self.loss = self._eager()
+
+    def _eager(self):
+        with torch.no_grad():
+            p = self.phase.detach()
+            loss, saved = self.plan.intensity_loss_fwd(p, self.target)
+            self.phase.grad = self.plan.intensity_loss_bwd(p, saved, self.ones)
+        self.opt.step()
+        return loss
+
+    def step(self) -> torch.Tensor:
+        if self.graph is None:
+            return self._eager()
+        self.graph.replay()
+        return self.loss
 
 
 def solve(target: torch.Tensor, init_phase: torch.Tensor, n_iter: int, history: bool = True):

@@ -58,7 +58,7 @@ int len_slot(int n) {
 }
 
 using AdjRowLauncher = hipError_t (*)(int, const pm::AdjParams&, int, hipStream_t);
-using AdjColLauncher = hipError_t (*)(const pm::AdjParams&, int, hipStream_t);
+using AdjColLauncher = hipError_t (*)(int, const pm::AdjParams&, int, hipStream_t);
 const AdjRowLauncher kAdjRow[13] = {pm::launch_adj_row_16,   pm::launch_adj_row_32,   pm::launch_adj_row_64,
                                     pm::launch_adj_row_128,  pm::launch_adj_row_256,  pm::launch_adj_row_512,
                                     pm::launch_adj_row_1024, pm::launch_adj_row_2048, pm::launch_adj_row_4096,
@@ -85,11 +85,23 @@ const ColLauncher kColLaunch[13] = {pm::launch_col_16,   pm::launch_col_32,   pm
                                     pm::launch_col_600,  pm::launch_col_800,
     pm::launch_col_1080, pm::launch_col_1920};
 
+// What a captured solve graph was recorded for (its kernel arguments bake
+// in the iteration count, the algorithm and its scalars).
+struct SolveKey {
+    int n_iter = 0;
+    bool hist = false;
+    int algo = 0;        // kAlgoGS, kAlgoRAAR, kAlgoGSField, kAlgoAdam
+    float beta = 0.0f;   // RAAR relaxation
+    int batch = 0;       // Adam: samples
+    double lr = 0.0, beta1 = 0.0, beta2 = 0.0, eps = 0.0;  // Adam
+    bool operator==(const SolveKey& o) const {
+        return n_iter == o.n_iter && hist == o.hist && algo == o.algo && beta == o.beta && batch == o.batch &&
+               lr == o.lr && beta1 == o.beta1 && beta2 == o.beta2 && eps == o.eps;
+    }
+};
+
 struct GraphEntry {
-    int n_iter;
-    bool hist;
-    int algo;      // 0 = alternating projections, 1 = RAAR
-    float beta;    // RAAR relaxation (part of the captured kernel arguments)
+    SolveKey key;
     hipGraphExec_t exec;
 };
 
@@ -153,6 +165,15 @@ struct pm_plan {
     // the partials; the plan then owns none of the three.
     bool ws_borrowed = false;
     hipEvent_t order_ev = nullptr;     // orders the handle's work across a stream switch
+    // Adam solves (phasemask_solve_adam), allocated for adam_cap samples on
+    // first use: the transform buffer, working phase, moments (natural
+    // layout) and the strip-tiled intensity.
+    int adam_cap = 0;
+    float2* a_saved = nullptr;
+    float* a_phase = nullptr;
+    float* a_m = nullptr;
+    float* a_v = nullptr;
+    float* a_inten = nullptr;
     // Device address of the allocation-free solve's scratch array on the
     // plan's device (looked up at create), or null with the lookup's error.
     unsigned char* scratch = nullptr;
@@ -217,6 +238,11 @@ void free_plan(pm_plan* h) {
     (void)hipFree(h->pw);
     (void)hipFree(h->Z);
     (void)hipFree(h->illum);
+    (void)hipFree(h->a_saved);
+    (void)hipFree(h->a_phase);
+    (void)hipFree(h->a_m);
+    (void)hipFree(h->a_v);
+    (void)hipFree(h->a_inten);
     (void)hipFree(h->pn2);
     (void)hipFree(h->vflags);
     (void)hipFree(h->io);
@@ -363,6 +389,7 @@ enum : int {
     kAlgoGS = 0,       // alternating projections, phases in and out
     kAlgoRAAR = 1,     // RAAR, phases in and out
     kAlgoGSField = 2,  // alternating projections, complex fields in and out
+    kAlgoAdam = 3,     // Adam on the intensity loss, phases in and out
 };
 
 // The whole solve after the pointer block is set: target preparation,
@@ -438,11 +465,19 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int al
 }
 
 pm_status enqueue_batch(pm_plan* h, hipStream_t s, int n_iter, bool err);
+pm_status enqueue_adam(pm_plan* h, hipStream_t s, const SolveKey& k);
+
+// The whole sequence of one solve, as the key describes it.
+pm_status enqueue_key(pm_plan* h, hipStream_t s, const SolveKey& k) {
+    if (h->batched) return enqueue_batch(h, s, k.n_iter, k.hist);
+    if (k.algo == kAlgoAdam) return enqueue_adam(h, s, k);
+    return enqueue_solve(h, s, k.n_iter, k.hist, k.algo, k.beta);
+}
 
 // Replays (capturing on first use) the graph of one solve shape.
-pm_status launch_graph(pm_plan* h, int n_iter, bool hist, int algo = kAlgoGS, float beta = 0.0f) {
+pm_status launch_graph(pm_plan* h, const SolveKey& key) {
     for (auto it = h->graphs.begin(); it != h->graphs.end(); ++it) {
-        if (it->n_iter == n_iter && it->hist == hist && it->algo == algo && it->beta == beta) {
+        if (it->key == key) {
             h->graphs.splice(h->graphs.begin(), h->graphs, it);
             PM_TRY(hipGraphLaunch(it->exec, h->stream), "hipGraphLaunch");
             return PM_OK;
@@ -450,8 +485,7 @@ pm_status launch_graph(pm_plan* h, int n_iter, bool hist, int algo = kAlgoGS, fl
     }
     hipGraph_t graph = nullptr;
     PM_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    pm_status st = h->batched ? enqueue_batch(h, h->cap_stream, n_iter, hist)
-                              : enqueue_solve(h, h->cap_stream, n_iter, hist, algo, beta);
+    pm_status st = enqueue_key(h, h->cap_stream, key);
     hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
     if (st != PM_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -466,9 +500,18 @@ pm_status launch_graph(pm_plan* h, int n_iter, bool hist, int algo = kAlgoGS, fl
         (void)hipGraphExecDestroy(h->graphs.back().exec);
         h->graphs.pop_back();
     }
-    h->graphs.push_front(GraphEntry{n_iter, hist, algo, beta, exec});
+    h->graphs.push_front(GraphEntry{key, exec});
     PM_TRY(hipGraphLaunch(exec, h->stream), "hipGraphLaunch");
     return PM_OK;
+}
+
+pm_status launch_graph(pm_plan* h, int n_iter, bool hist, int algo = kAlgoGS, float beta = 0.0f) {
+    SolveKey k;
+    k.n_iter = n_iter;
+    k.hist = hist;
+    k.algo = algo;
+    k.beta = beta;
+    return launch_graph(h, k);
 }
 
 // ----- batched solves ----------------------------------------------------------
@@ -1414,7 +1457,7 @@ pm_status phasemask_intensity_loss_fwd(pm_handle h, int batch, const float* phas
     p.nwg = h->slots_adj;
     hipStream_t s = h->stream;
     PM_TRY(kAdjRow[len_slot(h->W)](pm::ROW_INIT, p, batch, s), "loss row pass");
-    PM_TRY(kAdjCol[len_slot(h->H)](p, batch, s), "loss column pass");
+    PM_TRY(kAdjCol[len_slot(h->H)](pm::COL_LOSS, p, batch, s), "loss column pass");
     PM_TRY(pm::launch_sum_rows(h->part, h->slots_adj, loss, batch, s), "loss sum");
     return PM_OK;
 }
@@ -1439,6 +1482,133 @@ pm_status phasemask_intensity_loss_bwd(pm_handle h, int batch, const float* phas
     p.nwg = h->slots_adj;
     PM_TRY(kAdjRow[len_slot(h->W)](pm::ROW_GRAD, p, batch, h->stream), "gradient row pass");
     return PM_OK;
+}
+
+// ----- Adam solves on the intensity loss -------------------------------------
+
+// The whole Adam solve after the pointer block is set: set-up, the row
+// transform of exp(i phi^0), then per step the loss column pass (loss of
+// phi^{k-1}, residual-weighted field back through the inverse column
+// transform) and the Adam row pass (inverse row transform, gradient, update
+// to phi^k, forward row transform of exp(i phi^k)); with a history, the loss
+// of phi^n and the fixed-order sums; finally the phase to the caller.
+namespace {
+
+pm_status enqueue_adam(pm_plan* h, hipStream_t s, const SolveKey& k) {
+    const int batch = k.batch, n = k.n_iter;
+    PM_TRY(pm::launch_adam_prep(h->io, h->H, h->W, batch, h->a_phase, h->a_inten, h->a_m, h->a_v, s),
+           "Adam set-up");
+    pm::AdjParams p{};
+    p.saved = h->a_saved;
+    p.phase = h->a_phase;
+    p.grad = h->a_phase;  // the update is in place
+    p.inten = h->a_inten;
+    p.part = h->part;
+    p.twW = h->twW;
+    p.twH = h->twH;
+    p.H = h->H;
+    p.W = h->W;
+    p.nwg = h->slots_adj;
+    p.am = h->a_m;
+    p.av = h->a_v;
+    p.beta1 = (float)k.beta1;
+    p.beta2 = (float)k.beta2;
+    p.eps = (float)k.eps;
+    const AdjRowLauncher row = kAdjRow[len_slot(h->W)];
+    const AdjColLauncher col = kAdjCol[len_slot(h->H)];
+    if (n > 0 || k.hist) PM_TRY(row(pm::ROW_INIT, p, batch, s), "Adam row init");
+    for (int step = 1; step <= n; ++step) {
+        p.part_row0 = k.hist ? (step - 1) * batch : 0;
+        PM_TRY(col(pm::COL_LOSS_T, p, batch, s), "Adam loss column pass");
+        // bias corrections of step k (evaluated in double, rounded once)
+        p.adam_step = (float)(k.lr / (1.0 - std::pow(k.beta1, (double)step)));
+        p.adam_bc2s = (float)std::sqrt(1.0 - std::pow(k.beta2, (double)step));
+        const int mode = (step < n || k.hist) ? pm::ROW_ADAM : pm::ROW_ADAM_LAST;
+        PM_TRY(row(mode, p, batch, s), "Adam row pass");
+    }
+    if (k.hist) {
+        p.part_row0 = n * batch;
+        PM_TRY(col(pm::COL_LOSS_ONLY_T, p, batch, s), "Adam final loss");
+        PM_TRY(pm::launch_sum_rows_io(h->part, h->slots_adj, h->io, (n + 1) * batch, s), "Adam loss sums");
+    }
+    PM_TRY(pm::launch_adam_out(h->io, h->a_phase, (size_t)batch * h->N, s), "Adam output");
+    return PM_OK;
+}
+
+}  // namespace
+
+pm_status phasemask_solve_adam(pm_handle h, int batch, const float* target_intensity, const float* init_phase,
+                               int n_steps, double lr, double beta1, double beta2, double eps, float* out_phase,
+                               double* loss_history) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    if (!target_intensity || !init_phase || !out_phase) return fail(PM_EINVAL, "null array argument");
+    if (batch < 1 || batch > 65535) return fail(PM_EINVAL, "batch must be in [1, 65535]");
+    if (n_steps < 0) return fail(PM_EINVAL, "n_steps must be >= 0");
+    if (!(lr > 0.0 && std::isfinite(lr))) return fail(PM_EINVAL, "lr must be positive and finite");
+    if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0))
+        return fail(PM_EINVAL, "beta1 and beta2 must be in [0, 1)");
+    if (!(eps > 0.0 && std::isfinite(eps))) return fail(PM_EINVAL, "eps must be positive and finite");
+    if (misaligned(target_intensity, 16) || misaligned(init_phase, 16) || misaligned(out_phase, 16) ||
+        misaligned(loss_history, 8))
+        return fail(PM_EINVAL, "target_intensity, init_phase and out_phase must be 16-byte aligned");
+    const size_t nb = (size_t)batch * h->N * sizeof(float);
+    if (overlaps(out_phase, nb, target_intensity, nb)) return fail(PM_EINVAL, "out_phase overlaps the target");
+    const size_t hb = ((size_t)n_steps + 1) * batch * sizeof(double);
+    if (loss_history && (overlaps(loss_history, hb, target_intensity, nb) || overlaps(loss_history, hb, out_phase, nb) ||
+                         overlaps(loss_history, hb, init_phase, nb)))
+        return fail(PM_EINVAL, "loss_history overlaps an array");
+    if (h->adam_cap < batch) {
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+        drop_graphs(h);  // captured graphs hold the old buffers
+        const size_t n = (size_t)batch * h->N;
+        float2* sv = nullptr;
+        float *ph = nullptr, *m = nullptr, *v = nullptr, *it = nullptr;
+        e = hipMalloc(&sv, n * sizeof(float2));
+        if (e == hipSuccess) e = hipMalloc(&ph, n * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&m, n * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&v, n * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&it, n * sizeof(float));
+        if (e != hipSuccess) {
+            (void)hipFree(sv);
+            (void)hipFree(ph);
+            (void)hipFree(m);
+            (void)hipFree(v);
+            (void)hipFree(it);
+            return fail_hip(e, "hipMalloc(Adam state)");
+        }
+        const size_t old = (size_t)h->adam_cap * h->N * (sizeof(float2) + 4 * sizeof(float));
+        (void)hipFree(h->a_saved);
+        (void)hipFree(h->a_phase);
+        (void)hipFree(h->a_m);
+        (void)hipFree(h->a_v);
+        (void)hipFree(h->a_inten);
+        h->a_saved = sv;
+        h->a_phase = ph;
+        h->a_m = m;
+        h->a_v = v;
+        h->a_inten = it;
+        h->ws_bytes += n * (sizeof(float2) + 4 * sizeof(float)) - old;
+        h->adam_cap = batch;
+    }
+    const bool hist = loss_history != nullptr;
+    const size_t rows = hist ? ((size_t)n_steps + 1) * batch : (size_t)batch;
+    st = ensure_partials(h, (rows * h->slots_adj + h->stride - 1) / h->stride);
+    if (st != PM_OK) return st;
+    pm::PmIo io{target_intensity, init_phase, out_phase, loss_history};
+    PM_TRY(pm::launch_set_io(h->io, io, h->stream), "set io");
+    SolveKey k;
+    k.n_iter = n_steps;
+    k.hist = hist;
+    k.algo = kAlgoAdam;
+    k.batch = batch;
+    k.lr = lr;
+    k.beta1 = beta1;
+    k.beta2 = beta2;
+    k.eps = eps;
+    if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_adam(h, h->stream, k);
+    return launch_graph(h, k);
 }
 
 pm_status phasemask_initial_phase(pm_handle h, const float* target_amplitude, double t_dark, float* out_phase) {

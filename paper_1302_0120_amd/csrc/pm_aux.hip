@@ -288,6 +288,66 @@ hipError_t launch_sum_rows(const double* part, int nwg, double* out, int count, 
     return hipGetLastError();
 }
 
+// k_sum_rows into io->hist (read through the per-call pointer block).
+__global__ void __launch_bounds__(kAuxThreads) k_sum_rows_io(const double* part, int nwg, const PmIo* io) {
+    __shared__ double red[red_slots(kAuxThreads)];
+    const double* p = part + (size_t)blockIdx.x * nwg;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nwg; i += kAuxThreads) acc += p[i];
+    const double tot = block_sum<kAuxThreads>(acc, red);
+    if (threadIdx.x == 0) io->hist[blockIdx.x] = tot;
+}
+
+hipError_t launch_sum_rows_io(const double* part, int nwg, const PmIo* io, int count, hipStream_t s) {
+    k_sum_rows_io<<<count, kAuxThreads, 0, s>>>(part, nwg, io);
+    return hipGetLastError();
+}
+
+// ----- Adam solves on the intensity loss ----------------------------------------
+
+// Set-up over batch x H x W pixels, one thread per 4 adjacent pixels of a
+// row (W is a multiple of 4): the working phase (natural layout) from
+// io->phase_in, the intensity io->target into the strip-tiled layout (a
+// strip row of kC = 4 pixels is one float4), and zero moments.
+__global__ void __launch_bounds__(kAuxThreads)
+k_adam_prep(const PmIo* io, int H, int W, int batch, float* phase, float* inten, float* m, float* v) {
+    const size_t q = (size_t)blockIdx.x * kAuxThreads + threadIdx.x;  // float4 index
+    const size_t per = (size_t)H * (W / 4);
+    if (q >= per * (size_t)batch) return;
+    const size_t b = q / per;
+    const size_t r = q % per;
+    const int y = (int)(r / (W / 4));
+    const int s4 = (int)(r % (W / 4));  // strip index (4 columns)
+    const size_t n = (size_t)H * W;
+    const float4 ph = reinterpret_cast<const float4*>(io->phase_in + b * n)[(size_t)y * (W / 4) + s4];
+    const float4 it = reinterpret_cast<const float4*>(io->target + b * n)[(size_t)y * (W / 4) + s4];
+    reinterpret_cast<float4*>(phase + b * n)[(size_t)y * (W / 4) + s4] = ph;
+    reinterpret_cast<float4*>(inten + b * n)[(size_t)s4 * H + y] = it;
+    const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    reinterpret_cast<float4*>(m + b * n)[(size_t)y * (W / 4) + s4] = z;
+    reinterpret_cast<float4*>(v + b * n)[(size_t)y * (W / 4) + s4] = z;
+}
+
+hipError_t launch_adam_prep(const PmIo* io, int H, int W, int batch, float* phase, float* inten, float* m,
+                            float* v, hipStream_t s) {
+    const size_t quads = (size_t)batch * H * (W / 4);
+    const unsigned grid = (unsigned)((quads + kAuxThreads - 1) / kAuxThreads);
+    k_adam_prep<<<grid, kAuxThreads, 0, s>>>(io, H, W, batch, phase, inten, m, v);
+    return hipGetLastError();
+}
+
+// io->phase_out = phase, n floats (n a multiple of 4).
+__global__ void __launch_bounds__(kAuxThreads) k_adam_out(const PmIo* io, const float* phase, size_t n4) {
+    const size_t q = (size_t)blockIdx.x * kAuxThreads + threadIdx.x;
+    if (q < n4) reinterpret_cast<float4*>(io->phase_out)[q] = reinterpret_cast<const float4*>(phase)[q];
+}
+
+hipError_t launch_adam_out(const PmIo* io, const float* phase, size_t n, hipStream_t s) {
+    const size_t n4 = n / 4;
+    k_adam_out<<<(unsigned)((n4 + kAuxThreads - 1) / kAuxThreads), kAuxThreads, 0, s>>>(io, phase, n4);
+    return hipGetLastError();
+}
+
 // ----- physical error (Eq. 8) and target maxima -------------------------------
 
 __global__ void __launch_bounds__(kAuxThreads) k_max_partial(const float* x, int n, float* part) {

@@ -59,6 +59,8 @@ enum : int {
     R_ILLUM = 4096,   // illumination amplitude p of Eq. 1 on S (else p = 1)
     RIN_FIELD = 8192,   // read the natural-layout complex field io->field_in (as RIN_NAT)
     ROUT_FIELD = 16384, // write the natural-layout complex field to io->field_out (as ROUT_NAT)
+    R_ADAM = 32768,     // intensity-loss gradient, Adam update of the phase (and with R_FWD the
+                        // row FFT of exp(i phase) of the updated phase)
 };
 constexpr int ROW_INIT = RIN_PHASE | R_FWD;
 constexpr int ROW_ITER = RIN_TILED | R_INV | R_PS | R_FWD;
@@ -84,6 +86,10 @@ constexpr int ROW_LAST_FIELD = RIN_TILED | R_INV | R_PS | ROUT_FIELD;
 constexpr int ROW_LAST_FIELD_FWD = RIN_TILED | R_INV | R_PS | ROUT_FIELD | R_FWD;
 constexpr int ROW_LAST_FIELD_NE = ROW_LAST_FIELD | R_NOERR;
 constexpr int ROW_COPY_FIELD = RIN_FIELD | ROUT_FIELD;  // u^n = u^0 (no iterations)
+// Adam steps on the intensity loss: the row pass of step k (gradient of
+// phi^{k-1}, update to phi^k, and the forward row transform for step k + 1).
+constexpr int ROW_ADAM = RIN_TILED | R_INV | R_ADAM | R_FWD;
+constexpr int ROW_ADAM_LAST = RIN_TILED | R_INV | R_ADAM;
 
 // Column-pass modes (bit sets).
 enum : int {
@@ -99,6 +105,7 @@ enum : int {
     C_LOSS = 512,     // intensity residual r = |U|^2/N - I, loss partials, U <- r U
     C_BIT = 1024,     // load the 1-bit target pattern (lit where m^2 / max m^2 > t_dark)
     C_POW = 2048,     // store |U|^2 / N (float, strip-tiled) and the work-group maximum
+    C_ITILED = 4096,  // C_LOSS: the target intensity is strip-tiled (else natural layout)
 };
 constexpr int COL_ITER = CIN_TILED | C_FWD | C_PROJ | C_INV | COUT_TILED;
 constexpr int COL_ERR = CIN_TILED | C_FWD | C_ERR;
@@ -108,6 +115,10 @@ constexpr int COL_ITER_NE = COL_ITER | C_NOERR;
 constexpr int COL_LOSS = CIN_TILED | C_FWD | C_LOSS | C_INV | COUT_TILED;
 constexpr int COL_INIT_BIT = C_BIT | C_INV | COUT_TILED;
 constexpr int COL_POW = CIN_TILED | C_FWD | C_POW;
+// Adam steps: the loss column pass on a strip-tiled intensity, and the loss
+// of the final phase alone.
+constexpr int COL_LOSS_T = COL_LOSS | C_ITILED;
+constexpr int COL_LOSS_ONLY_T = CIN_TILED | C_FWD | C_LOSS | C_ITILED;
 
 struct RowParams {
     float2* X;             // tiled iterate
@@ -122,6 +133,11 @@ struct RowParams {
     float beta;            // R_RAAR: relaxation parameter
     const float* illum;    // R_ILLUM: illumination amplitude p, strip-tiled (float per pixel)
     int spread;            // launch at most one work-group per CU (grid fits the CUs)
+    // R_ADAM: first and second moments (natural layout) and the step's
+    // scalars: lr / (1 - beta1^k), sqrt(1 - beta2^k), beta1, beta2, eps
+    float* am;
+    float* av;
+    float adam_step, adam_bc2s, beta1, beta2, eps;
 };
 
 struct ColParams {
@@ -146,13 +162,18 @@ struct ColParams {
 struct AdjParams {
     float2* saved;              // [batch][N] tiled work buffer, kept from forward to backward
     const float* phase;         // [batch][H][W]
-    const float* inten;         // [batch][H][W] target intensity
-    float* grad;                // [batch][H][W] gradient (backward)
+    const float* inten;         // [batch][H][W] target intensity (strip-tiled with C_ITILED)
+    float* grad;                // [batch][H][W] gradient (backward); updated phase (R_ADAM)
     const double* grad_loss;    // [batch] upstream gradient of each sample's loss (backward)
-    double* part;               // [batch][nwg] loss partials (forward), nwg slots per sample
+    double* part;               // loss partials: row part_row0 + b of nwg slots per sample
     const float2* twW;
     const float2* twH;
     int H, W, nwg;
+    int part_row0;
+    // R_ADAM: moments [batch][H][W] and the step's scalars (as RowParams)
+    float* am;
+    float* av;
+    float adam_step, adam_bc2s, beta1, beta2, eps;
 };
 
 // Launchers, one pair per supported transform length (powers of two 16 ..
@@ -168,7 +189,7 @@ struct AdjParams {
                               hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 #define PM_DECLARE_ADJ_LAUNCHERS(L)                                                              \
     hipError_t launch_adj_row_##L(int mode, const AdjParams& p, int batch, hipStream_t s);  \
-    hipError_t launch_adj_col_##L(const AdjParams& p, int batch, hipStream_t s);
+    hipError_t launch_adj_col_##L(int mode, const AdjParams& p, int batch, hipStream_t s);
 PM_DECLARE_ADJ_LAUNCHERS(16)
 PM_DECLARE_ADJ_LAUNCHERS(32)
 PM_DECLARE_ADJ_LAUNCHERS(64)
@@ -303,5 +324,13 @@ hipError_t launch_physical_error(const float* pw, const double* pw_max_part, int
                                  double* scratch, double* out, hipStream_t s);
 // out[b] = sum of part[b * nwg .. b * nwg + nwg) in a fixed order, b < count.
 hipError_t launch_sum_rows(const double* part, int nwg, double* out, int count, hipStream_t s);
+// The same into io->hist (the per-call pointer block).
+hipError_t launch_sum_rows_io(const double* part, int nwg, const PmIo* io, int count, hipStream_t s);
+// Adam solve set-up over `batch` samples of H x W: phase = io->phase_in,
+// inten (strip-tiled) = io->target, moments m = v = 0.
+hipError_t launch_adam_prep(const PmIo* io, int H, int W, int batch, float* phase, float* inten, float* m,
+                            float* v, hipStream_t s);
+// io->phase_out = phase over batch x H x W floats.
+hipError_t launch_adam_out(const PmIo* io, const float* phase, size_t n, hipStream_t s);
 
 }  // namespace pm

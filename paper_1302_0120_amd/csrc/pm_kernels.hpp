@@ -278,7 +278,7 @@ __device__ __forceinline__ void col_body(const ColParams& a, int first, double* 
         // 1/sqrt(N) factors are folded into the gradient scale.
 #pragma unroll
         for (int t = 0; t < P; ++t) {
-            const float I = *natural(a.inten, t);
+            const float I = (MODE & C_ITILED) != 0 ? *tiled(a.inten, t) : *natural(a.inten, t);
             const float2 U = v[t];
             const float r = fmaf(fmaf(U.x, U.x, U.y * U.y), (float)a.invN, -I);
             acc = fma((double)r, (double)r, acc);
@@ -486,6 +486,37 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
             *natural(phase_out, t) = a.gscale * fmaf(cs, v[t].y, -(sn * v[t].x));
         }
     }
+    if constexpr ((MODE & R_ADAM) != 0) {
+        // v = unnormalised inverse of r U, as for ROUT_GRAD: the gradient of
+        // the intensity loss is g = 4 Im(e^{-i phi} F^H(r U)) (scale folded
+        // into gscale).  Adam (Kingma and Ba, Algorithm 1) on each pixel:
+        //   m <- beta1 m + (1 - beta1) g,   v <- beta2 v + (1 - beta2) g^2,
+        //   phi <- phi - (lr / (1 - beta1^k)) m / (sqrt(v) / sqrt(1 - beta2^k) + eps),
+        // then (R_FWD) exp(i phi) of the new phase feeds the forward row
+        // transform of the next step.
+        const float omb1 = 1.0f - a.beta1;
+        const float omb2 = 1.0f - a.beta2;
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+            float sn, cs;
+            const float ph = *natural(phase_in, t);
+            sincosf(ph, &sn, &cs);
+            const float g = a.gscale * fmaf(cs, v[t].y, -(sn * v[t].x));
+            float* mp = natural(a.am, t);
+            float* vp = natural(a.av, t);
+            const float m1 = fmaf(a.beta1, *mp, omb1 * g);
+            const float v1 = fmaf(a.beta2, *vp, omb2 * (g * g));
+            const float denom = sqrtf(v1) / a.adam_bc2s + a.eps;
+            const float ph1 = ph - (a.adam_step * m1) / denom;
+            *mp = m1;
+            *vp = v1;
+            *natural(phase_out, t) = ph1;
+            if constexpr ((MODE & R_FWD) != 0) {
+                sincosf(ph1, &sn, &cs);
+                v[t] = make_float2(cs, sn);
+            }
+        }
+    }
     if constexpr ((MODE & R_FWD) != 0) {
         fft_line<W, P, false, LD::NBUF, PAR1, SW, LAY>(v, j, line, LD::STRIDE, tw, key);
 #pragma unroll
@@ -532,7 +563,9 @@ k_row(RowParams a) {
 
 // Intensity-loss kernels over a batch of same-size phases, sample = blockIdx.y.
 // Forward: ROW_INIT (exp(i phi), row FFT) then the column kernel (COL_LOSS).
-// Backward: ROW_GRAD.
+// Backward: ROW_GRAD.  Adam steps: the column kernel (COL_LOSS_T) then
+// ROW_ADAM, whose phase input and output are both p.phase / p.grad (the
+// caller passes the same buffer: the update is in place).
 template <int W, int MODE>
 __global__ void __launch_bounds__(row_lines(W) * LineShape<W>::T)
 k_row_adj(AdjParams p) {
@@ -550,12 +583,35 @@ k_row_adj(AdjParams p) {
         a.gscale = (float)(4.0 * p.grad_loss[b] / (double)n);
         out = p.grad + b * n;
     }
+    if constexpr ((MODE & R_ADAM) != 0) {
+        // the gradient of the sample's own loss (unit upstream gradient),
+        // the phase updated in place
+        a.gscale = (float)(4.0 / (double)n);
+        out = p.grad + b * n;
+        a.am = p.am + b * n;
+        a.av = p.av + b * n;
+        a.adam_step = p.adam_step;
+        a.adam_bc2s = p.adam_bc2s;
+        a.beta1 = p.beta1;
+        a.beta2 = p.beta2;
+        a.eps = p.eps;
+    }
     row_body<W, LineShape<W>::P, row_lines(W), MODE, row_lanes_ok(W, LineShape<W>::P, row_lines(W)), 2,
              row_lds_layout(W)>(a, pass_tile<row_lines(W)>(blockIdx.x, gridDim.x) * row_lines(W), p.phase + b * n,
                                 out, nullptr, lds, red);
 }
 
-template <int H>
+// Strip of loss column work-group x of `nx`: work-groups are dealt to the 8
+// XCDs in turn, so with nx a multiple of 8 this gives XCD k the contiguous
+// strips [k nx / 8, (k + 1) nx / 8).  The natural-layout intensity is read
+// 16 bytes per row per strip; adjacent strips on one XCD then share each
+// 128-byte line through that XCD's L2 instead of every XCD fetching whole
+// lines for a quarter of their bytes.
+__host__ __device__ __forceinline__ int xcd_strip(int x, int nx) {
+    return (nx % 8 == 0) ? (x % 8) * (nx / 8) + x / 8 : x;
+}
+
+template <int H, int MODE>
 __global__ void __launch_bounds__(kC * LineShape<H>::T)
 k_col_adj(AdjParams p) {
     constexpr int NT = kC * LineShape<H>::T;
@@ -569,8 +625,9 @@ k_col_adj(AdjParams p) {
     a.W = p.W;
     a.invN = 1.0 / (double)n;
     a.inten = p.inten + b * n;
-    col_body<H, LineShape<H>::P, kC, COL_LOSS, col_lanes_ok(H, LineShape<H>::P, kC)>(
-        a, blockIdx.x, p.part + b * p.nwg + blockIdx.x * red_slots(NT), lds, red);
+    const int strip = xcd_strip(blockIdx.x, gridDim.x);
+    col_body<H, LineShape<H>::P, kC, MODE, col_lanes_ok(H, LineShape<H>::P, kC)>(
+        a, strip, p.part + (size_t)(p.part_row0 + b) * p.nwg + strip * red_slots(NT), lds, red);
 }
 
 }  // namespace pm

@@ -110,14 +110,21 @@ hipError_t PM_CAT(launch_adj_row_, PM_L)(int mode, const AdjParams& p, int batch
     switch (mode) {
         case ROW_INIT: k_row_adj<PM_L, ROW_INIT><<<grid, block, 0, s>>>(p); break;
         case ROW_GRAD: k_row_adj<PM_L, ROW_GRAD><<<grid, block, 0, s>>>(p); break;
+        case ROW_ADAM: k_row_adj<PM_L, ROW_ADAM><<<grid, block, 0, s>>>(p); break;
+        case ROW_ADAM_LAST: k_row_adj<PM_L, ROW_ADAM_LAST><<<grid, block, 0, s>>>(p); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t PM_CAT(launch_adj_col_, PM_L)(const AdjParams& p, int batch, hipStream_t s) {
+hipError_t PM_CAT(launch_adj_col_, PM_L)(int mode, const AdjParams& p, int batch, hipStream_t s) {
     const dim3 grid(p.W / kC, batch), block(kC * LineShape<PM_L>::T);
-    k_col_adj<PM_L><<<grid, block, 0, s>>>(p);
+    switch (mode) {
+        case COL_LOSS: k_col_adj<PM_L, COL_LOSS><<<grid, block, 0, s>>>(p); break;
+        case COL_LOSS_T: k_col_adj<PM_L, COL_LOSS_T><<<grid, block, 0, s>>>(p); break;
+        case COL_LOSS_ONLY_T: k_col_adj<PM_L, COL_LOSS_ONLY_T><<<grid, block, 0, s>>>(p); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

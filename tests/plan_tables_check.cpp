@@ -154,6 +154,16 @@ int main() {
     check(pm::row_lines(1024) == 2 && pm::row_lines(4096) == 2 && pm::row_lines(64) == 4 &&
               pm::row_lines(1920) == 4 && pm::row_lines(600) == 4 && pm::row_lines(1080) == 4,
           "row tile heights");
+    // the loss column pass's strip map: a bijection, contiguous strips per XCD
+    for (int nx : {4, 16, 128, 150, 256, 1024}) {
+        std::vector<int> hit(nx, 0);
+        for (int x = 0; x < nx; ++x) {
+            const int s = pm::xcd_strip(x, nx);
+            check(s >= 0 && s < nx, "strip map in range", nx, x, s);
+            if (s >= 0 && s < nx) check(++hit[s] == 1, "strip map one to one", nx, x, s);
+            if (nx % 8 == 0) check(s / (nx / 8) == x % 8, "XCD x % 8 takes a contiguous run of strips", nx, x);
+        }
+    }
     for (int L : lengths) {
         lds_line(L);
         pass_lds_line(L, pm::row_lds_layout(L));

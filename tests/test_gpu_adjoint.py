@@ -129,3 +129,120 @@ def test_intensity_workload_16x512(pmb):
     for b in (0, 7, 15):
         ref_g = gs.intensity_loss_grad(ph[b], it[b])
         assert np.linalg.norm(grad[b] - ref_g) / np.linalg.norm(ref_g) <= 1e-4, b
+
+
+def test_captured_adam_step_equals_eager(pmb):
+    """The Adam step on the intensity loss recorded into a graph: every
+    replay gives bitwise the losses, gradient and updated phases of the same
+    step run eagerly (replays separated by other eager work and
+    synchronisations); the first step's gradient is the autograd
+    Function's."""
+    batch, n, steps = 4, 256, 5
+    it, ph = _targets(batch, n, 90)
+    it_d = torch.from_numpy(it).cuda()
+    print(f"captured Adam step {batch} x {n}^2", flush=True)
+    p_e = torch.from_numpy(ph).cuda().requires_grad_(True)
+    eager = pmb.AdamIntensityStep(p_e, it_d, lr=0.05, capture=False)
+    ref = []
+    for _ in range(steps):
+        loss = eager.step().clone()
+        ref.append((loss, p_e.grad.clone(), p_e.detach().clone()))
+    # autograd path, first step's gradient
+    p_a = torch.from_numpy(ph).cuda().requires_grad_(True)
+    pmb.intensity_loss(p_a, it_d).sum().backward()
+    p_c = torch.from_numpy(ph).cuda().requires_grad_(True)
+    cap = pmb.AdamIntensityStep(p_c, it_d, lr=0.05, capture=True)
+    assert cap.graph is not None
+    for k in range(steps):
+        loss = cap.step()
+        torch.cuda.synchronize()
+        side = torch.randn(1 << 20, device="cuda").sum()  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(side)
+        l_ref, g_ref, p_ref = ref[k]
+        same = (torch.equal(loss, l_ref), torch.equal(p_c.grad, g_ref), torch.equal(p_c.detach(), p_ref))
+        print(f"replay {k}: loss/grad/phase equal {same}", flush=True)
+        assert all(same), k
+        if k == 0:
+            assert torch.equal(p_c.grad, p_a.grad)
+    assert float(ref[-1][0].sum()) < float(ref[0][0].sum())
+
+
+def test_adam_solve_vs_oracle(pmb):
+    """phasemask_solve_adam against the FP64 oracle's Adam (pinned on the CPU
+    against torch's Adam and the first-step closed form).  One step: where
+    the oracle gradient is not near zero (|g| > 1e-2 of its RMS; elsewhere
+    an FP32 gradient may differ in sign and Adam's first step is lr sign(g)),
+    the phase within 2e-6 rad.  Ten steps: the loss history within 1e-4
+    relative (an aggregate over all pixels, like the full-run error bound)."""
+    batch, n, lr = 2, 64, 0.05
+    it, ph = _targets(batch, n, 120)
+    plan = pmb.PhaseMask(n, n)
+    it_d, ph_d = torch.from_numpy(it).cuda(), torch.from_numpy(ph).cuda()
+    phi1, h1 = plan.solve_adam(it_d, ph_d, 1, lr)
+    phi10, h10 = plan.solve_adam(it_d, ph_d, 10, lr)
+    phi1, h1, h10 = phi1.cpu().numpy(), h1.cpu().numpy(), h10.cpu().numpy()
+    worst_step, worst_loss = 0.0, 0.0
+    for b in range(batch):
+        g = gs.intensity_loss_grad(ph[b], it[b])
+        ref1 = gs.adam_intensity(ph[b], it[b], 1, lr)
+        ok = np.abs(g) > 1e-2 * np.sqrt(np.mean(g * g))
+        assert ok.mean() > 0.95
+        worst_step = max(worst_step, float(np.max(np.abs(phi1[b].astype(np.float64) - ref1["phi"])[ok])))
+        ref10 = gs.adam_intensity(ph[b], it[b], 10, lr)
+        worst_loss = max(worst_loss, float(np.max(np.abs(h10[:, b] - ref10["losses"]) / ref10["losses"])))
+        assert abs(h1[0, b] - ref1["losses"][0]) / ref1["losses"][0] <= 1e-5
+    print(f"Adam solve vs oracle: first step max |dphi| {worst_step:.2e} rad, "
+          f"10-step loss history worst rel diff {worst_loss:.2e}", flush=True)
+    assert worst_step <= 2e-6
+    assert worst_loss <= 1e-4
+
+
+def test_adam_solve_matches_torch_adam_step_and_graph(pmb):
+    """The fused step computes the same gradient as the adjoint entry points
+    (bitwise), and its Adam update agrees with PyTorch's fused Adam given that
+    gradient to FP32 rounding; graph replay and eager launches, and repeated
+    solves, are bitwise equal; zero steps return the input."""
+    batch, n, lr = 3, 128, 0.03
+    it, ph = _targets(batch, n, 130)
+    it_d, ph_d = torch.from_numpy(it).cuda(), torch.from_numpy(ph).cuda()
+    plan = pmb.PhaseMask(n, n)
+    eager = pmb.PhaseMask(n, n, flags=pmb.PM_FLAG_NO_GRAPH)
+    a, ha = plan.solve_adam(it_d, ph_d, 7, lr)
+    a, ha = a.clone(), ha.clone()
+    b_, hb = plan.solve_adam(it_d, ph_d, 7, lr)
+    c, hc = eager.solve_adam(it_d, ph_d, 7, lr)
+    assert torch.equal(a, b_) and torch.equal(ha, hb)
+    assert torch.equal(a, c) and torch.equal(ha, hc)
+    z, hz = plan.solve_adam(it_d, ph_d, 0, lr)
+    assert torch.equal(z, ph_d)
+    loss0, saved = plan.intensity_loss_fwd(ph_d, it_d)
+    assert torch.equal(hz[0], loss0) and torch.equal(ha[0], loss0)
+    # one step against PyTorch's Adam on the adjoint gradient
+    p = ph_d.clone().requires_grad_(True)
+    step = pmb.AdamIntensityStep(p, it_d, lr=lr, capture=False)
+    step.step()
+    one, _ = plan.solve_adam(it_d, ph_d, 1, lr)
+    d = (one - p.detach()).abs().max().item()
+    print(f"Adam solve vs torch Adam, one step: max |dphi| {d:.2e} rad", flush=True)
+    assert d <= 4 * 2.0 ** -21  # a few float ulps at |phi| < 2 pi (+ lr)
+    # in place: out aliasing the input
+    buf = ph_d.clone()
+    same, _ = plan.solve_adam(it_d, buf, 7, lr, out=buf, history=False)
+    assert same.data_ptr() == buf.data_ptr() and torch.equal(buf, a)
+
+
+def test_adam_solve_workload_16x512(pmb):
+    """The 16 x 512^2 intensity workload, 200 Adam steps in one call: finite,
+    the loss falls for every sample, and the first history row is the loss
+    of the initial phases (bitwise that of the loss entry point)."""
+    it_np, ph_np = synth.intensity_problems(batch=16, size=512, n_spots=50)
+    it_np = (it_np.astype(np.float64) * (512 * 512 / it_np.astype(np.float64).sum(axis=(1, 2), keepdims=True)))
+    it_d = torch.from_numpy(it_np.astype(np.float32)).cuda()
+    ph_d = torch.from_numpy(ph_np).cuda()
+    plan = pmb.PhaseMask(512, 512)
+    out, hist = plan.solve_adam(it_d, ph_d, 200, 0.1)
+    assert torch.isfinite(out).all() and torch.isfinite(hist).all()
+    loss0, _ = plan.intensity_loss_fwd(ph_d, it_d)
+    assert torch.equal(hist[0], loss0)
+    assert bool((hist[-1] < 0.5 * hist[0]).all()), hist[[0, -1]]

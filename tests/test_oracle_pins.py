@@ -530,3 +530,53 @@ def test_start_from_a_field():
     assert abs(b["history"][0] - np.linalg.norm(2.0 * np.abs(U) - mt) / math.sqrt(n)) <= 1e-12
     with pytest.raises(ValueError):
         gs.gs_solve(m, phi, 1, u0=np.exp(1j * phi))
+
+
+def _adam_problem(n=16, seed=77):
+    rng = np.random.default_rng(seed)
+    y, x = np.mgrid[0:n, 0:n]
+    m = np.zeros((n, n))
+    for cy, cx in rng.uniform(n / 4, 3 * n / 4, (3, 2)):
+        m += np.exp(-((y - cy) ** 2 + (x - cx) ** 2) / (2 * 1.5 ** 2))
+    it = m * m
+    it *= n * n / it.sum()
+    phi0 = rng.uniform(0.0, 2.0 * np.pi, (n, n))
+    return it, phi0
+
+
+def test_adam_first_step_closed_form():
+    """Adam's bias corrections make the first step lr g / (|g| + eps) in
+    every coordinate (Kingma and Ba, Sec. 2: m_hat = g, v_hat = g^2 at t = 1)."""
+    it, phi0 = _adam_problem()
+    lr, eps = 0.05, 1e-8
+    g = gs.intensity_loss_grad(phi0, it)
+    out = gs.adam_intensity(phi0, it, 1, lr, eps=eps)
+    assert np.max(np.abs(out["phi"] - (phi0 - lr * g / (np.abs(g) + eps)))) <= 1e-15
+    # with eps far below |g| every coordinate moves by lr against its gradient
+    big = np.abs(g) > 1e3 * eps
+    assert big.mean() > 0.9
+    assert np.allclose(np.abs(out["phi"] - phi0)[big], lr, rtol=1e-6, atol=0)
+
+
+def test_adam_matches_torch_adam_in_fp64():
+    """An independent implementation (torch.optim.Adam, float64 on the CPU)
+    fed the oracle's gradients gives the oracle's trajectory."""
+    torch = pytest.importorskip("torch")
+    it, phi0 = _adam_problem(seed=78)
+    lr, b1, b2, eps, steps = 0.03, 0.9, 0.99, 1e-6, 6
+    p = torch.tensor(phi0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=lr, betas=(b1, b2), eps=eps)
+    for _ in range(steps):
+        opt.zero_grad()
+        p.grad = torch.tensor(gs.intensity_loss_grad(p.detach().numpy(), it), dtype=torch.float64)
+        opt.step()
+    out = gs.adam_intensity(phi0, it, steps, lr, b1, b2, eps)
+    assert np.max(np.abs(out["phi"] - p.detach().numpy())) <= 1e-12
+    assert out["losses"].shape == (steps + 1,)
+    assert out["losses"][0] == gs.intensity_loss(phi0, it)
+
+
+def test_adam_reduces_the_loss():
+    it, phi0 = _adam_problem(seed=79)
+    out = gs.adam_intensity(phi0, it, 40, 0.02)
+    assert out["losses"][-1] < 0.8 * out["losses"][0]
