@@ -22,6 +22,7 @@
 
 #include "pm_common.h"
 #include "pm_fft.hpp"
+#include "pm_plan.h"
 
 namespace {
 
@@ -256,28 +257,6 @@ pm_status check_handle(pm_plan* h, bool batched = false) {
     if (h->batched != batched)
         return fail(PM_ESTATE, batched ? "handle is not a batched plan" : "handle is a batched plan");
     return PM_OK;
-}
-
-// Staged twiddle table of the line plan (L, P) (layout: twiddle_block in
-// pm_fft.hpp): entry (q - 1) NS + k of the stage at NS with radix R is
-// exp(-2 pi i q k / (NS R)) = exp(-2 pi i e / L) with e = q k L / (NS R) < L,
-// evaluated in double and rounded once to float.
-std::vector<float2> staged_twiddles(int L, int P) {
-    std::vector<float2> t(std::max(1, pm::twiddle_entries(L, P)), make_float2(1.0f, 0.0f));
-    const double two_pi = 6.283185307179586476925286766559;
-    for (int ns = 1; ns < L; ns *= pm::line_stage_radix(L, P, ns)) {
-        const int R = pm::line_stage_radix(L, P, ns);
-        if (ns == 1) continue;
-        const int base = pm::twiddle_block(L, P, ns);
-        for (int q = 1; q < R; ++q) {
-            for (int k = 0; k < ns; ++k) {
-                const int e = q * k * (L / (ns * R));
-                const double a = two_pi * (double)e / (double)L;
-                t[base + (q - 1) * ns + k] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
-            }
-        }
-    }
-    return t;
 }
 
 // Layout of a caller-owned workspace (phasemask_set_workspace): the iterate,
@@ -873,8 +852,8 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
     const size_t n = (size_t)h->N;
     if ((e = hipMalloc(&h->X, n * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(iterate)");
     if ((e = hipMalloc(&h->mhat, n * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc(target)");
-    const std::vector<float2> tw_w = staged_twiddles(width, pm::points_per_thread(width));
-    const std::vector<float2> tw_h = staged_twiddles(height, pm::points_per_thread(height));
+    const std::vector<float2> tw_w = pm::staged_twiddles(width, pm::points_per_thread(width));
+    const std::vector<float2> tw_h = pm::staged_twiddles(height, pm::points_per_thread(height));
     if ((e = hipMalloc(&h->twW, tw_w.size() * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
     if ((e = hipMalloc(&h->twH, tw_h.size() * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
     if ((e = hipMalloc(&h->part_m, kNormGrid * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(norm)");
@@ -1378,14 +1357,7 @@ pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights
     if ((e = hipMalloc(&h->part, npart * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(partials)");
     if ((e = hipMalloc(&h->part_m, prep.size() * sizeof(double))) != hipSuccess) return bail(e, "hipMalloc(norm)");
     if ((e = hipMalloc(&h->bio, sizeof(pm::BatchIo))) != hipSuccess) return bail(e, "hipMalloc(io)");
-    std::vector<float2> tw(pm::batch_twiddle_offset(pm::kBatchSchedules, 0));
-    for (int sc = 0; sc < pm::kBatchSchedules; ++sc) {
-        for (int l = pm::kBatchMinLen; l <= pm::kBatchMaxLen; l *= 2) {
-            const std::vector<float2> t = staged_twiddles(l, pm::batch_points(sc, l));
-            std::copy(t.begin(), t.begin() + pm::twiddle_entries(l, pm::batch_points(sc, l)),
-                      tw.begin() + pm::batch_twiddle_offset(sc, l));
-        }
-    }
+    const std::vector<float2> tw = pm::batch_twiddles();
     if ((e = hipMalloc(&h->tw_batch, tw.size() * sizeof(float2))) != hipSuccess) return bail(e, "hipMalloc(twiddles)");
     h->part_entries = 1;
     h->stride = (int)npart;

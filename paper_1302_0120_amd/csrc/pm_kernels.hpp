@@ -118,10 +118,18 @@ __host__ __device__ constexpr bool col_lanes_ok(int H, int P, int G) {
 // loads are then in that XCD's L2 for the other.  Work-groups past the last
 // multiple of 16 keep their own index, so the map is a bijection of
 // [0, nwg) for any nwg; other tile sizes use the identity.
+// With 3-row tiles, four consecutive tiles (12 rows: three whole 128-byte
+// rows of every strip) go to work-groups wg, wg + 8, wg + 16, wg + 24.
+#ifndef PM_TILE3_XCD
+#define PM_TILE3_XCD 1
+#endif
 template <int G>
 __host__ __device__ __forceinline__ int pass_tile(int wg, int nwg) {
     if constexpr (G == 2) {
         if (wg < (nwg & ~15)) return 2 * ((wg / 16) * 8 + (wg & 7)) + ((wg / 8) & 1);
+    }
+    if constexpr (G == 3 && PM_TILE3_XCD) {
+        if (wg < (nwg & ~31)) return 4 * ((wg / 32) * 8 + (wg & 7)) + ((wg / 8) & 3);
     }
     return wg;
 }

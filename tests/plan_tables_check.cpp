@@ -8,14 +8,21 @@
 //   * the batched table offsets add up schedule by schedule;
 // the cross-lane and row-tile choices are checked on known plans, the
 // row-pass work-group to tile map on a range of grid sizes, the padded LDS
-// index of every length, and the one-mask kernels' static LDS.
+// index of every length, and the one-mask kernels' static LDS.  The twiddle
+// tables the library builds (pm_plan.h) are compared with the definition
+// exp(-2 pi i q k / (NS R)) entry by entry; tests/test_plan_tables_cpu.py
+// also runs this check built with AddressSanitizer and
+// UndefinedBehaviorSanitizer on the host code.
 // Prints "ok" and exits 0, or prints the first violation and exits 1.
 #include <cstdio>
 #include <vector>
 
+#include <cmath>
+
 #include "pm_common.h"
 #include "pm_fft.hpp"
 #include "pm_kernels.hpp"
+#include "pm_plan.h"
 
 namespace {
 
@@ -79,6 +86,26 @@ void pass_lds_line(int L, int lay) {
     }
 }
 
+// The library's staged table of (L, P) against its definition, entry by
+// entry (float rounding of the double value), and every entry on the unit
+// circle.
+void twiddle_values(int L, int P) {
+    const std::vector<float2> t = pm::staged_twiddles(L, P);
+    check((int)t.size() == std::max(1, pm::twiddle_entries(L, P)), "table size", L, P);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int ns = 1; ns < L; ns *= pm::line_stage_radix(L, P, ns)) {
+        const int R = pm::line_stage_radix(L, P, ns);
+        if (ns == 1) continue;
+        for (int q = 1; q < R; ++q)
+            for (int k = 0; k < ns; ++k) {
+                const float2 w = t[pm::twiddle_block(L, P, ns) + (q - 1) * ns + k];
+                const double a = two_pi * q * k / ((double)ns * R);
+                check(std::fabs(w.x - std::cos(a)) <= 1e-7 && std::fabs(w.y + std::sin(a)) <= 1e-7,
+                      "twiddle entry is exp(-2 pi i q k / (NS R))", L, q, k);
+            }
+    }
+}
+
 // Static LDS of the one-mask pass kernels (exchange buffers and FP64
 // reduction slots) within the 160 KiB of a CU.
 template <int L>
@@ -101,6 +128,7 @@ void lds_budget() {
 int main() {
     const int lengths[] = {16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 600, 800, 1080, 1920};
     for (int L : lengths) {
+        twiddle_values(L, pm::points_per_thread(L));
         walk(L, pm::points_per_thread(L));
         check(L % pm::points_per_thread(L) == 0, "P divides L", L);
     }
@@ -113,6 +141,18 @@ int main() {
         }
     }
     check(pm::batch_twiddle_offset(pm::kBatchSchedules, 0) == off, "batched table total", off);
+    {
+        const std::vector<float2> bt = pm::batch_twiddles();
+        check((int)bt.size() == off, "batched table size", (int)bt.size(), off);
+        for (int s = 0; s < pm::kBatchSchedules; ++s)
+            for (int L = pm::kBatchMinLen; L <= pm::kBatchMaxLen; L *= 2) {
+                const std::vector<float2> t = pm::staged_twiddles(L, pm::batch_points(s, L));
+                for (int i = 0; i < pm::twiddle_entries(L, pm::batch_points(s, L)); ++i) {
+                    const float2 a = bt[pm::batch_twiddle_offset(s, L) + i];
+                    check(a.x == t[i].x && a.y == t[i].y, "batched table holds each plan's table", s, L, i);
+                }
+            }
+    }
     // cross-lane last stages: radix 2 after radix P, radix 4 after radix P
     check(pm::lane_group(1024, 8) == 2, "8-8-8-2 takes its radix-2 stage across lanes");
     check(pm::lane_group(512, 8) == 0, "8-8-8 has no last stage across lanes");
@@ -144,6 +184,20 @@ int main() {
         for (int g = 0; 2 * g + 1 < (nwg & ~15); ++g)
             check(where[2 * g] % 8 == where[2 * g + 1] % 8, "row tile halves share an XCD", nwg, g);
         check(pm::pass_tile<4>(7, nwg) == 7, "4-row tiles keep their index", nwg);
+        // 3-row tiles: a bijection, and the four tiles of every 12 rows of a
+        // whole group of 32 work-groups sit on one XCD
+        std::vector<int> seen3(nwg, 0), where3(nwg, -1);
+        for (int wg = 0; wg < nwg; ++wg) {
+            const int t = pm::pass_tile<3>(wg, nwg);
+            check(t >= 0 && t < nwg, "3-row tile in range", nwg, wg, t);
+            if (t < 0 || t >= nwg) continue;
+            ++seen3[t];
+            where3[t] = wg;
+        }
+        for (int t = 0; t < nwg; ++t) check(seen3[t] == 1, "3-row tiles are a bijection", nwg, t);
+        for (int g = 0; 4 * g + 3 < (nwg & ~31); ++g)
+            for (int r = 1; r < 4; ++r)
+                check(where3[4 * g] % 8 == where3[4 * g + r] % 8, "3-row tile groups share an XCD", nwg, g);
     }
     check(pm::col_lines(1024) == pm::kC && pm::col_lines(4096) == 2 && pm::col_lines(600) == pm::kC,
           "column tile widths");

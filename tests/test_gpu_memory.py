@@ -1,0 +1,87 @@
+"""GPU tests of device-memory handling: a batched plan whose workspace does
+not fit the device fails with PM_ENOMEM, leaves *out NULL and no memory
+behind, and plans of every kind give back all their memory when destroyed
+(device free memory read before and after)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1302_0120_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pmb():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1302_0120_amd import binding
+    return binding
+
+
+def _free():
+    torch.cuda.synchronize()
+    return torch.cuda.mem_get_info()[0]
+
+
+def test_batched_create_out_of_memory(pmb):
+    """1024^2 masks take 12 bytes per pixel of workspace: ask for 1.5 times
+    the device's memory.  The workspace is the plan's first device
+    allocation, so nothing runs on the device before it fails."""
+    total = torch.cuda.mem_get_info()[1]
+    per_mask = 1024 * 1024 * 12
+    count = int(1.5 * total / per_mask) + 1
+    print(f"batched create of {count} masks of 1024^2 (~{count * per_mask / 2**30:.0f} GiB)", flush=True)
+    hs = (ctypes.c_int * count)(*([1024] * count))
+    h = ctypes.c_void_p(0x1234)
+    free0 = _free()
+    st = pmb.lib.phasemask_create_batched(ctypes.byref(h), count, hs, hs, pmb.PM_FLAG_NO_TUNE,
+                                          torch.cuda.current_stream().cuda_stream)
+    assert st == -3, (st, pmb.lib.phasemask_last_error())
+    assert h.value is None
+    assert b"hipMalloc" in pmb.lib.phasemask_last_error()
+    assert _free() == free0
+    # the library and the device are still usable
+    bp = pmb.BatchedPhaseMask([(64, 64)])
+    m, p = synth.spot_problem(synth.SPOTS_64)
+    out, err = bp.solve([torch.from_numpy(m).cuda()], [torch.from_numpy(p).cuda()], 2)
+    assert torch.isfinite(err).all()
+    bp.close()
+
+
+def test_plans_give_back_their_memory(pmb):
+    """Create, use (solves, RAAR, illumination, physical error, Adam state,
+    batched solves) and destroy plans; after one warm-up round the device's
+    free memory returns to the same value every round."""
+    rng = np.random.default_rng(5)
+    m = torch.from_numpy(synth.spot_amplitude(256, 256, 10, 2.0, 0.5, 1.0, rng)).cuda()
+    ph = torch.from_numpy(synth.uniform_phase(256, 256, rng)).cuda()
+    it = (m * m * (256 * 256 / float((m * m).sum()))).contiguous()
+
+    def round_trip():
+        plan = pmb.PhaseMask(256, 256)
+        plan.solve(m, ph, 5)
+        plan.solve_raar(m, ph, 3, 0.9)
+        plan.physical_error(m, ph)
+        plan.solve_adam(torch.stack([it, it]), torch.stack([ph, ph]), 3, 0.05)
+        plan.set_illumination(torch.ones_like(m))
+        plan.solve(m, ph, 2)
+        plan.close()
+        bp = pmb.BatchedPhaseMask([(256, 256), (128, 128)])
+        m2 = m[:128, :128].contiguous()
+        bp.solve([m, m2], [ph, ph[:128, :128].contiguous()], 3)
+        bp.close()
+        torch.cuda.synchronize()
+
+    round_trip()
+    torch.cuda.empty_cache()
+    free0 = _free()
+    for r in range(3):
+        round_trip()
+        torch.cuda.empty_cache()
+        free = _free()
+        print(f"round {r}: device free memory {free} (start {free0})", flush=True)
+        assert free == free0, (r, free0 - free)
