@@ -34,6 +34,10 @@ pm_status fail(pm_status s, const std::string& why) {
 }
 
 pm_status fail_hip(hipError_t e, const char* what) {
+    // The runtime also keeps a failed call's error as its last error, which
+    // the next launch check (hipGetLastError) would report as its own: the
+    // failure is handled here, so clear it.
+    (void)hipGetLastError();
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
     return e == hipErrorOutOfMemory ? PM_ENOMEM : PM_EDEVICE;
 }
