@@ -212,6 +212,25 @@ def bench_batched(torch, binding, synth, steps):
     }
 
 
+def bench_mfma_probe(torch, binding, waves=4096, reps=200):
+    """One 16-point DFT stage (the radix of the largest FFT plans) over
+    waves x 1024 points, reps times, with the data in registers: on the
+    vector ALUs (the passes' butterflies) and as FP32 matrix products
+    (16 complex multiply-adds per point, operands preloaded in the matrix
+    layout).  Points per second of stage work for each."""
+    x = torch.randn(waves * 1024, dtype=torch.complex64, device="cuda")
+    binding.probe_dft16(False, x, 2)
+    binding.probe_dft16(True, x, 2)
+    _, ms_v = binding.probe_dft16(False, x, reps)
+    _, ms_m = binding.probe_dft16(True, x, reps)
+    pts = waves * 1024 * reps
+    rv, rm = pts / (ms_v * 1e-3), pts / (ms_m * 1e-3)
+    return {"stage": "16-point DFT", "points": pts,
+            "vector_alu_points_per_s": rv, "matrix_core_points_per_s": rm,
+            "matrix_over_vector": rm / rv,
+            "matrix_tflops": 128 * rm / 1e12, "matrix_peak_tflops_fp32": 157.3}
+
+
 def bench_paper_slm(torch, binding, synth, steps=20):
     """The paper's own timing case as context: an 800 x 600 SLM (600 rows of
     800 pixels), 25 iterations, spot target; ms per solve with the target
@@ -554,6 +573,7 @@ def main():
     if not args.no_paper_slm:
         line["paper_slm"] = bench_paper_slm(torch, binding, synth)
     if not args.no_next_rows:
+        line["mfma_probe"] = bench_mfma_probe(torch, binding)
         line["next_rows"] = bench_next_rows(torch, binding, synth, m, phi0)
         line["other_configs"] = bench_other_configs(torch, binding, synth)
     if not args.no_cpu_baseline:

@@ -349,6 +349,17 @@ pm_status phasemask_solve_batched(pm_handle h, const float* const* targets,
  * one-mask handle. */
 int phasemask_batch_schedule(pm_handle h);
 
+/* Configuration a batched plan runs with: FFT schedule (picked at creation
+ * by the plan's tuner, which times every schedule on the plan's own
+ * buffers, cached per architecture and set of sizes, in-process and in the
+ * file named by PHASEMASK_TUNE_CACHE; PHASEMASK_SCHEDULE forces one,
+ * PM_FLAG_NO_TUNE takes 0), number of concurrent chains of launches
+ * (PHASEMASK_CHAINS, default 4) and the cache budget of one group of masks
+ * in bytes (PHASEMASK_GROUP_MB, default 48 MiB; 0 = one group).  Any output
+ * pointer may be NULL.
+ * Errors: PM_EINVAL for a NULL handle, PM_ESTATE for a one-mask handle. */
+pm_status phasemask_batch_config(pm_handle h, int* schedule, int* chains, size_t* group_bytes);
+
 /*
  * Intensity loss and its gradient (differentiable phase optimisation beside
  * the projections; not in the paper, which notes that other reconstruction
@@ -437,6 +448,26 @@ pm_status phasemask_solve_adam(pm_handle h, int batch, const float* target_inten
 pm_status phasemask_time_passes(pm_handle h, const float* target_amplitude,
                                 const float* phase, int reps,
                                 float* col_ms, float* row_ms);
+
+/*
+ * Arithmetic-rate probe for the choice of unit for the FFT butterflies (no
+ * handle; the null stream; synchronises).  Runs one 16-point DFT stage over
+ * waves x 1024 complex points, reps times, with the data in registers:
+ *   matrix_units = 0: on the vector ALUs with the radix-16 butterfly of the
+ *     passes, as forward-then-inverse pairs scaled by 1/16 (reps / 2 pairs);
+ *     out = in transformed so (about in).
+ *   matrix_units = 1: as FP32 matrix products (v_mfma_f32_16x16x4_f32), each
+ *     wave 4 blocks of 16 butterflies, Y = F X with F[k][t] = exp(-2 pi i k t
+ *     / 16), X[t][j] = in[1024 w + 256 b + 16 t + j], accumulated over the
+ *     reps: out[1024 w + 256 b + 16 k + j] = reps * Y[k][j].
+ *   in, out   complex float[waves * 1024], device, not overlapping.
+ *   waves     a multiple of 4 in [4, 2^20]; reps even, in [2, 2^20].
+ *   ms        receives the kernel's own duration.
+ * Both versions do 16 x reps DFT points per thread-lane of work, so
+ * waves * 1024 * reps / ms compares the units' rates for this stage.
+ * Errors: PM_EINVAL for bad arguments; PM_EDEVICE.
+ */
+pm_status phasemask_probe_dft16(int matrix_units, const void* in, void* out, int waves, int reps, float* ms);
 
 /* Plan facts.  Bytes of device memory the plan currently owns (a workspace
  * set by phasemask_set_workspace is the caller's and not counted). */

@@ -45,6 +45,8 @@ _SIGNATURES = {
     "phasemask_intensity_loss_bwd": (ctypes.c_int, [_c_handle, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                                     ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_batch_schedule": (ctypes.c_int, [_c_handle]),
+    "phasemask_batch_config": (ctypes.c_int, [_c_handle, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_size_t)]),
     "phasemask_solve_adam": (ctypes.c_int, [_c_handle, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
@@ -55,6 +57,8 @@ _SIGNATURES = {
                                              ctypes.POINTER(ctypes.c_float),
                                              ctypes.POINTER(ctypes.c_float)]),
     "phasemask_workspace_bytes": (ctypes.c_size_t, [_c_handle]),
+    "phasemask_probe_dft16": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                             ctypes.c_int, ctypes.POINTER(ctypes.c_float)]),
     "phasemask_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "phasemask_last_error": (ctypes.c_char_p, []),
 }
@@ -399,6 +403,14 @@ class BatchedPhaseMask:
         return int(lib.phasemask_batch_schedule(self._h))
 
     @property
+    def config(self):
+        """(FFT schedule, concurrent chains, group budget in bytes) the tuner chose."""
+        sc, ch, gb = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+        _check(lib.phasemask_batch_config(self._h, ctypes.byref(sc), ctypes.byref(ch), ctypes.byref(gb)),
+               "phasemask_batch_config")
+        return int(sc.value), int(ch.value), int(gb.value)
+
+    @property
     def workspace_bytes(self) -> int:
         return int(lib.phasemask_workspace_bytes(self._h)) if self._h is not None else 0
 
@@ -519,6 +531,21 @@ class AdamIntensityStep:
             return self._eager()
         self.graph.replay()
         return self.loss
+
+
+def probe_dft16(matrix_units: bool, x: torch.Tensor, reps: int):
+    """One 16-point DFT stage over x (complex64, waves * 1024 points) on the
+    vector ALUs or as FP32 matrix products, reps times; returns (out, ms)."""
+    if not (x.is_cuda and x.dtype == torch.complex64 and x.is_contiguous() and x.dim() == 1):
+        raise ValueError("x must be a contiguous 1-D complex64 device tensor")
+    if x.numel() % 4096 != 0:
+        raise ValueError("x must hold a multiple of 4096 points")
+    out = torch.empty_like(x)
+    ms = ctypes.c_float()
+    torch.cuda.synchronize(x.device)
+    _check(lib.phasemask_probe_dft16(int(bool(matrix_units)), x.data_ptr(), out.data_ptr(), x.numel() // 1024,
+                                     int(reps), ctypes.byref(ms)), "phasemask_probe_dft16")
+    return out, float(ms.value)
 
 
 def solve(target: torch.Tensor, init_phase: torch.Tensor, n_iter: int, history: bool = True):

@@ -72,6 +72,8 @@ def build(verbose: bool = False, jobs: int | None = None, defines=(), out: str |
                           "-o", os.path.join(build_dir, f"pm_batch_{which}_{sched}.o")])
     steps.append([hipcc, *flags, "-c", os.path.join(CSRC, "pm_aux.hip"),
                   "-o", os.path.join(build_dir, "pm_aux.o")])
+    steps.append([hipcc, *flags, "-c", os.path.join(CSRC, "pm_probe.hip"),
+                  "-o", os.path.join(build_dir, "pm_probe.o")])
     steps.append([hipcc, *flags, "-x", "hip", "-c", os.path.join(CSRC, "phasemask.cpp"),
                   "-o", os.path.join(build_dir, "phasemask.o")])
     jobs = jobs or min(8, os.cpu_count() or 1)

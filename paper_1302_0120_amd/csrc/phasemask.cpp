@@ -123,6 +123,7 @@ constexpr size_t kBatchGroupBytes = (size_t)48 << 20;
 // (PHASEMASK_CHAINS overrides, 1..8).
 constexpr int kBatchChains = 4;
 constexpr size_t kMaxCachedGraphs = 8;
+
 // Iterations per schedule the batched tuner times (groups on chains, as a
 // solve runs them).
 constexpr int kTuneIterations = 6;
@@ -1645,7 +1646,37 @@ pm_status phasemask_physical_error(pm_handle h, const float* target_amplitude, c
     return PM_OK;
 }
 
+pm_status phasemask_probe_dft16(int matrix_units, const void* in, void* out, int waves, int reps, float* ms) {
+    if (!in || !out || !ms) return fail(PM_EINVAL, "null argument");
+    if (waves < 4 || waves > (1 << 20) || waves % 4 != 0) return fail(PM_EINVAL, "waves must be a multiple of 4 in [4, 2^20]");
+    if (reps < 2 || reps > (1 << 20) || reps % 2 != 0) return fail(PM_EINVAL, "reps must be even, in [2, 2^20]");
+    if (misaligned(in, 8) || misaligned(out, 8)) return fail(PM_EINVAL, "misaligned array argument");
+    if (overlaps(in, (size_t)waves * 1024 * sizeof(float2), out, (size_t)waves * 1024 * sizeof(float2)))
+        return fail(PM_EINVAL, "out overlaps in");
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess)
+        e = pm::launch_probe_dft16(matrix_units != 0, (const float2*)in, (float2*)out, waves, reps, nullptr, a, b);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) return fail_hip(e, "DFT-16 probe");
+    return PM_OK;
+}
+
 int phasemask_batch_schedule(pm_handle h) { return (h != nullptr && h->batched) ? h->sched : -1; }
+
+pm_status phasemask_batch_config(pm_handle h, int* schedule, int* chains, size_t* group_bytes) {
+    pm_status st = check_handle(h, h != nullptr && h->batched);
+    if (st != PM_OK) return st;
+    if (!h->batched) return fail(PM_ESTATE, "handle is not a batched plan");
+    if (schedule) *schedule = h->sched;
+    if (chains) *chains = h->chains;
+    if (group_bytes) *group_bytes = h->group_bytes;
+    return PM_OK;
+}
 
 pm_status phasemask_time_passes(pm_handle h, const float* target_amplitude, const float* phase, int reps,
                                 float* col_ms, float* row_ms) {

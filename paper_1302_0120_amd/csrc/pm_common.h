@@ -322,6 +322,13 @@ hipError_t launch_max_partial(const float* x, int n, float* part, int grid, hipS
 hipError_t launch_physical_error(const float* pw, const double* pw_max_part, int n_pw_max, const float* target,
                                  const float* tmax_part, int ntmax, int H, int W, double t_lit, double t_dark,
                                  double* scratch, double* out, hipStream_t s);
+// Arithmetic-rate probe of one 16-point DFT stage (pm_probe.hip): matrix = 0
+// on the vector ALUs, 1 as FP32 matrix products; `waves` (a multiple of 4)
+// waves of 1024 complex points each, in and out; the launch records its own
+// start and end on ev0 / ev1.
+hipError_t launch_probe_dft16(int matrix, const float2* in, float2* out, int waves, int reps, hipStream_t s,
+                              hipEvent_t ev0, hipEvent_t ev1);
+
 // out[b] = sum of part[b * nwg .. b * nwg + nwg) in a fixed order, b < count.
 hipError_t launch_sum_rows(const double* part, int nwg, double* out, int count, hipStream_t s);
 // The same into io->hist (the per-call pointer block).

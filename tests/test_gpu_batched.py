@@ -211,9 +211,12 @@ def test_tuner_picks_and_caches(pmb, monkeypatch, tmp_path):
     cache = tmp_path / "tune.txt"
     monkeypatch.delenv("PHASEMASK_SCHEDULE", raising=False)
     monkeypatch.setenv("PHASEMASK_TUNE_CACHE", str(cache))
+    monkeypatch.delenv("PHASEMASK_CHAINS", raising=False)
+    monkeypatch.delenv("PHASEMASK_GROUP_MB", raising=False)
     shapes = [(512, 512), (256, 256), (256, 256), (128, 1024)]
     bp = pmb.BatchedPhaseMask(shapes)
     assert bp.schedule in (0, 1)
+    assert bp.config == (bp.schedule, 4, 48 << 20)
     # same sizes in another order: same key, same (cached) choice
     bp2 = pmb.BatchedPhaseMask(list(reversed(shapes)))
     assert bp2.schedule == bp.schedule
@@ -221,7 +224,12 @@ def test_tuner_picks_and_caches(pmb, monkeypatch, tmp_path):
         lines = cache.read_text().split()
         assert str(bp.schedule) in lines
     nt = pmb.BatchedPhaseMask(shapes, flags=pmb.PM_FLAG_NO_TUNE)
-    assert nt.schedule == 0
+    assert nt.config == (0, 4, 48 << 20)
+    monkeypatch.setenv("PHASEMASK_CHAINS", "3")
+    monkeypatch.setenv("PHASEMASK_GROUP_MB", "16")
+    assert pmb.BatchedPhaseMask(shapes).config[1:] == (3, 16 << 20)
+    monkeypatch.delenv("PHASEMASK_CHAINS")
+    monkeypatch.delenv("PHASEMASK_GROUP_MB")
     monkeypatch.setenv("PHASEMASK_SCHEDULE", "7")
     with pytest.raises(pmb.PhaseMaskError) as ei:
         pmb.BatchedPhaseMask(shapes)
