@@ -367,9 +367,19 @@ __host__ __device__ constexpr int lds_index(int lay, int i, int key) {
 #ifndef PM_COL_LDS_LAYOUT
 #define PM_COL_LDS_LAYOUT -1
 #endif
-// Layout of the one-mask column pass (PM_COL_LDS_LAYOUT overrides it at 1024).
+// Columns per one-mask column work-group at 1024 points (col_lines): 4 (a
+// whole strip) or 2 (half strips).
+#ifndef PM_COL_LINES_1024
+#define PM_COL_LINES_1024 4
+#endif
+
+// Layout of the one-mask column pass (PM_COL_LDS_LAYOUT overrides it at
+// 1024).  Half strips at 1024 hold two lines whose lanes alternate, as the
+// two-row tiles of the row pass do, and take the row pass's swizzle.
 __host__ __device__ constexpr int col_lds_layout(int L) {
-    return (PM_COL_LDS_LAYOUT >= 0 && L == 1024) ? PM_COL_LDS_LAYOUT : lds_layout(L);
+    return (PM_COL_LDS_LAYOUT >= 0 && L == 1024) ? PM_COL_LDS_LAYOUT
+         : (L == 1024 && PM_COL_LINES_1024 == 2) ? 4 * 64 + 8
+                                                 : lds_layout(L);
 }
 __host__ __device__ constexpr int lds_line_len_lay(int L, int lay) { return lds_pad_lay(lay, L) + lay % 64; }
 __host__ __device__ constexpr int lds_pad(int L, int i) { return lds_pad_lay(lds_layout(L), i); }
@@ -402,15 +412,25 @@ __host__ __device__ constexpr bool lds_mode(int L) {
 #ifndef PM_LDS_T_1920
 #define PM_LDS_T_1920 128
 #endif
+#ifndef PM_LDS_T_600
+#define PM_LDS_T_600 60
+#endif
+#ifndef PM_LDS_T_800
+#define PM_LDS_T_800 80
+#endif
+#ifndef PM_LDS_R_800
+#define PM_LDS_R_800 0
+#endif
 __host__ __device__ constexpr int lds_threads(int L) {
-    return L == 1920 ? PM_LDS_T_1920 : (L == 600 ? 60 : (L == 800 ? 80 : 120));
+    return L == 1920 ? PM_LDS_T_1920 : (L == 600 ? PM_LDS_T_600 : (L == 800 ? PM_LDS_T_800 : 120));
 }
 // Radix sequences in LDS mode (largest radix first, where no inter-stage
-// twiddles are needed): 1920 = 16*12*10, 600 = 10*6*10, 800 = 20*10*4,
-// 1080 = 30*6*6.
+// twiddles are needed): 1920 = 16*12*10, 600 = 10*6*10, 800 = 20*10*4
+// (PM_LDS_R_800 = 1: 10*10*8), 1080 = 30*6*6.
 __host__ __device__ constexpr int lds_stage_radix(int L, int NS) {
     return L == 1920 ? (NS == 1 ? 16 : (NS == 16 ? 12 : 10))
          : L == 600 ? (NS == 1 ? 10 : (NS == 10 ? 6 : 10))
+         : (L == 800 && PM_LDS_R_800 == 1) ? (NS == 1 ? 10 : (NS == 10 ? 10 : 8))
          : L == 800 ? (NS == 1 ? 20 : (NS == 20 ? 10 : 4))
                     : (NS == 1 ? 30 : 6);
 }
@@ -938,7 +958,7 @@ __host__ __device__ constexpr int row_lines(int W) {
 // (two work-groups per CU instead of one), 128^2 -1.7%, 256^2 -1%, but 512^2
 // +4.5%, 1024^2 +6%, 2048^2 +4%, so only 128, 256 and 4096 take half strips.
 __host__ __device__ constexpr int col_lines(int H) {
-    return (H == 128 || H == 256 || H == 4096) ? 2 : kC;
+    return (H == 128 || H == 256 || H == 4096 || (H == 1024 && PM_COL_LINES_1024 == 2)) ? 2 : kC;
 }
 
 // A second, taller row tile for 1920-point rows (0: none).  A 1920-point

@@ -230,9 +230,12 @@ __device__ __forceinline__ void col_body(const ColParams& a, int first, double* 
     float2* line = lds + (sl * kC + c - c0) * LP;
     // Layout scheme 5 (whole strips, lines 4 mod 16 elements apart) needs no
     // per-column key: the swizzle alone puts the four columns' accesses of a
-    // wave on disjoint banks in each exchange.
-    constexpr int key = 0;
+    // wave on disjoint banks in each exchange.  Scheme 4 (half strips, lines
+    // 8 mod 16 apart) flips bit 1 of the second column's indices, as for the
+    // second row of a two-row tile.
+    const int key = (LAY / 64 == 4 && c != c0) ? 2 : 0;
     static_assert(LAY / 64 != 5 || (G == kC && LP % 16 == 4), "swizzled columns: whole strips, lines 4 mod 16 apart");
+    static_assert(LAY / 64 != 4 || (G == 2 && LP % 16 == 8), "swizzled half strips: lines 8 mod 16 apart");
 
     constexpr int PAR1 = (MODE & C_FWD) != 0 ? fft_parity_after<H, P, 0, SW>() : 0;
     if constexpr ((MODE & C_FWD) != 0)
