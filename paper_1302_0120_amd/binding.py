@@ -13,7 +13,10 @@ import os
 
 import torch  # must load before the library: the process then has one HIP runtime
 
-_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libphasemask.so")
+# PHASEMASK_LIBRARY names another build of the same library (for instance the
+# timeline build, libphasemask_timeline.so) to load instead.
+_LIB_PATH = os.environ.get("PHASEMASK_LIBRARY") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libphasemask.so")
 
 # Every function the header declares, with (restype, argtypes).
 _c_handle = ctypes.c_void_p

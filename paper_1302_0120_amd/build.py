@@ -88,5 +88,18 @@ def build(verbose: bool = False, jobs: int | None = None, defines=(), out: str |
     return lib
 
 
+TIMELINE_LIB = os.path.join(PKG, "libphasemask_timeline.so")
+
+
+def build_timeline(verbose: bool = False) -> str:
+    """The library with per-work-group pass timelines (csrc/pm_trace.h), for
+    ``python -m paper_1302_0120_amd.pass_timeline``; a profiling build, not
+    loaded by the binding unless asked for."""
+    return build(verbose=verbose, defines=["PM_TIMELINE=1"], out=TIMELINE_LIB)
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--timeline" in sys.argv:
+        print(build_timeline(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))

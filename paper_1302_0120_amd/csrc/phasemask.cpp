@@ -1666,6 +1666,17 @@ pm_status phasemask_probe_dft16(int matrix_units, const void* in, void* out, int
     return PM_OK;
 }
 
+#ifdef PM_TIMELINE
+// Rate of the device wall clock the timeline records count (kHz), or -1.
+extern "C" int phasemask_timeline_clock_khz() {
+    int khz = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return -1;
+    return khz;
+}
+#endif
+
 int phasemask_batch_schedule(pm_handle h) { return (h != nullptr && h->batched) ? h->sched : -1; }
 
 pm_status phasemask_batch_config(pm_handle h, int* schedule, int* chains, size_t* group_bytes) {

@@ -20,6 +20,7 @@
 
 #include "pm_common.h"
 #include "pm_fft.hpp"
+#include "pm_trace.h"
 
 namespace pm {
 
@@ -160,6 +161,8 @@ __device__ __forceinline__ void col_body(const ColParams& a, int first, double* 
     using LD = LdsPlan<H, G, NBMAX, LAY>;
     constexpr int LP = LD::LP;
     static_assert(G % kC == 0 || G == 2, "whole strips, or half a strip, per work-group");
+    PM_TL_DECL
+    PM_TL_STAMP(0);
 
     const int tid = threadIdx.x;
     constexpr bool HALF = G < kC;
@@ -227,6 +230,8 @@ __device__ __forceinline__ void col_body(const ColParams& a, int first, double* 
 #pragma unroll
         for (int t = 0; t < P; ++t) v[t] = *tiled(a.X, t);
     }
+    PM_TL_WAIT();
+    PM_TL_STAMP(1);
     float2* line = lds + (sl * kC + c - c0) * LP;
     // Layout scheme 5 (whole strips, lines 4 mod 16 elements apart) needs no
     // per-column key: the swizzle alone puts the four columns' accesses of a
@@ -300,6 +305,7 @@ __device__ __forceinline__ void col_body(const ColParams& a, int first, double* 
     if constexpr ((MODE & C_INV) != 0)
         fft_line<H, P, true, LD::NBUF, PAR1, SW, LAY>(v, j, line, LD::STRIDE, tw, key);
 
+    PM_TL_STAMP(2);
     if constexpr ((MODE & COUT_TILED) != 0) {
 #pragma unroll
         for (int t = 0; t < P; ++t) store_shared(tiled(a.X, t), v[t]);
@@ -308,10 +314,13 @@ __device__ __forceinline__ void col_body(const ColParams& a, int first, double* 
 #pragma unroll
         for (int t = 0; t < P; ++t) *natural(a.nat_out, t) = v[t];
     }
+    PM_TL_WAIT();
+    PM_TL_STAMP(3);
 
     constexpr bool SUM = ((MODE & (C_PROJ | C_ERR)) != 0 && (MODE & C_NOERR) == 0) || (MODE & C_LOSS) != 0;
     if constexpr (SUM) group_sum_store<NT>(acc, part_slot);
     if constexpr ((MODE & C_POW) != 0) group_max_store<NT>(mx, part_slot);
+    PM_TL_COMMIT(0);
 }
 
 // Row pass over G adjacent rows starting at `row0`.  Thread tid = (jhi, rho,
@@ -331,6 +340,8 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
     static_assert(T % kC == 0, "row threads must cover whole strips");
     using LD = LdsPlan<W, G, NBMAX, LAY>;
     constexpr int LP = LD::LP;
+    PM_TL_DECL
+    PM_TL_STAMP(0);
 
     const int tid = threadIdx.x;
     int c, rho, jhi;
@@ -400,6 +411,8 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
 #pragma unroll
         for (int t = 0; t < P; ++t) *tiled(a.Z, t) = v[t];
     }
+    PM_TL_WAIT();
+    PM_TL_STAMP(1);
     float2* line = lds + rho * LP;
     // Swizzle key of this row's LDS line (layout scheme 4, two-row tiles:
     // the second row lies 8 mod 16 elements further and flips bit 1 of every
@@ -530,10 +543,14 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
     }
     if constexpr ((MODE & R_FWD) != 0) {
         fft_line<W, P, false, LD::NBUF, PAR1, SW, LAY>(v, j, line, LD::STRIDE, tw, key);
+        PM_TL_STAMP(2);
 #pragma unroll
         for (int t = 0; t < P; ++t) store_shared(tiled(a.X, t), v[t]);
+        PM_TL_WAIT();
+        PM_TL_STAMP(3);
     }
     if constexpr ((MODE & R_PS) != 0 && (MODE & R_NOERR) == 0) group_sum_store<NT>(acc, part_slot);
+    PM_TL_COMMIT(1);
 }
 
 // One-mask kernels: kC columns (one strip) or G rows per work-group

@@ -129,3 +129,19 @@ hipError_t PM_CAT(launch_adj_col_, PM_L)(int mode, const AdjParams& p, int batch
 }
 
 }  // namespace pm
+
+#ifdef PM_TIMELINE
+// Timeline records of this transform length's passes (pm_trace.h): copies
+// the ring buffer (2 * kTlLaunches * kTlWg * kTlFields 64-bit words) and the
+// launch counts (2 * kTlWg 32-bit words) to host memory; 0 or -1.
+extern "C" int PM_CAT(phasemask_timeline_read_, PM_L)(void* records, void* counts) {
+    if (hipMemcpyFromSymbol(records, HIP_SYMBOL(pm::tl_buf), sizeof(pm::tl_buf)) != hipSuccess) return -1;
+    if (hipMemcpyFromSymbol(counts, HIP_SYMBOL(pm::tl_cnt), sizeof(pm::tl_cnt)) != hipSuccess) return -1;
+    return 0;
+}
+// Restarts the launch counts of this length's passes; 0 or -1.
+extern "C" int PM_CAT(phasemask_timeline_reset_, PM_L)() {
+    static const unsigned zeros[2][pm::kTlWg] = {};
+    return hipMemcpyToSymbol(HIP_SYMBOL(pm::tl_cnt), zeros, sizeof(zeros)) == hipSuccess ? 0 : -1;
+}
+#endif
