@@ -268,6 +268,10 @@ def bench_paper_slm(torch, binding, synth, steps=20):
     res["ms_per_mask_incl_upload"], _ = timed(n_iter, True)
     res["ms_per_mask_5it_incl_upload"], _ = timed(5, True)
     res["speedup_vs_paper"] = res["paper_ms_incl_upload"] / res["ms_per_mask_incl_upload"]
+    # the iterate exchange alone (the passes in copy mode), per iteration
+    xbuf = torch.zeros((h, w), dtype=torch.complex64, device=dev)
+    plan.probe_exchange(xbuf, 10)
+    res["exchange_us_per_iteration"] = plan.probe_exchange(xbuf, 200) * 1e3 / 200
     plan.close()
     return res
 
@@ -532,6 +536,12 @@ def main():
     traffic = TRAFFIC_BYTES[kname] if kernel_source_hash() == TRAFFIC_SOURCE_HASH else None
     solve_gbs = (COL_BYTES_PER_PX + ROW_BYTES_PER_PX) * npx * n_iter / (ms_per_step * 1e-3) / 1e9
     copy_gbs, copy_us = copy_bandwidth(torch, npx * 8)
+    # The iterate exchange alone: the plan's own column and row passes in
+    # copy mode (same maps, tiles and launch order, each pass reading what
+    # the other wrote on other XCDs), per iteration.
+    xbuf = torch.zeros((h, w), dtype=torch.complex64, device=dev)
+    plan.probe_exchange(xbuf, 10)
+    exchange_us = plan.probe_exchange(xbuf, args.kernel_reps) * 1e3 / args.kernel_reps
 
     line = {
         "metric": METRIC,
@@ -556,7 +566,11 @@ def main():
                      "kernel_us": kms * 1e3, "bytes_per_launch": kbytes,
                      # measured copy of the same working set (the 8 MiB iterate
                      # read and written), and the kernel's fraction of it
-                     "copy_gbs": copy_gbs, "copy_us": copy_us, "frac_of_copy": achieved / copy_gbs},
+                     "copy_gbs": copy_gbs, "copy_us": copy_us, "frac_of_copy": achieved / copy_gbs,
+                     # one iteration's two passes moving their data alone (no
+                     # arithmetic), and the iteration's speed relative to it
+                     "exchange_us_per_iteration": exchange_us,
+                     "frac_of_exchange": exchange_us / iter_us},
         # per-launch durations in the timed solves (per-iteration device
         # time split by the eager launch-event ratio), and the eager ones
         "passes_us": {"column": col_us, "row": row_us},

@@ -469,6 +469,27 @@ pm_status phasemask_time_passes(pm_handle h, const float* target_amplitude,
  */
 pm_status phasemask_probe_dft16(int matrix_units, const void* in, void* out, int waves, int reps, float* ms);
 
+/*
+ * Data-movement probe of a one-mask plan: the iterate exchange of Sec. II's
+ * iteration without its arithmetic.  Runs reps pairs of the plan's own
+ * column and row pass kernels (same thread maps, tiles, work-groups per CU
+ * and launch order as a solve) in a copy mode that stores every element of
+ * the iterate where it was loaded, with the same write-through stores, so
+ * each pass reads what the other pass wrote from other XCDs, as in a solve.
+ *   buffer  device complex float[height * width] (16-byte aligned), any
+ *           contents; copied in place 2 * reps times, so it is unchanged on
+ *           return (bitwise).  The plan's own buffers are not touched.
+ *   reps    pairs, in [1, 10000].
+ *   ms      receives the duration of the reps pairs (one captured graph,
+ *           launched once untimed and once between events on the handle's
+ *           stream; the call synchronises).
+ * ms / reps is the time one iteration's two passes take for moving their
+ * data alone: the floor for the iteration that this data movement sets.
+ * Errors: PM_EINVAL (NULL handle or argument, reps out of range,
+ * misalignment), PM_ESTATE (batched handle), PM_EDEVICE.
+ */
+pm_status phasemask_probe_exchange(pm_handle h, void* buffer, int reps, float* ms);
+
 /* Plan facts.  Bytes of device memory the plan currently owns (a workspace
  * set by phasemask_set_workspace is the caller's and not counted). */
 size_t phasemask_workspace_bytes(pm_handle h);

@@ -59,6 +59,8 @@ _SIGNATURES = {
     "phasemask_time_passes": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                              ctypes.POINTER(ctypes.c_float),
                                              ctypes.POINTER(ctypes.c_float)]),
+    "phasemask_probe_exchange": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_float)]),
     "phasemask_workspace_bytes": (ctypes.c_size_t, [_c_handle]),
     "phasemask_probe_dft16": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                              ctypes.c_int, ctypes.POINTER(ctypes.c_float)]),
@@ -330,6 +332,17 @@ class PhaseMask:
         _check(lib.phasemask_time_passes(self._h, tp, pp, int(reps), ctypes.byref(c), ctypes.byref(r)),
                "phasemask_time_passes")
         return float(c.value), float(r.value)
+
+    def probe_exchange(self, buffer: torch.Tensor, reps: int = 100) -> float:
+        """ms for `reps` pairs of this plan's column and row passes in copy
+        mode (the iterate exchange without its arithmetic) on `buffer`, a
+        complex64 [height, width] device tensor that is copied in place and
+        comes back unchanged."""
+        bp = _dev_ptr(buffer, torch.complex64, self.shape, "buffer")
+        ms = ctypes.c_float()
+        self._stream()
+        _check(lib.phasemask_probe_exchange(self._h, bp, int(reps), ctypes.byref(ms)), "phasemask_probe_exchange")
+        return float(ms.value)
 
     @property
     def workspace_bytes(self) -> int:

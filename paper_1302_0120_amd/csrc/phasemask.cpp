@@ -1689,6 +1689,56 @@ pm_status phasemask_batch_config(pm_handle h, int* schedule, int* chains, size_t
     return PM_OK;
 }
 
+pm_status phasemask_probe_exchange(pm_handle h, void* buffer, int reps, float* ms) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    if (!buffer || !ms) return fail(PM_EINVAL, "null argument");
+    if (reps < 1 || reps > 10000) return fail(PM_EINVAL, "reps must be in [1, 10000]");
+    if (misaligned(buffer, 16)) return fail(PM_EINVAL, "buffer must be 16-byte aligned");
+    const RowLauncher row = kRowLaunch[len_slot(h->W)];
+    const ColLauncher col = kColLaunch[len_slot(h->H)];
+    pm::ColParams cp = col_params(h, h->part);
+    pm::RowParams rp = row_params(h, nullptr);
+    cp.X = (float2*)buffer;
+    rp.X = (float2*)buffer;
+    // The pairs go into one graph (captured per call: the buffer is a kernel
+    // argument), launched once untimed and once between the events.
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamBeginCapture(exchange)");
+    hipError_t el = hipSuccess;
+    for (int r = 0; r < reps && el == hipSuccess; ++r) {
+        el = col(pm::COL_COPY, cp, h->nwg_col, h->cap_stream, nullptr, nullptr);
+        if (el == hipSuccess) el = row(pm::ROW_COPY, rp, h->nwg_row, h->cap_stream, nullptr, nullptr);
+    }
+    e = hipStreamEndCapture(h->cap_stream, &graph);
+    if (el != hipSuccess) {
+        cleanup();
+        return fail_hip(el, "exchange pass");
+    }
+    if (e != hipSuccess) {
+        cleanup();
+        return fail_hip(e, "hipStreamEndCapture(exchange)");
+    }
+    if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) == hipSuccess &&
+        (e = hipEventCreate(&e0)) == hipSuccess && (e = hipEventCreate(&e1)) == hipSuccess &&
+        (e = hipGraphLaunch(exec, h->stream)) == hipSuccess && (e = hipEventRecord(e0, h->stream)) == hipSuccess &&
+        (e = hipGraphLaunch(exec, h->stream)) == hipSuccess && (e = hipEventRecord(e1, h->stream)) == hipSuccess &&
+        (e = hipEventSynchronize(e1)) == hipSuccess)
+        e = hipEventElapsedTime(ms, e0, e1);
+    cleanup();
+    if (e != hipSuccess) return fail_hip(e, "exchange probe");
+    return PM_OK;
+}
+
 pm_status phasemask_time_passes(pm_handle h, const float* target_amplitude, const float* phase, int reps,
                                 float* col_ms, float* row_ms) {
     pm_status st = check_handle(h);

@@ -61,6 +61,7 @@ enum : int {
     ROUT_FIELD = 16384, // write the natural-layout complex field to io->field_out (as ROUT_NAT)
     R_ADAM = 32768,     // intensity-loss gradient, Adam update of the phase (and with R_FWD the
                         // row FFT of exp(i phase) of the updated phase)
+    ROUT_TILED = 65536, // write the tiled iterate as read, no transform (exchange probe)
 };
 constexpr int ROW_INIT = RIN_PHASE | R_FWD;
 constexpr int ROW_ITER = RIN_TILED | R_INV | R_PS | R_FWD;
@@ -90,6 +91,9 @@ constexpr int ROW_COPY_FIELD = RIN_FIELD | ROUT_FIELD;  // u^n = u^0 (no iterati
 // phi^{k-1}, update to phi^k, and the forward row transform for step k + 1).
 constexpr int ROW_ADAM = RIN_TILED | R_INV | R_ADAM | R_FWD;
 constexpr int ROW_ADAM_LAST = RIN_TILED | R_INV | R_ADAM;
+// Exchange probe: the passes' loads and stores of the iterate with nothing
+// between them (each element written back where it was read).
+constexpr int ROW_COPY = RIN_TILED | ROUT_TILED;
 
 // Column-pass modes (bit sets).
 enum : int {
@@ -119,6 +123,7 @@ constexpr int COL_POW = CIN_TILED | C_FWD | C_POW;
 // of the final phase alone.
 constexpr int COL_LOSS_T = COL_LOSS | C_ITILED;
 constexpr int COL_LOSS_ONLY_T = CIN_TILED | C_FWD | C_LOSS | C_ITILED;
+constexpr int COL_COPY = CIN_TILED | COUT_TILED;
 
 struct RowParams {
     float2* X;             // tiled iterate

@@ -549,6 +549,11 @@ __device__ __forceinline__ void row_body(const RowParams& a, int row0, const flo
         PM_TL_WAIT();
         PM_TL_STAMP(3);
     }
+    if constexpr ((MODE & ROUT_TILED) != 0) {
+        static_assert((MODE & (R_INV | R_FWD | R_PS | RIN_TILED)) == RIN_TILED, "copy of the iterate only");
+#pragma unroll
+        for (int t = 0; t < P; ++t) store_shared(tiled(a.X, t), v[t]);
+    }
     if constexpr ((MODE & R_PS) != 0 && (MODE & R_NOERR) == 0) group_sum_store<NT>(acc, part_slot);
     PM_TL_COMMIT(1);
 }

@@ -66,6 +66,7 @@ hipError_t launch_rows(int mode, const RowParams& p, int grid, hipStream_t s, hi
         case ROW_FFT_INV: return launch(k_row<PM_L, ROW_FFT_INV, G>, grid, block, s, ev0, ev1, p);
         case ROW_INIT_FIELD: return launch(k_row<PM_L, ROW_INIT_FIELD, G>, grid, block, s, ev0, ev1, p);
         case ROW_COPY_FIELD: return launch(k_row<PM_L, ROW_COPY_FIELD, G>, grid, block, s, ev0, ev1, p);
+        case ROW_COPY: return launch(k_row<PM_L, ROW_COPY, G>, grid, block, s, ev0, ev1, p);
         default: return hipErrorInvalidValue;
     }
 }
@@ -101,6 +102,7 @@ hipError_t PM_CAT(launch_col_, PM_L)(int mode, const ColParams& p, int grid, hip
         case COL_ITER_NE: return launch(k_col<PM_L, COL_ITER_NE>, grid, block, s, ev0, ev1, p);
         case COL_INIT_BIT: return launch(k_col<PM_L, COL_INIT_BIT>, grid, block, s, ev0, ev1, p);
         case COL_POW: return launch(k_col<PM_L, COL_POW>, grid, block, s, ev0, ev1, p);
+        case COL_COPY: return launch(k_col<PM_L, COL_COPY>, grid, block, s, ev0, ev1, p);
         default: return hipErrorInvalidValue;
     }
 }

@@ -35,3 +35,27 @@ def test_probe_matrix_layout_and_vector_round_trip(pmb):
     back, ms_v = pmb.probe_dft16(False, xd, 2)
     err_v = np.linalg.norm(back.cpu().numpy() - x) / np.linalg.norm(x)
     assert err_v <= 1e-6 and ms_v > 0
+
+
+@pytest.mark.parametrize("shape", [(1024, 1024), (600, 800), (256, 128)])
+def test_exchange_probe_copies_in_place(pmb, shape):
+    """The exchange probe runs the plan's passes in copy mode: the buffer
+    comes back bitwise unchanged (every element stored where it was loaded,
+    by both thread maps), the plan's own solve is unaffected, and the time is
+    positive; bad arguments are PM_EINVAL, a batched handle PM_ESTATE."""
+    h, w = shape
+    print(f"exchange probe {shape}", flush=True)
+    rng = np.random.default_rng(h + w)
+    x = (rng.standard_normal((h, w)) + 1j * rng.standard_normal((h, w))).astype(np.complex64)
+    buf = torch.from_numpy(x).cuda()
+    plan = pmb.PhaseMask(h, w)
+    ms = plan.probe_exchange(buf, 3)
+    assert ms > 0
+    assert torch.equal(buf.cpu(), torch.from_numpy(x))
+    with pytest.raises(pmb.PhaseMaskError) as ei:
+        plan.probe_exchange(buf, 0)
+    assert ei.value.status == -1
+    bp = pmb.BatchedPhaseMask([(64, 64)])
+    import ctypes
+    ms_c = ctypes.c_float()
+    assert pmb.lib.phasemask_probe_exchange(bp._h, ctypes.c_void_p(buf.data_ptr()), 1, ctypes.byref(ms_c)) == -5
