@@ -48,15 +48,57 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     }
 }
 
-// One FP64 partial per reduction group (see red_width): a fixed xor
-// butterfly inside the group, then the group's first lane writes its sum to
-// slot[group].  No barrier; all threads must call.
+#ifndef PM_DPP_SUM
+#define PM_DPP_SUM 1
+#endif
+// A double moved between lanes by the DPP pattern CTRL (within rows of 16
+// lanes, every source lane valid).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// One FP64 partial per reduction group (see red_width), in a fixed order,
+// written by the group's first lane to slot[group].  No barrier; all threads
+// must call.  Groups of 16, 32 or 64 lanes (aligned rows of 16 lanes, all
+// active, since the work-group size is a multiple of the group size): four
+// DPP steps inside each row (pairs, quads, eights, sixteens: every lane then
+// holds its row's sum), then rows added from lane reads -- (row 0 + row 1)
+// + (row 2 + row 3) for 64, row 0 + row 1 and row 2 + row 3 for 32.  These
+// stay in the vector unit, where a cross-lane shuffle goes through the LDS
+// crossbar once per step (still used for smaller groups).
 template <int NT>
 __device__ __forceinline__ void group_sum_store(double v, double* slot) {
     constexpr int WS = red_width(NT);
+    if constexpr (WS >= 16 && PM_DPP_SUM) {
+        v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]: lane ^ 1
+        v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]: lane ^ 2
+        v += dpp_f64<0x141>(v);  // row_half_mirror: lane i <-> 7 - i in each 8
+        v += dpp_f64<0x140>(v);  // row_mirror: lane i <-> 15 - i in each 16
+        if constexpr (WS == 64) {
+            const double s = (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+            if (threadIdx.x % 64 == 0) slot[threadIdx.x / 64] = s;
+        } else if constexpr (WS == 32) {
+            const double s0 = readlane_f64(v, 0) + readlane_f64(v, 16);
+            const double s1 = readlane_f64(v, 32) + readlane_f64(v, 48);
+            if (threadIdx.x % 32 == 0) slot[threadIdx.x / 32] = (threadIdx.x % 64 == 0) ? s0 : s1;
+        } else {
+            if (threadIdx.x % 16 == 0) slot[threadIdx.x / 16] = v;
+        }
+    } else {
 #pragma unroll
-    for (int off = WS / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WS);
-    if (threadIdx.x % WS == 0) slot[threadIdx.x / WS] = v;
+        for (int off = WS / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WS);
+        if (threadIdx.x % WS == 0) slot[threadIdx.x / WS] = v;
+    }
 }
 
 // The same for a maximum (stored as a double).
