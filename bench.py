@@ -159,12 +159,14 @@ def copy_bandwidth(torch, nbytes, reps=200):
     return 2 * nbytes / (us * 1e-6) / 1e9, us
 
 
-def bench_batched(torch, binding, synth, steps):
+def bench_batched(torch, binding, synth, steps, plain_too=True, progress=False):
     """64 masks of sizes drawn from {256, 512, 1024}^2 (1-200 spots each), 100
     iterations: one batched graph launch versus the same masks solved one by
-    one with the one-mask path (each with its own plan and graph).  Both
-    report the final Fourier error of every mask."""
+    one with the one-mask path (each with its own plan and graph; skipped
+    with plain_too=False).  Both report the final Fourier error of every
+    mask."""
     n_iter = 100
+    say = (lambda m: print(m, flush=True)) if progress else (lambda m: None)
     probs = synth.batched_problems()
     shapes = [m.shape for m, _ in probs]
     dev = torch.device("cuda", 0)
@@ -172,14 +174,31 @@ def bench_batched(torch, binding, synth, steps):
     phases = [torch.from_numpy(p).to(dev) for _, p in probs]
     outs = [torch.empty_like(p) for p in phases]
     err = torch.empty(len(probs), dtype=torch.float64, device=dev)
+    say("batched: plan (tuner)")
     bp = binding.BatchedPhaseMask(shapes, device=dev)
+    say("batched: first solve")
     bp.solve(targets, phases, n_iter, outs=outs, final_err=err)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         bp.solve(targets, phases, n_iter, outs=outs, final_err=err)
+        say(f"batched: timed solve {k + 1} of {steps} enqueued")
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / steps
+    sum_px = sum(h * w for h, w in shapes)
+    gbs = (COL_BYTES_PER_PX + ROW_BYTES_PER_PX) * sum_px * n_iter / t_batch / 1e9
+    res = {
+        "workload": "64 masks, sizes uniform over {256,512,1024}^2 (seed 4), 1-200 spots, 100 it",
+        "sum_pixels": sum_px,
+        "masks_per_s": len(probs) / t_batch,
+        "ms_per_batch": t_batch * 1e3,
+        "algorithmic_gbs": gbs,
+        "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+        "max_final_error": float(err.max().item()),
+        "schedule": bp.schedule,
+    }
+    if not plain_too:
+        return res
 
     plans = {}
     hists = [torch.empty(2 * n_iter + 1, dtype=torch.float64, device=dev) for _ in probs]
@@ -195,21 +214,12 @@ def bench_batched(torch, binding, synth, steps):
         plain()
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / steps
-    sum_px = sum(h * w for h, w in shapes)
-    gbs = (COL_BYTES_PER_PX + ROW_BYTES_PER_PX) * sum_px * n_iter / t_batch / 1e9
-    return {
-        "workload": "64 masks, sizes uniform over {256,512,1024}^2 (seed 4), 1-200 spots, 100 it",
-        "sum_pixels": sum_px,
-        "masks_per_s": len(probs) / t_batch,
-        "ms_per_batch": t_batch * 1e3,
+    res.update({
         "plain_masks_per_s": len(probs) / t_plain,
         "plain_ms": t_plain * 1e3,
         "speedup_vs_plain": t_plain / t_batch,
-        "algorithmic_gbs": gbs,
-        "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
-        "max_final_error": float(err.max().item()),
-        "schedule": bp.schedule,
-    }
+    })
+    return res
 
 
 def bench_mfma_probe(torch, binding, waves=4096, reps=200):
@@ -447,6 +457,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-versus-plain measurement")
     ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched workload (no one-by-one comparison), printing its steps "
+                         "and one JSON object: for counter runs under rocprofv3")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the Adam-versus-GS measurement")
     ap.add_argument("--no-paper-slm", action="store_true",
@@ -476,6 +489,11 @@ def main():
         return
 
     from paper_1302_0120_amd import binding, synth
+
+    if args.only_batched:
+        print(json.dumps({"batched": bench_batched(torch, binding, synth, args.batched_steps,
+                                                   plain_too=False, progress=True)}), flush=True)
+        return
 
     spec = synth.SPOTS_1024
     h, w, n_iter = spec.height, spec.width, spec.n_iter
