@@ -222,6 +222,33 @@ def bench_batched(torch, binding, synth, steps, plain_too=True, progress=False):
     return res
 
 
+def bench_batched_uniform(torch, binding, synth, steps, count=16, size=1024):
+    """`count` masks of the headline's size (the 1024 x 1024 spot workload's
+    sizes, 1-200 spots each, 100 iterations) through the batched path: how
+    far the same pass design gets once every CU holds several tiles, which
+    the single mask cannot give it."""
+    n_iter = 100
+    probs = synth.batched_problems(count=count, sizes=(size,))
+    dev = torch.device("cuda", 0)
+    targets = [torch.from_numpy(m).to(dev) for m, _ in probs]
+    phases = [torch.from_numpy(p).to(dev) for _, p in probs]
+    outs = [torch.empty_like(p) for p in phases]
+    err = torch.empty(count, dtype=torch.float64, device=dev)
+    bp = binding.BatchedPhaseMask([(size, size)] * count, device=dev)
+    bp.solve(targets, phases, n_iter, outs=outs, final_err=err)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bp.solve(targets, phases, n_iter, outs=outs, final_err=err)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    gbs = (COL_BYTES_PER_PX + ROW_BYTES_PER_PX) * count * size * size * n_iter / t / 1e9
+    return {"workload": f"{count} masks of {size}x{size}, 1-200 spots, 100 it", "masks_per_s": count / t,
+            "ms_per_batch": t * 1e3, "gs_iterations_per_s": count * n_iter / t,
+            "algorithmic_gbs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "max_final_error": float(err.max().item()), "schedule": bp.schedule}
+
+
 def bench_mfma_probe(torch, binding, waves=4096, reps=200):
     """One 16-point DFT stage (the radix of the largest FFT plans) over
     waves x 1024 points, reps times, with the data in registers: on the
@@ -600,6 +627,7 @@ def main():
     }
     if not args.no_batched:
         line["batched"] = bench_batched(torch, binding, synth, args.batched_steps)
+        line["batched_uniform_1024"] = bench_batched_uniform(torch, binding, synth, args.batched_steps)
     if not args.no_adjoint:
         line["adjoint"] = bench_adjoint(torch, binding, synth, args.adam_lr)
     if not args.no_paper_slm:
