@@ -268,6 +268,37 @@ def bench_mfma_probe(torch, binding, waves=4096, reps=200):
             "matrix_tflops": 128 * rm / 1e12, "matrix_peak_tflops_fp32": 157.3}
 
 
+def bench_many(torch, binding, synth, h, w, n_iter, count, steps):
+    """`count` masks of h x w (1-200 spots each) solved together as a
+    uniform batch (phasemask_solve_many, FP64 histories): ms per batch and
+    per mask, masks/s and algorithmic GB/s (36 B/px per iteration)."""
+    import numpy as np
+    dev = torch.device("cuda", 0)
+    ms_, ps_ = [], []
+    for b in range(count):
+        rng = np.random.default_rng(7000 + b)
+        ms_.append(synth.spot_amplitude(h, w, int(rng.integers(1, 201)), 2.0, 0.5, 1.0, rng))
+        ps_.append(synth.uniform_phase(h, w, rng))
+    md = torch.from_numpy(np.stack(ms_)).to(dev)
+    pd = torch.from_numpy(np.stack(ps_)).to(dev)
+    plan = binding.PhaseMask(h, w, device=dev)
+    out = torch.empty_like(pd)
+    hist = torch.empty((count, 2 * n_iter + 1), dtype=torch.float64, device=dev)
+    for _ in range(3):
+        plan.solve_many(md, pd, n_iter, out=out, history=hist)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.solve_many(md, pd, n_iter, out=out, history=hist)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    gbs = (COL_BYTES_PER_PX + ROW_BYTES_PER_PX) * count * h * w * n_iter / t / 1e9
+    plan.close()
+    return {"masks": count, "n_iter": n_iter, "ms_per_batch": t * 1e3, "ms_per_mask": t * 1e3 / count,
+            "masks_per_s": count / t, "gs_iterations_per_s": count * n_iter / t, "algorithmic_gbs": gbs,
+            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "max_final_error": float(hist[:, -1].max().item())}
+
+
 def bench_paper_slm(torch, binding, synth, steps=20):
     """The paper's own timing case as context: an 800 x 600 SLM (600 rows of
     800 pixels), 25 iterations, spot target; ms per solve with the target
@@ -305,6 +336,9 @@ def bench_paper_slm(torch, binding, synth, steps=20):
     res["ms_per_mask_incl_upload"], _ = timed(n_iter, True)
     res["ms_per_mask_5it_incl_upload"], _ = timed(5, True)
     res["speedup_vs_paper"] = res["paper_ms_incl_upload"] / res["ms_per_mask_incl_upload"]
+    # a uniform batch of the panel's masks (phasemask_solve_many): every
+    # pass one launch over all masks
+    res["many"] = bench_many(torch, binding, synth, h, w, n_iter, 16, steps)
     # the iterate exchange alone (the passes in copy mode), per iteration
     xbuf = torch.zeros((h, w), dtype=torch.complex64, device=dev)
     plan.probe_exchange(xbuf, 10)
@@ -628,6 +662,8 @@ def main():
     if not args.no_batched:
         line["batched"] = bench_batched(torch, binding, synth, args.batched_steps)
         line["batched_uniform_1024"] = bench_batched_uniform(torch, binding, synth, args.batched_steps)
+        line["batched_uniform_1024"]["one_mask_kernels"] = bench_many(torch, binding, synth, 1024, 1024, 100, 16,
+                                                                      args.batched_steps)
     if not args.no_adjoint:
         line["adjoint"] = bench_adjoint(torch, binding, synth, args.adam_lr)
     if not args.no_paper_slm:

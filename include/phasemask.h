@@ -169,6 +169,34 @@ pm_status phasemask_solve(pm_handle h, const float* target_amplitude,
                           float* out_phase, double* err_history);
 
 /*
+ * The alternating projections of Sec. II (Eqs. 4a, 5, 6) on a uniform batch
+ * of `batch` masks of the plan's size, e.g. a stream of stimulation patterns
+ * for the same SLM panel (Sec. I: frame rates of 0.1-1 kHz): every pass of
+ * the solve is one launch over all masks, so the GPU holds several tiles per
+ * CU where one mask holds one.  Mask b's arrays follow mask b - 1's:
+ *   target_amplitude  float[batch][height][width] (16-byte aligned), m >= 0;
+ *   init_phase        float[batch][height][width];
+ *   out_phase         float[batch][height][width], may alias init_phase;
+ *   err_history       double[batch][2 n_iter + 1] or NULL, mask b's history
+ *                     as phasemask_solve writes it.
+ * Each mask's phases and history are bitwise those of phasemask_solve on
+ * that mask alone (same kernels and summation order).  The illumination of
+ * phasemask_set_illumination does not apply (p = 1; PM_EUNSUPPORTED while one
+ * is set).  The plan keeps the batch's iterates, rescaled targets and
+ * partial sums (12 bytes per pixel and mask, plus partials), allocated on
+ * first use for the largest batch and history seen, which synchronises the
+ * stream and drops the captured graphs; without PM_FLAG_NO_GRAPH the solve
+ * is one captured graph per (n_iter, batch, history).
+ * Errors: PM_EINVAL for a NULL array, batch outside [1, 65535], n_iter
+ * outside [0, 2^20], misalignment or overlapping arrays (out_phase with the
+ * target, err_history with any array); PM_EUNSUPPORTED (illumination set);
+ * PM_ESTATE (batched handle); PM_ENOMEM; PM_EDEVICE.
+ */
+pm_status phasemask_solve_many(pm_handle h, int batch, const float* target_amplitude,
+                               const float* init_phase, int n_iter,
+                               float* out_phase, double* err_history);
+
+/*
  * For callers that cannot allocate device memory when they solve (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * phasemask_solve without any allocation.  Same arguments, results (bitwise)

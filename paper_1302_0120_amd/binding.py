@@ -32,6 +32,8 @@ _SIGNATURES = {
                                              ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_solve_noalloc": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                                ctypes.c_void_p, ctypes.c_void_p]),
+    "phasemask_solve_many": (ctypes.c_int, [_c_handle, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "phasemask_workspace_size": (ctypes.c_size_t, [_c_handle, ctypes.c_int]),
     "phasemask_set_workspace": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_size_t]),
     "phasemask_solve_raar": (ctypes.c_int, [_c_handle, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
@@ -162,6 +164,30 @@ class PhaseMask:
         hp = 0 if hist is None else _dev_ptr(hist, torch.float64, (2 * int(n_iter) + 1,), "history")
         self._stream()
         _check(lib.phasemask_solve(self._h, tp, pp, int(n_iter), op, hp or None), "phasemask_solve")
+        return out, hist
+
+    def solve_many(self, targets: torch.Tensor, init_phases: torch.Tensor, n_iter: int,
+                   out: torch.Tensor | None = None, history: bool | torch.Tensor = True):
+        """n_iter GS iterations on a uniform batch: float32 [batch, height,
+        width] targets and initial phases; returns (phases [batch, height,
+        width], histories [batch, 2 n_iter + 1] or None)."""
+        if targets.dim() != 3:
+            raise ValueError("targets must be [batch, height, width]")
+        b = int(targets.shape[0])
+        shape = (b,) + self.shape
+        tp = _dev_ptr(targets, torch.float32, shape, "targets")
+        pp = _dev_ptr(init_phases, torch.float32, shape, "init_phases")
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=self.device)
+        op = _dev_ptr(out, torch.float32, shape, "out")
+        hist = None
+        if isinstance(history, torch.Tensor):
+            hist = history
+        elif history:
+            hist = torch.empty((b, 2 * int(n_iter) + 1), dtype=torch.float64, device=self.device)
+        hp = 0 if hist is None else _dev_ptr(hist, torch.float64, (b, 2 * int(n_iter) + 1), "history")
+        self._stream()
+        _check(lib.phasemask_solve_many(self._h, b, tp, pp, int(n_iter), op, hp or None), "phasemask_solve_many")
         return out, hist
 
     def solve_noalloc(self, target: torch.Tensor, init_phase: torch.Tensor, n_iter: int,

@@ -180,6 +180,16 @@ struct pm_plan {
     float* a_m = nullptr;
     float* a_v = nullptr;
     float* a_inten = nullptr;
+    // Uniform batches (phasemask_solve_many), allocated on first use for
+    // many_cap masks of many_entries history entries each: the iterates,
+    // rescaled targets, target-norm partials and FP64 error partials of
+    // every mask (mask b's partials many_entries * stride doubles further).
+    int many_cap = 0;
+    size_t many_entries = 0;
+    float2* m_X = nullptr;
+    float* m_mhat = nullptr;
+    double* m_partm = nullptr;
+    double* m_part = nullptr;
     // Device address of the allocation-free solve's scratch array on the
     // plan's device (looked up at create), or null with the lookup's error.
     unsigned char* scratch = nullptr;
@@ -249,6 +259,10 @@ void free_plan(pm_plan* h) {
     (void)hipFree(h->a_m);
     (void)hipFree(h->a_v);
     (void)hipFree(h->a_inten);
+    (void)hipFree(h->m_X);
+    (void)hipFree(h->m_mhat);
+    (void)hipFree(h->m_partm);
+    (void)hipFree(h->m_part);
     (void)hipFree(h->pn2);
     (void)hipFree(h->vflags);
     (void)hipFree(h->io);
@@ -374,6 +388,7 @@ enum : int {
     kAlgoRAAR = 1,     // RAAR, phases in and out
     kAlgoGSField = 2,  // alternating projections, complex fields in and out
     kAlgoAdam = 3,     // Adam on the intensity loss, phases in and out
+    kAlgoMany = 4,     // alternating projections on a uniform batch of masks
 };
 
 // The whole solve after the pointer block is set: target preparation,
@@ -448,6 +463,61 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int al
     return PM_OK;
 }
 
+// A uniform batch of `batch` masks (phasemask_solve_many): the one-mask
+// solve's sequence with every launch covering all masks (grid.y = mask),
+// each mask with its own iterate, rescaled target, partials and history.
+pm_status enqueue_many(pm_plan* h, hipStream_t s, int n_iter, bool hist, int batch) {
+    const RowLauncher row = kRowLaunch[len_slot(h->W)];
+    const ColLauncher col = kColLaunch[len_slot(h->H)];
+    const size_t bstride = h->many_entries * (size_t)h->stride;
+    auto pe = [&](int e) { return h->m_part + (size_t)e * h->stride; };
+    pm::RowParams rp = row_params(h, nullptr);
+    rp.X = h->m_X;
+    rp.illum = nullptr;
+    rp.nb = batch;
+    rp.part_bstride = bstride;
+    rp.spread = (long)h->nwg_row * batch <= h->num_cu;
+    pm::ColParams cp = col_params(h, nullptr);
+    cp.X = h->m_X;
+    cp.mhat = h->m_mhat;
+    cp.nb = batch;
+    cp.part_bstride = bstride;
+    cp.spread = (long)h->nwg_col * batch <= h->num_cu;
+    auto rpe = [&](double* part) {
+        pm::RowParams r = rp;
+        r.part = part;
+        return r;
+    };
+    auto cpe = [&](double* part) {
+        pm::ColParams c = cp;
+        c.part = part;
+        return c;
+    };
+    if (n_iter == 0) {
+        PM_TRY(pm::launch_wrap_phase(h->io, h->N * batch, s), "wrap phase");
+        if (!hist) return PM_OK;
+    }
+    PM_TRY(pm::launch_norm_partial(h->io, h->N, h->m_partm, kNormGrid, s, batch), "target norm");
+    PM_TRY(pm::launch_target_tile(h->io, h->H, h->W, h->m_partm, kNormGrid, h->m_mhat, s, nullptr, batch),
+           "target tile");
+    PM_TRY(row(pm::ROW_INIT_MANY, rpe(nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+    const int col_mode = hist ? pm::COL_ITER_MANY : pm::COL_ITER_NE_MANY;
+    const int row_mode = hist ? pm::ROW_ITER_MANY : pm::ROW_ITER_NE_MANY;
+    const int last_mode = hist ? pm::ROW_LAST_FWD_MANY : pm::ROW_LAST_NE_MANY;
+    for (int nu = 0; nu < n_iter; ++nu) {
+        PM_TRY(col(col_mode, cpe(pe(2 * nu)), h->nwg_col, s, nullptr, nullptr), "column pass");
+        const int mode = nu < n_iter - 1 ? row_mode : last_mode;
+        PM_TRY(row(mode, rpe(pe(2 * nu + 1)), h->nwg_row, s, nullptr, nullptr), "row pass");
+    }
+    if (hist) {
+        PM_TRY(col(pm::COL_ERR_MANY, cpe(pe(2 * n_iter)), h->nwg_col, s, nullptr, nullptr), "column error");
+        PM_TRY(pm::launch_finalize(h->m_part, h->stride, h->slots_col, h->slots_row, 1.0 / h->N, h->io, 0,
+                                   2 * n_iter + 1, s, 1, nullptr, batch, bstride),
+               "finalize");
+    }
+    return PM_OK;
+}
+
 pm_status enqueue_batch(pm_plan* h, hipStream_t s, int n_iter, bool err);
 pm_status enqueue_adam(pm_plan* h, hipStream_t s, const SolveKey& k);
 
@@ -455,6 +525,7 @@ pm_status enqueue_adam(pm_plan* h, hipStream_t s, const SolveKey& k);
 pm_status enqueue_key(pm_plan* h, hipStream_t s, const SolveKey& k) {
     if (h->batched) return enqueue_batch(h, s, k.n_iter, k.hist);
     if (k.algo == kAlgoAdam) return enqueue_adam(h, s, k);
+    if (k.algo == kAlgoMany) return enqueue_many(h, s, k.n_iter, k.hist, k.batch);
     return enqueue_solve(h, s, k.n_iter, k.hist, k.algo, k.beta);
 }
 
@@ -1048,6 +1119,84 @@ pm_status phasemask_solve(pm_handle h, const float* target_amplitude, const floa
     PM_TRY(pm::launch_set_io(h->io, io, h->stream), "set io");
     if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_solve(h, h->stream, n_iter, hist);
     return launch_graph(h, n_iter, hist);
+}
+
+namespace {
+
+// Makes the uniform-batch buffers hold `batch` masks of `entries` history
+// entries each (growing them synchronises the stream and drops the graphs).
+pm_status ensure_many(pm_plan* h, int batch, size_t entries) {
+    entries = std::max<size_t>(entries, 2);
+    if (batch <= h->many_cap && entries <= h->many_entries) return PM_OK;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+    drop_graphs(h);
+    const int cap = std::max(batch, h->many_cap);
+    const size_t ent = std::max(entries, h->many_entries);
+    const size_t n = (size_t)h->N * cap;
+    float2* x = nullptr;
+    float* m = nullptr;
+    double* pm_ = nullptr;
+    double* pt = nullptr;
+    if ((e = hipMalloc(&x, n * sizeof(float2))) != hipSuccess || (e = hipMalloc(&m, n * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&pm_, (size_t)kNormGrid * cap * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&pt, ent * (size_t)h->stride * cap * sizeof(double))) != hipSuccess) {
+        (void)hipFree(x);
+        (void)hipFree(m);
+        (void)hipFree(pm_);
+        (void)hipFree(pt);
+        return fail_hip(e, "hipMalloc(uniform batch)");
+    }
+    const size_t old_bytes = h->many_cap == 0 ? 0
+        : (size_t)h->N * h->many_cap * (sizeof(float2) + sizeof(float)) + (size_t)kNormGrid * h->many_cap * sizeof(double) +
+              h->many_entries * (size_t)h->stride * h->many_cap * sizeof(double);
+    (void)hipFree(h->m_X);
+    (void)hipFree(h->m_mhat);
+    (void)hipFree(h->m_partm);
+    (void)hipFree(h->m_part);
+    h->m_X = x;
+    h->m_mhat = m;
+    h->m_partm = pm_;
+    h->m_part = pt;
+    h->many_cap = cap;
+    h->many_entries = ent;
+    h->ws_bytes = h->ws_bytes - old_bytes + n * (sizeof(float2) + sizeof(float)) + (size_t)kNormGrid * cap * sizeof(double) +
+                  ent * (size_t)h->stride * cap * sizeof(double);
+    return PM_OK;
+}
+
+}  // namespace
+
+pm_status phasemask_solve_many(pm_handle h, int batch, const float* target_amplitude, const float* init_phase,
+                               int n_iter, float* out_phase, double* err_history) {
+    pm_status st = check_handle(h);
+    if (st != PM_OK) return st;
+    if (batch < 1 || batch > 65535) return fail(PM_EINVAL, "batch must be in [1, 65535]");
+    if (!target_amplitude || !init_phase || !out_phase) return fail(PM_EINVAL, "null array argument");
+    if (n_iter < 0 || n_iter > (1 << 20)) return fail(PM_EINVAL, "n_iter must be in [0, 2^20]");
+    if (misaligned(target_amplitude, 16)) return fail(PM_EINVAL, "target must be 16-byte aligned");
+    if (misaligned(init_phase, 4) || misaligned(out_phase, 4) || misaligned(err_history, 8))
+        return fail(PM_EINVAL, "misaligned array argument");
+    if (h->illum_on) return fail(PM_EUNSUPPORTED, "uniform batches use p = 1 (clear the illumination first)");
+    const size_t nb = (size_t)h->N * batch * sizeof(float);
+    const size_t hb = (2 * (size_t)n_iter + 1) * batch * sizeof(double);
+    if (overlaps(out_phase, nb, target_amplitude, nb)) return fail(PM_EINVAL, "out_phase overlaps the target");
+    if (err_history && (overlaps(err_history, hb, target_amplitude, nb) || overlaps(err_history, hb, out_phase, nb) ||
+                        overlaps(err_history, hb, init_phase, nb)))
+        return fail(PM_EINVAL, "err_history overlaps an array argument");
+    const bool hist = err_history != nullptr;
+    if ((st = validate_input(h, target_amplitude, true, false, "target", batch)) != PM_OK) return st;
+    if ((st = validate_input(h, init_phase, false, false, "init_phase", batch)) != PM_OK) return st;
+    if ((st = ensure_many(h, batch, 2 * (size_t)n_iter + 1)) != PM_OK) return st;
+    pm::PmIo io{target_amplitude, init_phase, out_phase, err_history};
+    PM_TRY(pm::launch_set_io(h->io, io, h->stream), "set io");
+    if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_many(h, h->stream, n_iter, hist, batch);
+    SolveKey k;
+    k.n_iter = n_iter;
+    k.hist = hist;
+    k.algo = kAlgoMany;
+    k.batch = batch;
+    return launch_graph(h, k);
 }
 
 // ----- allocation-free solve ----------------------------------------------------

@@ -41,9 +41,10 @@ __device__ __forceinline__ void sq_partial(const float* x, int n, double* part, 
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
+// Mask blockIdx.y of a uniform batch (0 for one mask).
 __global__ void __launch_bounds__(kAuxThreads) k_norm_partial(const PmIo* io, int n, double* part) {
     __shared__ double red[red_slots(kAuxThreads)];
-    sq_partial(io->target, n, part, red);
+    sq_partial(io->target + (size_t)blockIdx.y * n, n, part + (size_t)blockIdx.y * gridDim.x, red);
 }
 
 __global__ void __launch_bounds__(kAuxThreads) k_sq_partial(const float* x, int n, double* part) {
@@ -75,11 +76,15 @@ k_tile_plain(const float* src, int H, int W, float* dst, const double* part, int
 // mhat = m / ||m|| in the strip-tiled layout.  Every work-group sums the
 // partials itself in the same fixed order, so all see the same norm.
 // One thread per 4 consecutive pixels of a row (= one strip chunk, kC = 4).
+// Mask blockIdx.y of a uniform batch (0 for one mask).
 __global__ void __launch_bounds__(kAuxThreads)
 k_target_tile(const PmIo* io, int H, int W, const double* part, int npart, float* mhat, const double* pn2) {
     static_assert(kC == 4, "one float4 per strip chunk");
     __shared__ double red[red_slots(kAuxThreads)];
     __shared__ double inv_norm;
+    const size_t mb = (size_t)blockIdx.y * H * W;
+    part += (size_t)blockIdx.y * npart;
+    mhat += mb;
     double acc = 0.0;
     for (int i = threadIdx.x; i < npart; i += kAuxThreads) acc += part[i];
     const double tot = block_sum<kAuxThreads>(acc, red);
@@ -99,7 +104,7 @@ k_target_tile(const PmIo* io, int H, int W, const double* part, int npart, float
     if (i < H * w4) {
         const int y = i / w4;
         const int q = i - y * w4;
-        const float4 m = reinterpret_cast<const float4*>(io->target)[i];
+        const float4 m = reinterpret_cast<const float4*>(io->target + mb)[i];
         float4 o;
         o.x = (float)((double)m.x * inv);
         o.y = (float)((double)m.y * inv);
@@ -115,13 +120,15 @@ k_target_tile(const PmIo* io, int H, int W, const double* part, int npart, float
 // part[e * stride + i].
 // With an illumination p (pn2 = ||p||^2 on the device) the errors are
 // relative to ||p||: E_F = sqrt(sum N / ||p||^2), G = sqrt(sum / ||p||^2).
+// Mask blockIdx.y of a uniform batch (0 for one mask): partials from
+// part + blockIdx.y part_bstride, entries to io->hist + blockIdx.y gridDim.x.
 __global__ void __launch_bounds__(kAuxThreads)
 k_finalize(const double* part, int stride, int n_col, int n_row, double invN,
-           const PmIo* io, int first_entry, int entry_step, const double* pn2) {
+           const PmIo* io, int first_entry, int entry_step, const double* pn2, size_t part_bstride) {
     __shared__ double red[red_slots(kAuxThreads)];
     const int e = first_entry + blockIdx.x * entry_step;
     const int nwg = (e & 1) ? n_row : n_col;
-    const double* p = part + (size_t)e * stride;
+    const double* p = part + (size_t)blockIdx.y * part_bstride + (size_t)e * stride;
     double acc = 0.0;
     for (int i = threadIdx.x; i < nwg; i += kAuxThreads) acc += p[i];
     const double tot = block_sum<kAuxThreads>(acc, red);
@@ -129,7 +136,8 @@ k_finalize(const double* part, int stride, int n_col, int n_row, double invN,
         double* hist = io->hist;
         const double ef2 = pn2 == nullptr ? 1.0 : 1.0 / (invN * pn2[0]);
         const double g2 = pn2 == nullptr ? invN : 1.0 / pn2[0];
-        if (hist != nullptr) hist[blockIdx.x] = (e & 1) ? sqrt(tot * g2) : sqrt(tot * ef2);
+        if (hist != nullptr)
+            hist[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = (e & 1) ? sqrt(tot * g2) : sqrt(tot * ef2);
     }
 }
 
@@ -454,23 +462,26 @@ hipError_t launch_set_io(PmIo* io, const PmIo& val, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_norm_partial(const PmIo* io, int n, double* part, int grid, hipStream_t s) {
-    k_norm_partial<<<grid, kAuxThreads, 0, s>>>(io, n, part);
+hipError_t launch_norm_partial(const PmIo* io, int n, double* part, int grid, hipStream_t s, int batch) {
+    if (batch < 1) return hipErrorInvalidValue;
+    k_norm_partial<<<dim3(grid, batch), kAuxThreads, 0, s>>>(io, n, part);
     return hipGetLastError();
 }
 
 hipError_t launch_target_tile(const PmIo* io, int H, int W, const double* part, int npart,
-                              float* mhat, hipStream_t s, const double* pn2) {
+                              float* mhat, hipStream_t s, const double* pn2, int batch) {
+    if (batch < 1) return hipErrorInvalidValue;
     const int grid = (H * (W / 4) + kAuxThreads - 1) / kAuxThreads;
-    k_target_tile<<<grid, kAuxThreads, 0, s>>>(io, H, W, part, npart, mhat, pn2);
+    k_target_tile<<<dim3(grid, batch), kAuxThreads, 0, s>>>(io, H, W, part, npart, mhat, pn2);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const double* part, int stride, int n_col, int n_row, double invN,
                            const PmIo* io, int first_entry, int count, hipStream_t s, int entry_step,
-                           const double* pn2) {
-    k_finalize<<<count, kAuxThreads, 0, s>>>(part, stride, n_col, n_row, invN, io, first_entry, entry_step,
-                                             pn2);
+                           const double* pn2, int batch, size_t part_bstride) {
+    if (batch < 1) return hipErrorInvalidValue;
+    k_finalize<<<dim3(count, batch), kAuxThreads, 0, s>>>(part, stride, n_col, n_row, invN, io, first_entry,
+                                                          entry_step, pn2, part_bstride);
     return hipGetLastError();
 }
 

@@ -62,6 +62,8 @@ enum : int {
     R_ADAM = 32768,     // intensity-loss gradient, Adam update of the phase (and with R_FWD the
                         // row FFT of exp(i phase) of the updated phase)
     ROUT_TILED = 65536, // write the tiled iterate as read, no transform (exchange probe)
+    R_MANY = 131072,    // one of a uniform batch of masks (blockIdx.y): iterate, phases and
+                        // partials offset by the mask's index (phasemask_solve_many)
 };
 constexpr int ROW_INIT = RIN_PHASE | R_FWD;
 constexpr int ROW_ITER = RIN_TILED | R_INV | R_PS | R_FWD;
@@ -94,6 +96,14 @@ constexpr int ROW_ADAM_LAST = RIN_TILED | R_INV | R_ADAM;
 // Exchange probe: the passes' loads and stores of the iterate with nothing
 // between them (each element written back where it was read).
 constexpr int ROW_COPY = RIN_TILED | ROUT_TILED;
+// Uniform batches of masks (phasemask_solve_many): the phase-in, phase-out
+// solve modes, one mask per blockIdx.y.
+constexpr int ROW_INIT_MANY = ROW_INIT | R_MANY;
+constexpr int ROW_ITER_MANY = ROW_ITER | R_MANY;
+constexpr int ROW_ITER_NE_MANY = ROW_ITER_NE | R_MANY;
+constexpr int ROW_LAST_MANY = ROW_LAST | R_MANY;
+constexpr int ROW_LAST_FWD_MANY = ROW_LAST_FWD | R_MANY;
+constexpr int ROW_LAST_NE_MANY = ROW_LAST_NE | R_MANY;
 
 // Column-pass modes (bit sets).
 enum : int {
@@ -110,6 +120,7 @@ enum : int {
     C_BIT = 1024,     // load the 1-bit target pattern (lit where m^2 / max m^2 > t_dark)
     C_POW = 2048,     // store |U|^2 / N (float, strip-tiled) and the work-group maximum
     C_ITILED = 4096,  // C_LOSS: the target intensity is strip-tiled (else natural layout)
+    C_MANY = 8192,    // one of a uniform batch of masks (blockIdx.y), as R_MANY
 };
 constexpr int COL_ITER = CIN_TILED | C_FWD | C_PROJ | C_INV | COUT_TILED;
 constexpr int COL_ERR = CIN_TILED | C_FWD | C_ERR;
@@ -124,6 +135,9 @@ constexpr int COL_POW = CIN_TILED | C_FWD | C_POW;
 constexpr int COL_LOSS_T = COL_LOSS | C_ITILED;
 constexpr int COL_LOSS_ONLY_T = CIN_TILED | C_FWD | C_LOSS | C_ITILED;
 constexpr int COL_COPY = CIN_TILED | COUT_TILED;
+constexpr int COL_ITER_MANY = COL_ITER | C_MANY;
+constexpr int COL_ITER_NE_MANY = COL_ITER_NE | C_MANY;
+constexpr int COL_ERR_MANY = COL_ERR | C_MANY;
 
 struct RowParams {
     float2* X;             // tiled iterate
@@ -143,6 +157,10 @@ struct RowParams {
     float* am;
     float* av;
     float adam_step, adam_bc2s, beta1, beta2, eps;
+    // R_MANY: masks in the launch (grid.y) and doubles between two masks'
+    // partials
+    int nb;
+    size_t part_bstride;
 };
 
 struct ColParams {
@@ -161,6 +179,8 @@ struct ColParams {
     double t_dark;         // C_BIT: lit threshold on the normalised intensity
     float* pw;             // C_POW: |U|^2 / N, strip-tiled
     int spread;            // launch at most one work-group per CU (grid fits the CUs)
+    int nb;                // C_MANY: masks in the launch (grid.y)
+    size_t part_bstride;   // C_MANY: doubles between two masks' partials
 };
 
 // Intensity-loss passes over a batch of same-size phases (blockIdx.y = sample).
@@ -301,16 +321,21 @@ hipError_t launch_batch_finalize(const BatchIo* io, const BatchMask* masks, int 
 
 // Small kernels (pm_aux.hip).
 hipError_t launch_set_io(PmIo* io, const PmIo& val, hipStream_t s);
-hipError_t launch_norm_partial(const PmIo* io, int n, double* part, int grid, hipStream_t s);
+// With batch > 1 (a uniform batch of masks, one per grid.y): mask b's target
+// is io->target + b n, its partials part + b grid.
+hipError_t launch_norm_partial(const PmIo* io, int n, double* part, int grid, hipStream_t s, int batch = 1);
 // mhat = m / ||m||, or with an illumination (pn2 = device pointer to ||p||^2)
-// m ||p|| / (||m|| sqrt(N)), strip-tiled.
+// m ||p|| / (||m|| sqrt(N)), strip-tiled.  Batches as launch_norm_partial
+// (mask b's partials at part + b npart, its mhat at mhat + b H W).
 hipError_t launch_target_tile(const PmIo* io, int H, int W, const double* part, int npart,
-                              float* mhat, hipStream_t s, const double* pn2 = nullptr);
+                              float* mhat, hipStream_t s, const double* pn2 = nullptr, int batch = 1);
 // History entries first_entry + k * entry_step, k < count, into hist[k].
 // pn2: ||p||^2 on the device with an illumination, else null (p = 1).
+// With batch > 1, mask b's partials start at part + b part_bstride and its
+// entries go to io->hist + b count.
 hipError_t launch_finalize(const double* part, int stride, int n_col, int n_row, double invN,
                            const PmIo* io, int first_entry, int count, hipStream_t s, int entry_step = 1,
-                           const double* pn2 = nullptr);
+                           const double* pn2 = nullptr, int batch = 1, size_t part_bstride = 0);
 // Illumination set-up: p (natural layout [H][W]) copied to the strip-tiled
 // `illum`, and ||p||^2 (FP64, fixed summation order) to *pn2; `part` holds
 // `grid` doubles of scratch.

@@ -608,6 +608,13 @@ k_col(ColParams a) {
     constexpr int NT = G * LineShape<H>::T;
     __shared__ __align__(16) float2 lds[LdsPlan<H, G, 2, col_lds_layout(H)>::FLOATS2];
     __shared__ double red[red_slots(NT)];
+    if constexpr ((MODE & C_MANY) != 0) {
+        // mask blockIdx.y of a uniform batch: its iterate, target, partials
+        const size_t mb = (size_t)blockIdx.y * H * a.W;
+        a.X += mb;
+        a.mhat += mb;
+        a.part += blockIdx.y * a.part_bstride;
+    }
     col_body<H, LineShape<H>::P, G, MODE, col_lanes_ok(H, LineShape<H>::P, G), 2, col_lds_layout(H)>(
         a, pass_tile<G>(blockIdx.x, gridDim.x), a.part + blockIdx.x * red_slots(NT), lds, red);
 }
@@ -632,6 +639,16 @@ k_row(RowParams a) {
     if constexpr ((MODE & ROUT_PHASE) != 0) pout = a.io->phase_out;
     if constexpr ((MODE & RIN_FIELD) != 0) a.nat_in = a.io->field_in;
     if constexpr ((MODE & ROUT_FIELD) != 0) a.nat_out = a.io->field_out;
+    if constexpr ((MODE & R_MANY) != 0) {
+        // mask blockIdx.y of a uniform batch: its iterate, phases, partials
+        static_assert((MODE & (R_ILLUM | R_RAAR | R_STOREZ | RIN_NAT | ROUT_NAT | RIN_FIELD | ROUT_FIELD)) == 0,
+                      "uniform batches: the phase-in, phase-out solve modes");
+        const size_t mb = (size_t)blockIdx.y * a.H * W;
+        a.X += mb;
+        if (pin != nullptr) pin += mb;
+        if (pout != nullptr) pout += mb;
+        a.part += blockIdx.y * a.part_bstride;
+    }
     row_body<W, LineShape<W>::P, G, field_as_nat(MODE), row_lanes_ok(W, LineShape<W>::P, G), 2, row_lds_layout(W)>(
         a, pass_tile<G>(blockIdx.x, gridDim.x) * G, pin, pout, a.part + blockIdx.x * red_slots(NT), lds, red);
 }

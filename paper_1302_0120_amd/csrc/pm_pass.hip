@@ -36,10 +36,12 @@ hipError_t launch(void (*kern)(Params), int grid, int block, hipStream_t s, hipE
             if (e != hipSuccess) return e;
         }
     }
+    // grid.y: the masks of a uniform batch (R_MANY / C_MANY modes), else 1
+    const dim3 g(grid, p.nb > 1 ? p.nb : 1);
     if (ev0 != nullptr || ev1 != nullptr) {
-        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), dyn, s, ev0, ev1, 0, p);
+        hipExtLaunchKernelGGL(kern, g, dim3(block), dyn, s, ev0, ev1, 0, p);
     } else {
-        kern<<<grid, block, dyn, s>>>(p);
+        kern<<<g, block, dyn, s>>>(p);
     }
     return hipGetLastError();
 }
@@ -67,6 +69,12 @@ hipError_t launch_rows(int mode, const RowParams& p, int grid, hipStream_t s, hi
         case ROW_INIT_FIELD: return launch(k_row<PM_L, ROW_INIT_FIELD, G>, grid, block, s, ev0, ev1, p);
         case ROW_COPY_FIELD: return launch(k_row<PM_L, ROW_COPY_FIELD, G>, grid, block, s, ev0, ev1, p);
         case ROW_COPY: return launch(k_row<PM_L, ROW_COPY, G>, grid, block, s, ev0, ev1, p);
+        case ROW_INIT_MANY: return launch(k_row<PM_L, ROW_INIT_MANY, G>, grid, block, s, ev0, ev1, p);
+        case ROW_ITER_MANY: return launch(k_row<PM_L, ROW_ITER_MANY, G>, grid, block, s, ev0, ev1, p);
+        case ROW_ITER_NE_MANY: return launch(k_row<PM_L, ROW_ITER_NE_MANY, G>, grid, block, s, ev0, ev1, p);
+        case ROW_LAST_MANY: return launch(k_row<PM_L, ROW_LAST_MANY, G>, grid, block, s, ev0, ev1, p);
+        case ROW_LAST_FWD_MANY: return launch(k_row<PM_L, ROW_LAST_FWD_MANY, G>, grid, block, s, ev0, ev1, p);
+        case ROW_LAST_NE_MANY: return launch(k_row<PM_L, ROW_LAST_NE_MANY, G>, grid, block, s, ev0, ev1, p);
         default: return hipErrorInvalidValue;
     }
 }
@@ -103,6 +111,9 @@ hipError_t PM_CAT(launch_col_, PM_L)(int mode, const ColParams& p, int grid, hip
         case COL_INIT_BIT: return launch(k_col<PM_L, COL_INIT_BIT>, grid, block, s, ev0, ev1, p);
         case COL_POW: return launch(k_col<PM_L, COL_POW>, grid, block, s, ev0, ev1, p);
         case COL_COPY: return launch(k_col<PM_L, COL_COPY>, grid, block, s, ev0, ev1, p);
+        case COL_ITER_MANY: return launch(k_col<PM_L, COL_ITER_MANY>, grid, block, s, ev0, ev1, p);
+        case COL_ITER_NE_MANY: return launch(k_col<PM_L, COL_ITER_NE_MANY>, grid, block, s, ev0, ev1, p);
+        case COL_ERR_MANY: return launch(k_col<PM_L, COL_ERR_MANY>, grid, block, s, ev0, ev1, p);
         default: return hipErrorInvalidValue;
     }
 }

@@ -1,0 +1,90 @@
+"""GPU tests of uniform batches (phasemask_solve_many): every mask's phases
+and error history are bitwise those of the one-mask solve of that mask
+(same kernels, same summation order), at power-of-two and panel sizes, with
+and without a history and graphs, growing and shrinking the batch; and the
+argument checks."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import gs
+from paper_1302_0120_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pmb():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1302_0120_amd import binding
+    return binding
+
+
+def _batch(h, w, count, seed):
+    ms, ps = [], []
+    for b in range(count):
+        rng = np.random.default_rng(seed + b)
+        ms.append(synth.spot_amplitude(h, w, int(rng.integers(1, 60)), 2.0, 0.5, 1.0, rng))
+        ps.append(synth.uniform_phase(h, w, rng))
+    return np.stack(ms), np.stack(ps)
+
+
+@pytest.mark.parametrize("shape,count,n_iter", [((600, 800), 3, 5), ((1024, 1024), 2, 4), ((64, 64), 5, 10),
+                                                ((256, 128), 3, 0)])
+def test_many_equals_one_mask_solves(pmb, shape, count, n_iter):
+    h, w = shape
+    print(f"solve_many {shape} x {count}, {n_iter} iterations", flush=True)
+    m, p = _batch(h, w, count, 7 + h)
+    md, pd = torch.from_numpy(m).cuda(), torch.from_numpy(p).cuda()
+    for flags in (0, pmb.PM_FLAG_NO_GRAPH):
+        plan = pmb.PhaseMask(h, w, flags=flags)
+        out, hist = plan.solve_many(md, pd, n_iter)
+        out_ne, none = plan.solve_many(md, pd, n_iter, history=False)
+        assert none is None
+        for b in range(count):
+            ref, href = plan.solve(md[b], pd[b], n_iter)
+            assert torch.equal(out[b], ref), (b, flags)
+            assert torch.equal(out_ne[b], ref), (b, flags)
+            assert torch.equal(hist[b], href), (b, flags)
+
+
+def test_many_against_oracle_and_grow_shrink(pmb):
+    """One iteration per mask against the oracle (1e-5), then a larger and a
+    smaller batch through the same plan."""
+    h, w = 128, 128
+    plan = pmb.PhaseMask(h, w)
+    for count in (2, 6, 3):
+        m, p = _batch(h, w, count, 100 + count)
+        out, hist = plan.solve_many(torch.from_numpy(m).cuda(), torch.from_numpy(p).cuda(), 1)
+        for b in range(count):
+            ref = gs.gs_solve(m[b], p[b], 1)
+            u = np.exp(1j * out[b].cpu().numpy().astype(np.float64))
+            err = np.linalg.norm(u - ref["u"]) / np.linalg.norm(ref["u"])
+            assert err <= 1e-5, (count, b, err)
+            rel = np.abs(hist[b].cpu().numpy() - ref["history"]) / ref["history"]
+            assert rel.max() <= 1e-5, (count, b, rel)
+
+
+def test_many_argument_errors(pmb):
+    h, w = 64, 64
+    plan = pmb.PhaseMask(h, w)
+    m, p = _batch(h, w, 2, 3)
+    md, pd = torch.from_numpy(m).cuda(), torch.from_numpy(p).cuda()
+    out = torch.empty_like(pd)
+    lib = pmb.lib
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+    assert lib.phasemask_solve_many(plan._h, 0, ptr(md), ptr(pd), 3, ptr(out), None) == -1
+    assert lib.phasemask_solve_many(plan._h, 2, None, ptr(pd), 3, ptr(out), None) == -1
+    assert lib.phasemask_solve_many(plan._h, 2, ptr(md), ptr(pd), -1, ptr(out), None) == -1
+    assert lib.phasemask_solve_many(plan._h, 2, ptr(md), ptr(pd), 3, ptr(md), None) == -1  # out on the target
+    plan.set_illumination(torch.ones((h, w), dtype=torch.float32, device="cuda"))
+    assert lib.phasemask_solve_many(plan._h, 2, ptr(md), ptr(pd), 3, ptr(out), None) == -2
+    plan.set_illumination(None)
+    assert lib.phasemask_solve_many(plan._h, 2, ptr(md), ptr(pd), 3, ptr(out), None) == 0
+    bp = pmb.BatchedPhaseMask([(64, 64)])
+    assert lib.phasemask_solve_many(bp._h, 2, ptr(md), ptr(pd), 3, ptr(out), None) == -5
+    torch.cuda.synchronize()
