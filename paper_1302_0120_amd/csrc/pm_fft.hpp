@@ -338,11 +338,20 @@ __host__ __device__ constexpr int lds_layout(int L) { return lds_pad_scheme(L) *
 #ifndef PM_ROW_LDS_LAYOUT
 #define PM_ROW_LDS_LAYOUT -1
 #endif
+// The row swizzle also at 512 points (two-row tiles, same exchange patterns:
+// 512 row pass conflict-free; 512^2 x 50 solve 0.4150 -> 0.4128 ms).
+#ifndef PM_ROW_SWZ_512
+#define PM_ROW_SWZ_512 1
+#endif
 __host__ __device__ constexpr int row_lds_layout(int L) {
     return (PM_ROW_LDS_LAYOUT >= 0 && L <= 1024 && (L & (L - 1)) == 0) ? PM_ROW_LDS_LAYOUT
-         : L == 1024 ? 4 * 64 + 8
-                     : lds_layout(L);
+         : (L == 1024 || (L == 512 && PM_ROW_SWZ_512)) ? 4 * 64 + 8
+                                                       : lds_layout(L);
 }
+// The intensity-loss row passes keep the unswizzled layout at 512: there the
+// swizzle made the 16 x 512^2 Adam solve 5% slower (0.0475 -> 0.0499 ms per
+// step).
+__host__ __device__ constexpr int adj_row_lds_layout(int L) { return L == 512 ? lds_layout(L) : row_lds_layout(L); }
 // Schemes 4 and 5 are swizzles without spare slots: element i of a line
 // sits at i ^ mask(i), mask(i) = (bit 4 of i) << 2 ^ key (scheme 4) or
 // (bits 3-4 of i) << 1 ^ key (scheme 5), where `key` (0, 2, 4 or 6) is a
@@ -372,14 +381,17 @@ __host__ __device__ constexpr int lds_index(int lay, int i, int key) {
 #ifndef PM_COL_LINES_1024
 #define PM_COL_LINES_1024 4
 #endif
+#ifndef PM_COL_LINES_512
+#define PM_COL_LINES_512 4
+#endif
 
 // Layout of the one-mask column pass (PM_COL_LDS_LAYOUT overrides it at
 // 1024).  Half strips at 1024 hold two lines whose lanes alternate, as the
 // two-row tiles of the row pass do, and take the row pass's swizzle.
 __host__ __device__ constexpr int col_lds_layout(int L) {
     return (PM_COL_LDS_LAYOUT >= 0 && L == 1024) ? PM_COL_LDS_LAYOUT
-         : (L == 1024 && PM_COL_LINES_1024 == 2) ? 4 * 64 + 8
-                                                 : lds_layout(L);
+         : ((L == 1024 && PM_COL_LINES_1024 == 2) || (L == 512 && PM_COL_LINES_512 == 2)) ? 4 * 64 + 8
+                                                                                          : lds_layout(L);
 }
 __host__ __device__ constexpr int lds_line_len_lay(int L, int lay) { return lds_pad_lay(lay, L) + lay % 64; }
 __host__ __device__ constexpr int lds_pad(int L, int i) { return lds_pad_lay(lds_layout(L), i); }
@@ -958,7 +970,10 @@ __host__ __device__ constexpr int row_lines(int W) {
 // (two work-groups per CU instead of one), 128^2 -1.7%, 256^2 -1%, but 512^2
 // +4.5%, 1024^2 +6%, 2048^2 +4%, so only 128, 256 and 4096 take half strips.
 __host__ __device__ constexpr int col_lines(int H) {
-    return (H == 128 || H == 256 || H == 4096 || (H == 1024 && PM_COL_LINES_1024 == 2)) ? 2 : kC;
+    return (H == 128 || H == 256 || H == 4096 || (H == 1024 && PM_COL_LINES_1024 == 2) ||
+            (H == 512 && PM_COL_LINES_512 == 2))
+               ? 2
+               : kC;
 }
 
 // A second, taller row tile for 1920-point rows (0: none).  A 1920-point

@@ -662,7 +662,7 @@ template <int W, int MODE>
 __global__ void __launch_bounds__(row_lines(W) * LineShape<W>::T)
 k_row_adj(AdjParams p) {
     constexpr int NT = row_lines(W) * LineShape<W>::T;
-    __shared__ __align__(16) float2 lds[LdsPlan<W, row_lines(W), 2, row_lds_layout(W)>::FLOATS2];
+    __shared__ __align__(16) float2 lds[LdsPlan<W, row_lines(W), 2, adj_row_lds_layout(W)>::FLOATS2];
     __shared__ double red[red_slots(NT)];
     const size_t n = (size_t)p.H * W;
     const size_t b = blockIdx.y;
@@ -689,7 +689,7 @@ k_row_adj(AdjParams p) {
         a.eps = p.eps;
     }
     row_body<W, LineShape<W>::P, row_lines(W), MODE, row_lanes_ok(W, LineShape<W>::P, row_lines(W)), 2,
-             row_lds_layout(W)>(a, pass_tile<row_lines(W)>(blockIdx.x, gridDim.x) * row_lines(W), p.phase + b * n,
+             adj_row_lds_layout(W)>(a, pass_tile<row_lines(W)>(blockIdx.x, gridDim.x) * row_lines(W), p.phase + b * n,
                                 out, nullptr, lds, red);
 }
 
