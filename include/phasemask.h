@@ -97,7 +97,11 @@ pm_status phasemask_create(pm_handle* out, int height, int width,
                            unsigned flags, void* stream);
 
 /* Release the plan and its workspace.  Synchronises the handle's stream
- * first.  Destroying NULL returns PM_EINVAL. */
+ * first.  Destroying NULL returns PM_EINVAL.  The library keeps a registry
+ * of live plans: every call given a handle that is not one (destroyed, or
+ * never returned by a create call) returns PM_ESTATE without touching it --
+ * unless a later plan happens to occupy the same address -- and the size
+ * queries return 0 (phasemask_batch_schedule -1). */
 pm_status phasemask_destroy(pm_handle h);
 
 /*

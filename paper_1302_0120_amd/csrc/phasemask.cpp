@@ -13,6 +13,7 @@
 #include <fstream>
 #include <map>
 #include <mutex>
+#include <set>
 #include <sstream>
 #include <list>
 #include <new>
@@ -270,9 +271,37 @@ void free_plan(pm_plan* h) {
     delete h;
 }
 
-pm_status check_handle(pm_plan* h, bool batched = false) {
+// Plans returned by phasemask_create / _create_batched and not yet destroyed.
+// Every entry point checks its handle here before touching it, so a destroyed
+// handle (or any other pointer) is refused with PM_ESTATE instead of being
+// dereferenced -- unless a later plan happens to occupy the same address.
+std::mutex g_live_mu;
+std::set<const pm_plan*> g_live;
+
+void plan_register(const pm_plan* h) {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.insert(h);
+}
+bool plan_unregister(const pm_plan* h) {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    return g_live.erase(h) == 1;
+}
+bool plan_live(const pm_plan* h) {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    return g_live.count(h) == 1;
+}
+
+// A live plan of either kind.
+pm_status check_any(pm_plan* h) {
     if (h == nullptr) return fail(PM_EINVAL, "null handle");
+    if (!plan_live(h)) return fail(PM_ESTATE, "not a live plan (destroyed, or never created)");
     if (h->dead) return fail(PM_ESTATE, "handle is in an unusable state");
+    return PM_OK;
+}
+
+pm_status check_handle(pm_plan* h, bool batched = false) {
+    pm_status st = check_any(h);
+    if (st != PM_OK) return st;
     if (h->batched != batched)
         return fail(PM_ESTATE, batched ? "handle is not a batched plan" : "handle is a batched plan");
     return PM_OK;
@@ -959,19 +988,21 @@ pm_status phasemask_create(pm_handle* out, int height, int width, unsigned flags
                      "workspace %zu bytes\n", height, width, line(width).c_str(), h->nwg_row,
                      h->rows, line(height).c_str(), h->nwg_col, h->ws_bytes);
     }
+    plan_register(h);
     *out = h;
     return PM_OK;
 }
 
 pm_status phasemask_destroy(pm_handle h) {
     if (h == nullptr) return fail(PM_EINVAL, "null handle");
+    if (!plan_unregister(h)) return fail(PM_ESTATE, "not a live plan (destroyed, or never created)");
     (void)hipStreamSynchronize(h->stream);
     free_plan(h);
     return PM_OK;
 }
 
 pm_status phasemask_set_stream(pm_handle h, void* stream) {
-    pm_status st = check_handle(h, h != nullptr && h->batched);
+    pm_status st = check_any(h);
     if (st != PM_OK) return st;
     const hipStream_t ns = (hipStream_t)stream;
     if (ns == h->stream) return PM_OK;
@@ -1025,10 +1056,10 @@ pm_status phasemask_set_illumination(pm_handle h, const float* illumination) {
     return PM_OK;
 }
 
-size_t phasemask_workspace_bytes(pm_handle h) { return h ? h->ws_bytes : 0; }
+size_t phasemask_workspace_bytes(pm_handle h) { return (h != nullptr && plan_live(h)) ? h->ws_bytes : 0; }
 
 size_t phasemask_workspace_size(pm_handle h, int n_iter) {
-    if (h == nullptr || h->dead || h->batched || n_iter < 0) return 0;
+    if (h == nullptr || !plan_live(h) || h->dead || h->batched || n_iter < 0) return 0;
     return ws_layout(h).part_off + std::max(min_partial_entries(h), 2 * (size_t)n_iter + 1) * (size_t)h->stride *
                                        sizeof(double);
 }
@@ -1541,6 +1572,7 @@ pm_status phasemask_create_batched(pm_handle* out, int count, const int* heights
     h->ws_bytes = off + npart * sizeof(double) + prep.size() * (sizeof(double) + sizeof(pm::BatchTask)) +
                   (max_col + max_row) * sizeof(pm::BatchTask) + count * (sizeof(pm::BatchMask) + sizeof(int)) +
                   sizeof(pm::BatchIo) + tw.size() * sizeof(float2);
+    plan_register(h);
     *out = h;
     return PM_OK;
 }
@@ -1826,10 +1858,10 @@ extern "C" int phasemask_timeline_clock_khz() {
 }
 #endif
 
-int phasemask_batch_schedule(pm_handle h) { return (h != nullptr && h->batched) ? h->sched : -1; }
+int phasemask_batch_schedule(pm_handle h) { return (h != nullptr && plan_live(h) && h->batched) ? h->sched : -1; }
 
 pm_status phasemask_batch_config(pm_handle h, int* schedule, int* chains, size_t* group_bytes) {
-    pm_status st = check_handle(h, h != nullptr && h->batched);
+    pm_status st = check_any(h);
     if (st != PM_OK) return st;
     if (!h->batched) return fail(PM_ESTATE, "handle is not a batched plan");
     if (schedule) *schedule = h->sched;

@@ -92,3 +92,26 @@ def test_batched_host_side_argument_errors(lib):
     lib.phasemask_solve_batched.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                             ctypes.c_void_p, ctypes.c_void_p]
     assert lib.phasemask_solve_batched(None, None, None, 1, None, None) == -1
+
+
+def test_handles_that_are_not_live_plans(lib):
+    """A pointer that is not a live plan (never created, or destroyed) is
+    refused with PM_ESTATE before it is dereferenced; the size queries answer
+    0 / -1.  (The GPU tests destroy real plans and call them again.)"""
+    bogus = ctypes.c_void_p(0x12345678)
+    f = ctypes.c_void_p(0x1000)
+    lib.phasemask_solve.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int] + [ctypes.c_void_p] * 2
+    assert lib.phasemask_solve(bogus, f, f, 3, f, None) == -5
+    lib.phasemask_destroy.argtypes = [ctypes.c_void_p]
+    assert lib.phasemask_destroy(bogus) == -5
+    lib.phasemask_set_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.phasemask_set_stream(bogus, None) == -5
+    lib.phasemask_batch_config.argtypes = [ctypes.c_void_p] * 4
+    assert lib.phasemask_batch_config(bogus, None, None, None) == -5
+    lib.phasemask_workspace_bytes.argtypes = [ctypes.c_void_p]
+    lib.phasemask_workspace_bytes.restype = ctypes.c_size_t
+    assert lib.phasemask_workspace_bytes(bogus) == 0
+    lib.phasemask_batch_schedule.argtypes = [ctypes.c_void_p]
+    assert lib.phasemask_batch_schedule(bogus) == -1
+    lib.phasemask_last_error.restype = ctypes.c_char_p
+    assert b"not a live plan" in lib.phasemask_last_error()

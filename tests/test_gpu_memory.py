@@ -85,3 +85,21 @@ def test_plans_give_back_their_memory(pmb):
         free = _free()
         print(f"round {r}: device free memory {free} (start {free0})", flush=True)
         assert free == free0, (r, free0 - free)
+
+
+def test_destroyed_handle_is_refused(pmb):
+    """After phasemask_destroy the handle is no longer a live plan: calls with
+    it, and a second destroy, return PM_ESTATE instead of touching freed
+    memory; a plan created afterwards works."""
+    import ctypes
+    h = ctypes.c_void_p()
+    assert pmb.lib.phasemask_create(ctypes.byref(h), 64, 64, 0, None) == 0
+    assert pmb.lib.phasemask_destroy(h) == 0
+    f = ctypes.c_void_p(0x1000)
+    assert pmb.lib.phasemask_solve(h, f, f, 3, f, None) == -5
+    assert pmb.lib.phasemask_destroy(h) == -5
+    assert pmb.lib.phasemask_workspace_bytes(h) == 0
+    plan = pmb.PhaseMask(64, 64)
+    m = torch.ones((64, 64), dtype=torch.float32, device="cuda")
+    out, _ = plan.solve(m, torch.zeros_like(m), 2)
+    assert torch.isfinite(out).all()
