@@ -383,7 +383,8 @@ int phasemask_batch_schedule(pm_handle h);
 
 /* Configuration a batched plan runs with: FFT schedule (picked at creation
  * by the plan's tuner, which times every schedule on the plan's own
- * buffers, cached per architecture and set of sizes, in-process and in the
+ * buffers and keeps the lowest-numbered one unless a later schedule is more
+ * than 2% faster, cached per architecture and set of sizes, in-process and in the
  * file named by PHASEMASK_TUNE_CACHE; PHASEMASK_SCHEDULE forces one,
  * PM_FLAG_NO_TUNE takes 0), number of concurrent chains of launches
  * (PHASEMASK_CHAINS, default 4) and the cache budget of one group of masks
