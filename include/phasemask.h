@@ -191,8 +191,9 @@ pm_status phasemask_solve(pm_handle h, const float* target_amplitude,
  * first use for the largest batch and history seen, which synchronises the
  * stream and drops the captured graphs; without PM_FLAG_NO_GRAPH the solve
  * is one captured graph per (n_iter, batch, history).
- * Errors: PM_EINVAL for a NULL array, batch outside [1, 65535], n_iter
- * outside [0, 2^20], misalignment or overlapping arrays (out_phase with the
+ * Errors: PM_EINVAL for a NULL array, batch outside [1, 65535] or with
+ * batch * height * width >= 2^31, n_iter outside [0, 2^20], misalignment or
+ * overlapping arrays (out_phase with the
  * target, err_history with any array); PM_EUNSUPPORTED (illumination set);
  * PM_ESTATE (batched handle); PM_ENOMEM; PM_EDEVICE.
  */

@@ -1209,6 +1209,8 @@ pm_status phasemask_solve_many(pm_handle h, int batch, const float* target_ampli
     pm_status st = check_handle(h);
     if (st != PM_OK) return st;
     if (batch < 1 || batch > 65535) return fail(PM_EINVAL, "batch must be in [1, 65535]");
+    if ((long long)h->N * batch > 0x7fffffffLL)
+        return fail(PM_EINVAL, "batch * height * width must be below 2^31 pixels");
     if (!target_amplitude || !init_phase || !out_phase) return fail(PM_EINVAL, "null array argument");
     if (n_iter < 0 || n_iter > (1 << 20)) return fail(PM_EINVAL, "n_iter must be in [0, 2^20]");
     if (misaligned(target_amplitude, 16)) return fail(PM_EINVAL, "target must be 16-byte aligned");

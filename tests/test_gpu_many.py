@@ -80,6 +80,8 @@ def test_many_argument_errors(pmb):
     assert lib.phasemask_solve_many(plan._h, 0, ptr(md), ptr(pd), 3, ptr(out), None) == -1
     assert lib.phasemask_solve_many(plan._h, 2, None, ptr(pd), 3, ptr(out), None) == -1
     assert lib.phasemask_solve_many(plan._h, 2, ptr(md), ptr(pd), -1, ptr(out), None) == -1
+    big = pmb.PhaseMask(1024, 1024)  # 2048 masks of 2^20 pixels: 2^31 pixels
+    assert lib.phasemask_solve_many(big._h, 2048, ptr(md), ptr(pd), 1, ptr(out), None) == -1
     assert lib.phasemask_solve_many(plan._h, 2, ptr(md), ptr(pd), 3, ptr(md), None) == -1  # out on the target
     plan.set_illumination(torch.ones((h, w), dtype=torch.float32, device="cuda"))
     assert lib.phasemask_solve_many(plan._h, 2, ptr(md), ptr(pd), 3, ptr(out), None) == -2
