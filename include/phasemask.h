@@ -184,9 +184,9 @@ pm_status phasemask_solve(pm_handle h, const float* target_amplitude,
  *   err_history       double[batch][2 n_iter + 1] or NULL, mask b's history
  *                     as phasemask_solve writes it.
  * Each mask's phases and history are bitwise those of phasemask_solve on
- * that mask alone (same kernels and summation order).  The illumination of
- * phasemask_set_illumination does not apply (p = 1; PM_EUNSUPPORTED while one
- * is set).  The plan keeps the batch's iterates, rescaled targets and
+ * that mask alone (same kernels and summation order), also with the
+ * illumination of phasemask_set_illumination, which every mask of the batch
+ * shares.  The plan keeps the batch's iterates, rescaled targets and
  * partial sums (12 bytes per pixel and mask, plus partials), allocated on
  * first use for the largest batch and history seen, which synchronises the
  * stream and drops the captured graphs; without PM_FLAG_NO_GRAPH the solve
@@ -194,8 +194,8 @@ pm_status phasemask_solve(pm_handle h, const float* target_amplitude,
  * Errors: PM_EINVAL for a NULL array, batch outside [1, 65535] or with
  * batch * height * width >= 2^31, n_iter outside [0, 2^20], misalignment or
  * overlapping arrays (out_phase with the
- * target, err_history with any array); PM_EUNSUPPORTED (illumination set);
- * PM_ESTATE (batched handle); PM_ENOMEM; PM_EDEVICE.
+ * target, err_history with any array); PM_ESTATE (batched handle);
+ * PM_ENOMEM; PM_EDEVICE.
  */
 pm_status phasemask_solve_many(pm_handle h, int batch, const float* target_amplitude,
                                const float* init_phase, int n_iter,

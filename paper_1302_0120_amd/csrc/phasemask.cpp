@@ -506,7 +506,6 @@ pm_status enqueue_many(pm_plan* h, hipStream_t s, int n_iter, bool hist, int bat
     auto pe = [&](int e) { return h->m_part + (size_t)e * h->stride; };
     pm::RowParams rp = row_params(h, nullptr);
     rp.X = h->m_X;
-    rp.illum = nullptr;
     rp.nb = batch;
     rp.part_bstride = bstride;
     rp.spread = (long)h->nwg_row * batch <= h->num_cu;
@@ -531,21 +530,21 @@ pm_status enqueue_many(pm_plan* h, hipStream_t s, int n_iter, bool hist, int bat
         if (!hist) return PM_OK;
     }
     PM_TRY(pm::launch_norm_partial(h->io, h->N, h->m_partm, kNormGrid, s, batch), "target norm");
-    PM_TRY(pm::launch_target_tile(h->io, h->H, h->W, h->m_partm, kNormGrid, h->m_mhat, s, nullptr, batch),
+    PM_TRY(pm::launch_target_tile(h->io, h->H, h->W, h->m_partm, kNormGrid, h->m_mhat, s, pnorm2(h), batch),
            "target tile");
-    PM_TRY(row(pm::ROW_INIT_MANY, rpe(nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
+    PM_TRY(row(rmode(h, pm::ROW_INIT_MANY), rpe(nullptr), h->nwg_row, s, nullptr, nullptr), "row init");
     const int col_mode = hist ? pm::COL_ITER_MANY : pm::COL_ITER_NE_MANY;
     const int row_mode = hist ? pm::ROW_ITER_MANY : pm::ROW_ITER_NE_MANY;
     const int last_mode = hist ? pm::ROW_LAST_FWD_MANY : pm::ROW_LAST_NE_MANY;
     for (int nu = 0; nu < n_iter; ++nu) {
         PM_TRY(col(col_mode, cpe(pe(2 * nu)), h->nwg_col, s, nullptr, nullptr), "column pass");
         const int mode = nu < n_iter - 1 ? row_mode : last_mode;
-        PM_TRY(row(mode, rpe(pe(2 * nu + 1)), h->nwg_row, s, nullptr, nullptr), "row pass");
+        PM_TRY(row(rmode(h, mode), rpe(pe(2 * nu + 1)), h->nwg_row, s, nullptr, nullptr), "row pass");
     }
     if (hist) {
         PM_TRY(col(pm::COL_ERR_MANY, cpe(pe(2 * n_iter)), h->nwg_col, s, nullptr, nullptr), "column error");
         PM_TRY(pm::launch_finalize(h->m_part, h->stride, h->slots_col, h->slots_row, 1.0 / h->N, h->io, 0,
-                                   2 * n_iter + 1, s, 1, nullptr, batch, bstride),
+                                   2 * n_iter + 1, s, 1, pnorm2(h), batch, bstride),
                "finalize");
     }
     return PM_OK;
@@ -1216,7 +1215,6 @@ pm_status phasemask_solve_many(pm_handle h, int batch, const float* target_ampli
     if (misaligned(target_amplitude, 16)) return fail(PM_EINVAL, "target must be 16-byte aligned");
     if (misaligned(init_phase, 4) || misaligned(out_phase, 4) || misaligned(err_history, 8))
         return fail(PM_EINVAL, "misaligned array argument");
-    if (h->illum_on) return fail(PM_EUNSUPPORTED, "uniform batches use p = 1 (clear the illumination first)");
     const size_t nb = (size_t)h->N * batch * sizeof(float);
     const size_t hb = (2 * (size_t)n_iter + 1) * batch * sizeof(double);
     if (overlaps(out_phase, nb, target_amplitude, nb)) return fail(PM_EINVAL, "out_phase overlaps the target");

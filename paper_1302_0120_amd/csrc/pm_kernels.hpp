@@ -641,7 +641,8 @@ k_row(RowParams a) {
     if constexpr ((MODE & ROUT_FIELD) != 0) a.nat_out = a.io->field_out;
     if constexpr ((MODE & R_MANY) != 0) {
         // mask blockIdx.y of a uniform batch: its iterate, phases, partials
-        static_assert((MODE & (R_ILLUM | R_RAAR | R_STOREZ | RIN_NAT | ROUT_NAT | RIN_FIELD | ROUT_FIELD)) == 0,
+        // (the illumination p, when set, is the plan's and shared by the masks)
+        static_assert((MODE & (R_RAAR | R_STOREZ | RIN_NAT | ROUT_NAT | RIN_FIELD | ROUT_FIELD)) == 0,
                       "uniform batches: the phase-in, phase-out solve modes");
         const size_t mb = (size_t)blockIdx.y * a.H * W;
         a.X += mb;

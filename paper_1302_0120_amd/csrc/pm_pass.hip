@@ -53,6 +53,9 @@ hipError_t launch(void (*kern)(Params), int grid, int block, hipStream_t s, hipE
     X(ROW_INIT) X(ROW_ITER) X(ROW_LAST) X(ROW_LAST_FWD) X(ROW_GAP) X(ROW_ITER_NE) X(ROW_LAST_NE) \
     X(ROW_INIT_Z) X(ROW_RAAR) X(ROW_RAAR_LAST) X(ROW_RAAR_LAST_FWD) \
     X(ROW_LAST_FIELD) X(ROW_LAST_FIELD_FWD) X(ROW_LAST_FIELD_NE)
+// Row modes of uniform batches, each also built with R_ILLUM.
+#define PM_ROW_MANY_MODES(X) \
+    X(ROW_INIT_MANY) X(ROW_ITER_MANY) X(ROW_ITER_NE_MANY) X(ROW_LAST_MANY) X(ROW_LAST_FWD_MANY) X(ROW_LAST_NE_MANY)
 #define PM_ROW_CASE(M)                                                                         \
     case M: return launch(k_row<PM_L, M, G>, grid, block, s, ev0, ev1, p);                     \
     case M | R_ILLUM: return launch(k_row<PM_L, M | R_ILLUM, G>, grid, block, s, ev0, ev1, p);
@@ -69,12 +72,7 @@ hipError_t launch_rows(int mode, const RowParams& p, int grid, hipStream_t s, hi
         case ROW_INIT_FIELD: return launch(k_row<PM_L, ROW_INIT_FIELD, G>, grid, block, s, ev0, ev1, p);
         case ROW_COPY_FIELD: return launch(k_row<PM_L, ROW_COPY_FIELD, G>, grid, block, s, ev0, ev1, p);
         case ROW_COPY: return launch(k_row<PM_L, ROW_COPY, G>, grid, block, s, ev0, ev1, p);
-        case ROW_INIT_MANY: return launch(k_row<PM_L, ROW_INIT_MANY, G>, grid, block, s, ev0, ev1, p);
-        case ROW_ITER_MANY: return launch(k_row<PM_L, ROW_ITER_MANY, G>, grid, block, s, ev0, ev1, p);
-        case ROW_ITER_NE_MANY: return launch(k_row<PM_L, ROW_ITER_NE_MANY, G>, grid, block, s, ev0, ev1, p);
-        case ROW_LAST_MANY: return launch(k_row<PM_L, ROW_LAST_MANY, G>, grid, block, s, ev0, ev1, p);
-        case ROW_LAST_FWD_MANY: return launch(k_row<PM_L, ROW_LAST_FWD_MANY, G>, grid, block, s, ev0, ev1, p);
-        case ROW_LAST_NE_MANY: return launch(k_row<PM_L, ROW_LAST_NE_MANY, G>, grid, block, s, ev0, ev1, p);
+        PM_ROW_MANY_MODES(PM_ROW_CASE)
         default: return hipErrorInvalidValue;
     }
 }
@@ -82,6 +80,7 @@ hipError_t launch_rows(int mode, const RowParams& p, int grid, hipStream_t s, hi
 }  // namespace
 #undef PM_ROW_CASE
 #undef PM_ROW_SOLVE_MODES
+#undef PM_ROW_MANY_MODES
 
 // The row tile is p.H / grid rows: row_lines(PM_L), or row_lines_alt(PM_L)
 // where the length has one.
