@@ -164,6 +164,9 @@ pm_status phasemask_set_illumination(pm_handle h, const float* illumination);
  *                     P_M u^nu; the final entry costs one extra transform).
  *                     Reductions are in FP64 and deterministic: repeating a
  *                     call gives bitwise identical results.
+ * The plan keeps 2 n_iter + 1 entries of FP64 partial sums for a history
+ * (grown on first use, which synchronises the stream and drops the captured
+ * graphs); a solve without a history writes none and grows nothing.
  * Errors: PM_EINVAL for a NULL array, n_iter < 0, or overlapping output and
  * target; PM_ENOMEM if the partial-sum buffer for n_iter cannot be grown;
  * PM_EDEVICE if a launch fails.
@@ -187,8 +190,9 @@ pm_status phasemask_solve(pm_handle h, const float* target_amplitude,
  * that mask alone (same kernels and summation order), also with the
  * illumination of phasemask_set_illumination, which every mask of the batch
  * shares.  The plan keeps the batch's iterates, rescaled targets and
- * partial sums (12 bytes per pixel and mask, plus partials), allocated on
- * first use for the largest batch and history seen, which synchronises the
+ * partial sums (12 bytes per pixel and mask, plus, with a history, 2 n_iter + 1
+ * entries of partials), allocated on first use for the
+ * largest batch and history seen, which synchronises the
  * stream and drops the captured graphs; without PM_FLAG_NO_GRAPH the solve
  * is one captured graph per (n_iter, batch, history).
  * Errors: PM_EINVAL for a NULL array, batch outside [1, 65535] or with

@@ -430,7 +430,9 @@ pm_status enqueue_solve(pm_plan* h, hipStream_t s, int n_iter, bool hist, int al
     const int lw = len_slot(h->W), lh = len_slot(h->H);
     const RowLauncher row = kRowLaunch[lw];
     const ColLauncher col = kColLaunch[lh];
-    auto pe = [&](int e) { return h->part + (size_t)e * h->stride; };
+    // Partials of history entry e; without a history the passes write none
+    // and the plan holds a single entry.
+    auto pe = [&](int e) { return hist ? h->part + (size_t)e * h->stride : h->part; };
     const bool field = algo == kAlgoGSField;
     // u^0: exp(i phi0) (times p), or the caller's field as given.
     const int init_mode = field ? pm::ROW_INIT_FIELD : rmode(h, pm::ROW_INIT);
@@ -503,7 +505,7 @@ pm_status enqueue_many(pm_plan* h, hipStream_t s, int n_iter, bool hist, int bat
     const RowLauncher row = kRowLaunch[len_slot(h->W)];
     const ColLauncher col = kColLaunch[len_slot(h->H)];
     const size_t bstride = h->many_entries * (size_t)h->stride;
-    auto pe = [&](int e) { return h->m_part + (size_t)e * h->stride; };
+    auto pe = [&](int e) { return hist ? h->m_part + (size_t)e * h->stride : h->m_part; };
     pm::RowParams rp = row_params(h, nullptr);
     rp.X = h->m_X;
     rp.nb = batch;
@@ -1149,7 +1151,7 @@ pm_status phasemask_solve(pm_handle h, const float* target_amplitude, const floa
     const bool hist = err_history != nullptr;
     if ((st = validate_input(h, target_amplitude, true, true, "target")) != PM_OK) return st;
     if ((st = validate_input(h, init_phase, false, false, "init_phase")) != PM_OK) return st;
-    st = ensure_partials(h, 2 * (size_t)n_iter + 1);
+    st = ensure_partials(h, hist ? 2 * (size_t)n_iter + 1 : 1);
     if (st != PM_OK) return st;
     pm::PmIo io{target_amplitude, init_phase, out_phase, err_history};
     PM_TRY(pm::launch_set_io(h->io, io, h->stream), "set io");
@@ -1224,7 +1226,7 @@ pm_status phasemask_solve_many(pm_handle h, int batch, const float* target_ampli
     const bool hist = err_history != nullptr;
     if ((st = validate_input(h, target_amplitude, true, false, "target", batch)) != PM_OK) return st;
     if ((st = validate_input(h, init_phase, false, false, "init_phase", batch)) != PM_OK) return st;
-    if ((st = ensure_many(h, batch, 2 * (size_t)n_iter + 1)) != PM_OK) return st;
+    if ((st = ensure_many(h, batch, hist ? 2 * (size_t)n_iter + 1 : 1)) != PM_OK) return st;
     pm::PmIo io{target_amplitude, init_phase, out_phase, err_history};
     PM_TRY(pm::launch_set_io(h->io, io, h->stream), "set io");
     if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_many(h, h->stream, n_iter, hist, batch);
@@ -1369,7 +1371,7 @@ pm_status phasemask_solve_field(pm_handle h, const float* target_amplitude, cons
         return fail(PM_EINVAL, "err_history overlaps a field");
     if ((st = validate_input(h, target_amplitude, true, true, "target")) != PM_OK) return st;
     if ((st = validate_input(h, (const float*)init_field, false, false, "init_field", 2)) != PM_OK) return st;
-    st = ensure_partials(h, 2 * (size_t)n_iter + 1);
+    st = ensure_partials(h, hist ? 2 * (size_t)n_iter + 1 : 1);
     if (st != PM_OK) return st;
     pm::PmIo io{target_amplitude, nullptr, nullptr, err_history, (const float2*)init_field, (float2*)out_field};
     PM_TRY(pm::launch_set_io(h->io, io, h->stream), "set io");
@@ -1394,7 +1396,7 @@ pm_status phasemask_solve_raar(pm_handle h, const float* target_amplitude, const
         return fail(PM_EINVAL, "err_history overlaps the target");
     if ((st = validate_input(h, target_amplitude, true, true, "target")) != PM_OK) return st;
     if ((st = validate_input(h, init_phase, false, false, "init_phase")) != PM_OK) return st;
-    st = ensure_partials(h, 2 * (size_t)n_iter + 1);
+    st = ensure_partials(h, hist ? 2 * (size_t)n_iter + 1 : 1);
     if (st != PM_OK) return st;
     if (h->Z == nullptr) {
         hipError_t e = hipStreamSynchronize(h->stream);

@@ -103,3 +103,40 @@ def test_destroyed_handle_is_refused(pmb):
     m = torch.ones((64, 64), dtype=torch.float32, device="cuda")
     out, _ = plan.solve(m, torch.zeros_like(m), 2)
     assert torch.isfinite(out).all()
+
+
+def test_solves_without_history_hold_no_partial_sums(pmb):
+    """Without a history the passes write no FP64 partial sums, so a long
+    solve leaves the plan's workspace as it was (one solve, RAAR, the field
+    solve and a uniform batch); with a history the partials grow to 2 n + 1
+    entries, and the results are the same either way."""
+    h = w = 64
+    rng = np.random.default_rng(5)
+    m = torch.from_numpy(synth.spot_amplitude(h, w, 12, 2.0, 0.5, 1.0, rng)).cuda()
+    p = torch.from_numpy(synth.uniform_phase(h, w, rng)).cuda()
+    u0 = torch.exp(1j * p.double()).to(torch.complex64)
+    plan = pmb.PhaseMask(h, w)
+    # first uses allocate the first block of entries and RAAR's second iterate
+    plan.solve(m, p, 1)
+    plan.solve_raar(m, p, 1, 0.9)
+    plan.solve_field(m, u0, 1)
+    base = plan.workspace_bytes
+    n = 400  # 801 entries: more than the first block holds
+    out, none = plan.solve(m, p, n, history=False)
+    assert none is None
+    plan.solve_raar(m, p, n, 0.9, history=False)
+    plan.solve_field(m, u0, n, history=False)
+    assert plan.workspace_bytes == base
+    ref, hist = plan.solve(m, p, n)
+    assert torch.equal(out, ref)
+    assert plan.workspace_bytes > base
+    many = pmb.PhaseMask(h, w)
+    mb, pb = torch.stack([m, m * 0.5 + 0.1]), torch.stack([p, -p])
+    many.solve_many(mb, pb, 1, history=False)
+    base_many = many.workspace_bytes
+    outs, _ = many.solve_many(mb, pb, n, history=False)
+    assert many.workspace_bytes == base_many
+    refs, _ = many.solve_many(mb, pb, n)
+    assert torch.equal(outs, refs)
+    assert many.workspace_bytes > base_many
+    torch.cuda.synchronize()
