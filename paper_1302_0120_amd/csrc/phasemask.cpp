@@ -111,7 +111,10 @@ struct GraphEntry {
     hipGraphExec_t exec;
 };
 
-constexpr int kNormGrid = 64;          // work-groups of the target-norm partial pass
+// Work-groups of the target-norm partial pass: each thread then loads one or
+// two float4 of an 800 x 600 or 1024^2 target (with 64 work-groups, 8 or 16
+// in a row; the pass took 7.8 us at 800 x 600).
+constexpr int kNormGrid = 512;
 // Default cache budget of one group of masks in a batched solve (the
 // working sets of the masks whose iterations run together);
 // PHASEMASK_GROUP_MB overrides it, 0 = all masks in one group.  With

@@ -30,6 +30,7 @@ __device__ __forceinline__ void sq_partial(const float* x, int n, double* part, 
     const float4* x4 = reinterpret_cast<const float4*>(x);
     const int n4 = n / 4;
     double acc = 0.0;
+#pragma unroll 4
     for (int i = blockIdx.x * kAuxThreads + threadIdx.x; i < n4; i += gridDim.x * kAuxThreads) {
         const float4 q = x4[i];
         acc = fma((double)q.x, (double)q.x, acc);
@@ -85,8 +86,13 @@ k_target_tile(const PmIo* io, int H, int W, const double* part, int npart, float
     const size_t mb = (size_t)blockIdx.y * H * W;
     part += (size_t)blockIdx.y * npart;
     mhat += mb;
+    // this thread's four pixels, loaded while the partials are summed
+    const int w4 = W / 4;
+    const int i = blockIdx.x * kAuxThreads + threadIdx.x;
+    const bool in = i < H * w4;
+    const float4 m = in ? reinterpret_cast<const float4*>(io->target + mb)[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     double acc = 0.0;
-    for (int i = threadIdx.x; i < npart; i += kAuxThreads) acc += part[i];
+    for (int k = threadIdx.x; k < npart; k += kAuxThreads) acc += part[k];
     const double tot = block_sum<kAuxThreads>(acc, red);
     // p = 1: m / ||m||.  Illumination p: m ||p|| / (||m|| sqrt(N)), the
     // energy-matched target on the scale of unnormalised transforms.
@@ -99,12 +105,9 @@ k_target_tile(const PmIo* io, int H, int W, const double* part, int npart, float
     }
     __syncthreads();
     const double inv = inv_norm;
-    const int w4 = W / 4;
-    const int i = blockIdx.x * kAuxThreads + threadIdx.x;
-    if (i < H * w4) {
+    if (in) {
         const int y = i / w4;
         const int q = i - y * w4;
-        const float4 m = reinterpret_cast<const float4*>(io->target + mb)[i];
         float4 o;
         o.x = (float)((double)m.x * inv);
         o.y = (float)((double)m.y * inv);
