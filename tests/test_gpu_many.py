@@ -52,7 +52,7 @@ def test_many_equals_one_mask_solves(pmb, shape, count, n_iter):
             assert torch.equal(hist[b], href), (b, flags)
 
 
-@pytest.mark.parametrize("shape,count,n_iter", [((600, 800), 2, 5), ((256, 256), 3, 6)])
+@pytest.mark.parametrize("shape,count,n_iter", [((600, 800), 2, 5), ((256, 256), 3, 6), ((64, 128), 3, 0)])
 def test_many_illuminated_equals_one_mask_solves(pmb, shape, count, n_iter):
     """A shared Gaussian illumination p (Eq. 1): each mask of the batch is
     bitwise the one-mask solve with the same p; switching p off and on
@@ -63,14 +63,17 @@ def test_many_illuminated_equals_one_mask_solves(pmb, shape, count, n_iter):
     md, pd = torch.from_numpy(m).cuda(), torch.from_numpy(p).cuda()
     illum = torch.from_numpy(synth.gaussian_illumination(h, w, 0.4)).cuda()
     plan = pmb.PhaseMask(h, w)
-    plain, _ = plan.solve_many(md, pd, n_iter)
+    plain, plain_hist = plan.solve_many(md, pd, n_iter)
     plan.set_illumination(illum)
     out, hist = plan.solve_many(md, pd, n_iter)
     for b in range(count):
         ref, href = plan.solve(md[b], pd[b], n_iter)
         assert torch.equal(out[b], ref), b
         assert torch.equal(hist[b], href), b
-    assert not torch.equal(out, plain)
+    if n_iter > 0:
+        assert not torch.equal(out, plain)
+    else:
+        assert not torch.equal(hist, plain_hist)  # E_F^0 is relative to ||p||
     plan.set_illumination(None)
     again, _ = plan.solve_many(md, pd, n_iter)
     assert torch.equal(again, plain)
@@ -93,6 +96,13 @@ def test_many_illuminated_against_oracle(pmb):
         assert err <= 1e-5, (b, err)
         rel = np.abs(hist[b].cpu().numpy() - ref["history"]) / ref["history"]
         assert rel.max() <= 1e-5, (b, rel)
+    # no iteration: the phases come back wrapped, the history is E_F^0 with p
+    out0, hist0 = plan.solve_many(torch.from_numpy(m).cuda(), torch.from_numpy(p).cuda(), 0)
+    for b in range(3):
+        ref = gs.gs_solve(m[b], p[b], 0, p=pp)
+        assert abs(hist0[b, 0].item() - ref["history"][0]) / ref["history"][0] <= 1e-5, b
+        d = np.angle(np.exp(1j * (out0[b].cpu().numpy().astype(np.float64) - p[b])))
+        assert np.abs(d).max() <= 1e-6, b
 
 
 def test_many_against_oracle_and_grow_shrink(pmb):
