@@ -85,7 +85,8 @@ typedef enum {
  * n_x = width).  Allocates the plan's device workspace (the iterate, the
  * rescaled target, twiddle tables and reduction partials: about 12 bytes per
  * pixel, plus FP64 partial sums of N / 128 to N / 16 bytes (N = height x
- * width) per error-history entry, grown on demand) on the current device.
+ * width), at least 4 KiB, per error-history entry, grown on demand) on the
+ * current device.
  * `stream` is a hipStream_t (NULL = the null stream) used by every later
  * call until phasemask_set_stream changes it.
  * With the environment variable PHASEMASK_LOG set, the plan's transform
@@ -123,7 +124,8 @@ pm_status phasemask_set_stream(pm_handle h, void* stream);
  * are relative to ||p|| with the target energy-matched to ||p||:
  *     E_F = || |F u| - m ||p|| / ||m|| || / ||p||,
  *     G   = || |P_M u| - p || / ||p||.
- * Applies to phasemask_solve, phasemask_solve_field (whose P_S then gives
+ * Applies to phasemask_solve, phasemask_solve_many (one p for every mask
+ * of the batch), phasemask_solve_field (whose P_S then gives
  * modulus p; its init_field is taken as given), phasemask_solve_raar,
  * phasemask_error, phasemask_physical_error (whose field is
  * u = p exp(i phase)) and phasemask_time_passes until changed; the output phase is that of the
