@@ -121,6 +121,23 @@ def test_one_iteration_parity_literal(pmb, shape):
     assert rel_h.max() <= 1e-5, rel_h
 
 
+def test_one_iteration_large_phases(pmb):
+    """Initial phases are any real numbers (radians): phases spread over
+    [-1e4, 1e4] with a few pixels at +-3e5 and 1e6 take the full range
+    reduction of exp(i phi); one iteration against the oracle (which forms
+    exp(i phi) of the same float32 values in float64), literal 1e-5."""
+    h, w = 256, 256
+    print("one iteration 256x256, phases up to 1e6 rad", flush=True)
+    rng = np.random.default_rng(9)
+    m = synth.spot_amplitude(h, w, 40, 2.0, 0.5, 1.0, rng)
+    phi0 = rng.uniform(-1e4, 1e4, size=(h, w)).astype(np.float32)
+    phi0[0, :4] = np.float32([3e5, -3e5, 1e6, -1e6])
+    err, rel_h = _one_iteration_case(pmb, h, w, m, phi0)
+    print(f"large phases: err {err:.3e}, history rel {rel_h.max():.3e}", flush=True)
+    assert err <= 1e-5, err
+    assert rel_h.max() <= 1e-5, rel_h
+
+
 def test_one_iteration_parity_4096(pmb):
     h = w = 4096
     print("one iteration 4096x4096", flush=True)
