@@ -126,6 +126,9 @@ constexpr size_t kBatchGroupBytes = (size_t)48 << 20;
 // Default number of concurrent chains the groups are spread over
 // (PHASEMASK_CHAINS overrides, 1..8).
 constexpr int kBatchChains = 4;
+// Concurrent chains of launches in an Adam solve of several samples (one
+// group of samples per chain).
+constexpr int kAdamChains = 2;
 constexpr size_t kMaxCachedGraphs = 8;
 
 // Iterations per schedule the batched tuner times (groups on chains, as a
@@ -183,6 +186,7 @@ struct pm_plan {
     // first use: the transform buffer, working phase, moments (natural
     // layout) and the strip-tiled intensity.
     int adam_cap = 0;
+    int adam_chains = 0;               // concurrent chains of an Adam solve (0: not chosen yet)
     float2* a_saved = nullptr;
     float* a_phase = nullptr;
     float* a_m = nullptr;
@@ -1685,21 +1689,49 @@ pm_status enqueue_adam(pm_plan* h, hipStream_t s, const SolveKey& k) {
     p.eps = (float)k.eps;
     const AdjRowLauncher row = kAdjRow[len_slot(h->W)];
     const AdjColLauncher col = kAdjCol[len_slot(h->H)];
-    if (n > 0 || k.hist) PM_TRY(row(pm::ROW_INIT, p, batch, s), "Adam row init");
-    for (int step = 1; step <= n; ++step) {
-        p.part_row0 = k.hist ? (step - 1) * batch : 0;
-        PM_TRY(col(pm::COL_LOSS_T, p, batch, s), "Adam loss column pass");
-        // bias corrections of step k (evaluated in double, rounded once)
-        p.adam_step = (float)(k.lr / (1.0 - std::pow(k.beta1, (double)step)));
-        p.adam_bc2s = (float)std::sqrt(1.0 - std::pow(k.beta2, (double)step));
-        const int mode = (step < n || k.hist) ? pm::ROW_ADAM : pm::ROW_ADAM_LAST;
-        PM_TRY(row(mode, p, batch, s), "Adam row pass");
+    // The samples are independent: contiguous groups of them run their steps
+    // on concurrent chains (the solve's stream and side streams forked from
+    // it), so that one chain's kernel boundaries overlap another's passes.
+    // Each sample keeps its own buffers and partial rows, so the results do
+    // not depend on the grouping.
+    const int chains = std::min(h->adam_chains, batch);
+    for (int c = 1; c < chains; ++c) {
+        PM_TRY(hipEventRecord(h->fork_ev[c - 1], s), "hipEventRecord(fork)");
+        PM_TRY(hipStreamWaitEvent(h->side[c - 1], h->fork_ev[c - 1], 0), "hipStreamWaitEvent(fork)");
     }
-    if (k.hist) {
-        p.part_row0 = n * batch;
-        PM_TRY(col(pm::COL_LOSS_ONLY_T, p, batch, s), "Adam final loss");
+    for (int c = 0; c < chains; ++c) {
+        const int b0 = (int)((long)batch * c / chains);
+        const int gb = (int)((long)batch * (c + 1) / chains) - b0;
+        hipStream_t cs = c == 0 ? s : h->side[c - 1];
+        pm::AdjParams q = p;
+        const size_t off = (size_t)b0 * h->N;
+        q.saved += off;
+        q.phase += off;
+        q.grad += off;
+        q.inten += off;
+        q.am += off;
+        q.av += off;
+        if (n > 0 || k.hist) PM_TRY(row(pm::ROW_INIT, q, gb, cs), "Adam row init");
+        for (int step = 1; step <= n; ++step) {
+            q.part_row0 = (k.hist ? (step - 1) * batch : 0) + b0;
+            PM_TRY(col(pm::COL_LOSS_T, q, gb, cs), "Adam loss column pass");
+            // bias corrections of step k (evaluated in double, rounded once)
+            q.adam_step = (float)(k.lr / (1.0 - std::pow(k.beta1, (double)step)));
+            q.adam_bc2s = (float)std::sqrt(1.0 - std::pow(k.beta2, (double)step));
+            const int mode = (step < n || k.hist) ? pm::ROW_ADAM : pm::ROW_ADAM_LAST;
+            PM_TRY(row(mode, q, gb, cs), "Adam row pass");
+        }
+        if (k.hist) {
+            q.part_row0 = n * batch + b0;
+            PM_TRY(col(pm::COL_LOSS_ONLY_T, q, gb, cs), "Adam final loss");
+        }
+    }
+    for (int c = 1; c < chains; ++c) {
+        PM_TRY(hipEventRecord(h->join_ev[c - 1], h->side[c - 1]), "hipEventRecord(join)");
+        PM_TRY(hipStreamWaitEvent(s, h->join_ev[c - 1], 0), "hipStreamWaitEvent(join)");
+    }
+    if (k.hist)
         PM_TRY(pm::launch_sum_rows_io(h->part, h->slots_adj, h->io, (n + 1) * batch, s), "Adam loss sums");
-    }
     PM_TRY(pm::launch_adam_out(h->io, h->a_phase, (size_t)batch * h->N, s), "Adam output");
     return PM_OK;
 }
@@ -1727,6 +1759,17 @@ pm_status phasemask_solve_adam(pm_handle h, int batch, const float* target_inten
     if (loss_history && (overlaps(loss_history, hb, target_intensity, nb) || overlaps(loss_history, hb, out_phase, nb) ||
                          overlaps(loss_history, hb, init_phase, nb)))
         return fail(PM_EINVAL, "loss_history overlaps an array");
+    // concurrent chains (PHASEMASK_ADAM_CHAINS=<1..8>, default kAdamChains),
+    // chosen at the handle's first Adam solve
+    int chains = h->adam_chains;
+    if (chains == 0) {
+        chains = kAdamChains;
+        if (const char* c = std::getenv("PHASEMASK_ADAM_CHAINS"); c != nullptr && c[0] != '\0') {
+            const long v = std::atol(c);
+            if (v < 1 || v > 8) return fail(PM_EINVAL, "PHASEMASK_ADAM_CHAINS out of range");
+            chains = (int)v;
+        }
+    }
     if (h->adam_cap < batch) {
         hipError_t e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
@@ -1760,6 +1803,26 @@ pm_status phasemask_solve_adam(pm_handle h, int batch, const float* target_inten
         h->a_inten = it;
         h->ws_bytes += n * (sizeof(float2) + 4 * sizeof(float)) - old;
         h->adam_cap = batch;
+    }
+    if (h->adam_chains == 0) {
+        // a side stream with its fork and join events per chain after the first
+        for (int c = (int)h->side.size() + 1; c < chains; ++c) {
+            hipStream_t x = nullptr;
+            hipEvent_t f = nullptr, j = nullptr;
+            hipError_t e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&f, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                if (x) (void)hipStreamDestroy(x);
+                if (f) (void)hipEventDestroy(f);
+                if (j) (void)hipEventDestroy(j);
+                return fail_hip(e, "side stream of an Adam chain");
+            }
+            h->side.push_back(x);
+            h->fork_ev.push_back(f);
+            h->join_ev.push_back(j);
+        }
+        h->adam_chains = chains;
     }
     const bool hist = loss_history != nullptr;
     const size_t rows = hist ? ((size_t)n_steps + 1) * batch : (size_t)batch;

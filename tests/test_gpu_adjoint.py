@@ -232,6 +232,33 @@ def test_adam_solve_matches_torch_adam_step_and_graph(pmb):
     assert same.data_ptr() == buf.data_ptr() and torch.equal(buf, a)
 
 
+@pytest.mark.parametrize("chains", ["1", "4"])
+def test_adam_chains_do_not_change_results(pmb, monkeypatch, chains):
+    """The samples of an Adam solve run in groups on concurrent chains of
+    launches; the phases and losses are bitwise those of the default two
+    chains with one chain or four (5 samples: uneven groups)."""
+    batch, n, lr = 5, 64, 0.05
+    it, ph = _targets(batch, n, 140)
+    it_d, ph_d = torch.from_numpy(it).cuda(), torch.from_numpy(ph).cuda()
+    ref_plan = pmb.PhaseMask(n, n)
+    ref, href = ref_plan.solve_adam(it_d, ph_d, 6, lr)
+    monkeypatch.setenv("PHASEMASK_ADAM_CHAINS", chains)
+    plan = pmb.PhaseMask(n, n)
+    out, hist = plan.solve_adam(it_d, ph_d, 6, lr)
+    assert torch.equal(out, ref) and torch.equal(hist, href)
+    eager = pmb.PhaseMask(n, n, flags=pmb.PM_FLAG_NO_GRAPH)
+    out_e, hist_e = eager.solve_adam(it_d, ph_d, 6, lr)
+    assert torch.equal(out_e, ref) and torch.equal(hist_e, href)
+
+
+def test_adam_chains_out_of_range(pmb, monkeypatch):
+    monkeypatch.setenv("PHASEMASK_ADAM_CHAINS", "9")
+    it, ph = _targets(2, 64, 150)
+    plan = pmb.PhaseMask(64, 64)
+    with pytest.raises(pmb.PhaseMaskError):
+        plan.solve_adam(torch.from_numpy(it).cuda(), torch.from_numpy(ph).cuda(), 2, 0.05)
+
+
 def test_adam_solve_workload_16x512(pmb):
     """The 16 x 512^2 intensity workload, 200 Adam steps in one call: finite,
     the loss falls for every sample, and the first history row is the loss
