@@ -100,9 +100,12 @@ struct SolveKey {
     float beta = 0.0f;   // RAAR relaxation
     int batch = 0;       // Adam: samples
     double lr = 0.0, beta1 = 0.0, beta2 = 0.0, eps = 0.0;  // Adam
+    int chain = -1;      // Adam: the steps of chain `chain` of `chains` only (-1: the whole solve)
+    int chains = 1;
     bool operator==(const SolveKey& o) const {
         return n_iter == o.n_iter && hist == o.hist && algo == o.algo && beta == o.beta && batch == o.batch &&
-               lr == o.lr && beta1 == o.beta1 && beta2 == o.beta2 && eps == o.eps;
+               lr == o.lr && beta1 == o.beta1 && beta2 == o.beta2 && eps == o.eps && chain == o.chain &&
+               chains == o.chains;
     }
 };
 
@@ -561,21 +564,24 @@ pm_status enqueue_many(pm_plan* h, hipStream_t s, int n_iter, bool hist, int bat
 
 pm_status enqueue_batch(pm_plan* h, hipStream_t s, int n_iter, bool err);
 pm_status enqueue_adam(pm_plan* h, hipStream_t s, const SolveKey& k);
+pm_status enqueue_adam_chain(pm_plan* h, hipStream_t s, const SolveKey& k);
 
 // The whole sequence of one solve, as the key describes it.
 pm_status enqueue_key(pm_plan* h, hipStream_t s, const SolveKey& k) {
     if (h->batched) return enqueue_batch(h, s, k.n_iter, k.hist);
-    if (k.algo == kAlgoAdam) return enqueue_adam(h, s, k);
+    if (k.algo == kAlgoAdam) return k.chain >= 0 ? enqueue_adam_chain(h, s, k) : enqueue_adam(h, s, k);
     if (k.algo == kAlgoMany) return enqueue_many(h, s, k.n_iter, k.hist, k.batch);
     return enqueue_solve(h, s, k.n_iter, k.hist, k.algo, k.beta);
 }
 
-// Replays (capturing on first use) the graph of one solve shape.
-pm_status launch_graph(pm_plan* h, const SolveKey& key) {
+// Replays (capturing on first use) the graph of one solve shape, on the
+// handle's stream or on `stream`.
+pm_status launch_graph(pm_plan* h, const SolveKey& key, hipStream_t stream = nullptr) {
+    hipStream_t ls = stream != nullptr ? stream : h->stream;
     for (auto it = h->graphs.begin(); it != h->graphs.end(); ++it) {
         if (it->key == key) {
             h->graphs.splice(h->graphs.begin(), h->graphs, it);
-            PM_TRY(hipGraphLaunch(it->exec, h->stream), "hipGraphLaunch");
+            PM_TRY(hipGraphLaunch(it->exec, ls), "hipGraphLaunch");
             return PM_OK;
         }
     }
@@ -597,7 +603,7 @@ pm_status launch_graph(pm_plan* h, const SolveKey& key) {
         h->graphs.pop_back();
     }
     h->graphs.push_front(GraphEntry{key, exec});
-    PM_TRY(hipGraphLaunch(exec, h->stream), "hipGraphLaunch");
+    PM_TRY(hipGraphLaunch(exec, ls), "hipGraphLaunch");
     return PM_OK;
 }
 
@@ -1667,10 +1673,7 @@ pm_status phasemask_intensity_loss_bwd(pm_handle h, int batch, const float* phas
 // of phi^n and the fixed-order sums; finally the phase to the caller.
 namespace {
 
-pm_status enqueue_adam(pm_plan* h, hipStream_t s, const SolveKey& k) {
-    const int batch = k.batch, n = k.n_iter;
-    PM_TRY(pm::launch_adam_prep(h->io, h->H, h->W, batch, h->a_phase, h->a_inten, h->a_m, h->a_v, s),
-           "Adam set-up");
+pm::AdjParams adam_params(pm_plan* h, const SolveKey& k) {
     pm::AdjParams p{};
     p.saved = h->a_saved;
     p.phase = h->a_phase;
@@ -1687,44 +1690,68 @@ pm_status enqueue_adam(pm_plan* h, hipStream_t s, const SolveKey& k) {
     p.beta1 = (float)k.beta1;
     p.beta2 = (float)k.beta2;
     p.eps = (float)k.eps;
+    return p;
+}
+
+// The samples are independent: contiguous groups of them run their steps
+// on concurrent chains, so that one chain's kernel boundaries overlap
+// another's passes.  Each sample keeps its own buffers and partial rows, so
+// the results do not depend on the grouping.  This is chain k.chain of
+// k.chains: the row transform of exp(i phi^0), the steps and (with a
+// history) the loss of phi^n of its samples, all on stream s.
+pm_status enqueue_adam_chain(pm_plan* h, hipStream_t s, const SolveKey& k) {
+    const int batch = k.batch, n = k.n_iter, c = k.chain;
+    const int b0 = (int)((long)batch * c / k.chains);
+    const int gb = (int)((long)batch * (c + 1) / k.chains) - b0;
+    if (gb == 0) return PM_OK;
+    pm::AdjParams q = adam_params(h, k);
+    const size_t off = (size_t)b0 * h->N;
+    q.saved += off;
+    q.phase += off;
+    q.grad += off;
+    q.inten += off;
+    q.am += off;
+    q.av += off;
     const AdjRowLauncher row = kAdjRow[len_slot(h->W)];
     const AdjColLauncher col = kAdjCol[len_slot(h->H)];
-    // The samples are independent: contiguous groups of them run their steps
-    // on concurrent chains (the solve's stream and side streams forked from
-    // it), so that one chain's kernel boundaries overlap another's passes.
-    // Each sample keeps its own buffers and partial rows, so the results do
-    // not depend on the grouping.
+    if (n > 0 || k.hist) PM_TRY(row(pm::ROW_INIT, q, gb, s), "Adam row init");
+    for (int step = 1; step <= n; ++step) {
+        q.part_row0 = (k.hist ? (step - 1) * batch : 0) + b0;
+        PM_TRY(col(pm::COL_LOSS_T, q, gb, s), "Adam loss column pass");
+        // bias corrections of step k (evaluated in double, rounded once)
+        q.adam_step = (float)(k.lr / (1.0 - std::pow(k.beta1, (double)step)));
+        q.adam_bc2s = (float)std::sqrt(1.0 - std::pow(k.beta2, (double)step));
+        const int mode = (step < n || k.hist) ? pm::ROW_ADAM : pm::ROW_ADAM_LAST;
+        PM_TRY(row(mode, q, gb, s), "Adam row pass");
+    }
+    if (k.hist) {
+        q.part_row0 = n * batch + b0;
+        PM_TRY(col(pm::COL_LOSS_ONLY_T, q, gb, s), "Adam final loss");
+    }
+    return PM_OK;
+}
+
+// The whole Adam solve after the pointer block is set: set-up of all
+// samples on s, the chains (chain 0 on s, the others on side streams forked
+// from s and joined back; each a captured graph of its own unless
+// PM_FLAG_NO_GRAPH, so that every graph stays a single chain of kernels),
+// then the fixed-order loss sums and the phases to the caller.
+pm_status enqueue_adam(pm_plan* h, hipStream_t s, const SolveKey& k, bool graphs) {
+    const int batch = k.batch, n = k.n_iter;
+    PM_TRY(pm::launch_adam_prep(h->io, h->H, h->W, batch, h->a_phase, h->a_inten, h->a_m, h->a_v, s),
+           "Adam set-up");
     const int chains = std::min(h->adam_chains, batch);
     for (int c = 1; c < chains; ++c) {
         PM_TRY(hipEventRecord(h->fork_ev[c - 1], s), "hipEventRecord(fork)");
         PM_TRY(hipStreamWaitEvent(h->side[c - 1], h->fork_ev[c - 1], 0), "hipStreamWaitEvent(fork)");
     }
     for (int c = 0; c < chains; ++c) {
-        const int b0 = (int)((long)batch * c / chains);
-        const int gb = (int)((long)batch * (c + 1) / chains) - b0;
+        SolveKey kc = k;
+        kc.chain = c;
+        kc.chains = chains;
         hipStream_t cs = c == 0 ? s : h->side[c - 1];
-        pm::AdjParams q = p;
-        const size_t off = (size_t)b0 * h->N;
-        q.saved += off;
-        q.phase += off;
-        q.grad += off;
-        q.inten += off;
-        q.am += off;
-        q.av += off;
-        if (n > 0 || k.hist) PM_TRY(row(pm::ROW_INIT, q, gb, cs), "Adam row init");
-        for (int step = 1; step <= n; ++step) {
-            q.part_row0 = (k.hist ? (step - 1) * batch : 0) + b0;
-            PM_TRY(col(pm::COL_LOSS_T, q, gb, cs), "Adam loss column pass");
-            // bias corrections of step k (evaluated in double, rounded once)
-            q.adam_step = (float)(k.lr / (1.0 - std::pow(k.beta1, (double)step)));
-            q.adam_bc2s = (float)std::sqrt(1.0 - std::pow(k.beta2, (double)step));
-            const int mode = (step < n || k.hist) ? pm::ROW_ADAM : pm::ROW_ADAM_LAST;
-            PM_TRY(row(mode, q, gb, cs), "Adam row pass");
-        }
-        if (k.hist) {
-            q.part_row0 = n * batch + b0;
-            PM_TRY(col(pm::COL_LOSS_ONLY_T, q, gb, cs), "Adam final loss");
-        }
+        pm_status st = graphs ? launch_graph(h, kc, cs) : enqueue_adam_chain(h, cs, kc);
+        if (st != PM_OK) return st;
     }
     for (int c = 1; c < chains; ++c) {
         PM_TRY(hipEventRecord(h->join_ev[c - 1], h->side[c - 1]), "hipEventRecord(join)");
@@ -1735,6 +1762,8 @@ pm_status enqueue_adam(pm_plan* h, hipStream_t s, const SolveKey& k) {
     PM_TRY(pm::launch_adam_out(h->io, h->a_phase, (size_t)batch * h->N, s), "Adam output");
     return PM_OK;
 }
+
+pm_status enqueue_adam(pm_plan* h, hipStream_t s, const SolveKey& k) { return enqueue_adam(h, s, k, false); }
 
 }  // namespace
 
@@ -1839,8 +1868,7 @@ pm_status phasemask_solve_adam(pm_handle h, int batch, const float* target_inten
     k.beta1 = beta1;
     k.beta2 = beta2;
     k.eps = eps;
-    if (h->flags & PM_FLAG_NO_GRAPH) return enqueue_adam(h, h->stream, k);
-    return launch_graph(h, k);
+    return enqueue_adam(h, h->stream, k, (h->flags & PM_FLAG_NO_GRAPH) == 0);
 }
 
 pm_status phasemask_initial_phase(pm_handle h, const float* target_amplitude, double t_dark, float* out_phase) {
