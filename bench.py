@@ -38,7 +38,7 @@ ADAM_FUSED_BYTES_PER_PX = 20 + 40
 # valid only for the kernel sources it was taken on (hash below).
 KERNEL_SOURCES = ("pm_common.h", "pm_fft.hpp", "pm_kernels.hpp", "pm_pass.hip")
 TRAFFIC_SOURCE_HASH = "0d28a96a29195a3f"
-TRAFFIC_BYTES = {"row pass": 16947056, "column pass": 21131644}
+TRAFFIC_BYTES = {"row pass": 16947086, "column pass": 21131686}
 
 
 def kernel_source_hash() -> str:
@@ -493,7 +493,7 @@ def bench_adjoint(torch, binding, synth, lr, steps=200):
         "adam": {"steps": steps, "lr": lr, "ms_per_step": t_adam * 1e3 / steps,
                  "total_ms": t_adam * 1e3, "final_fourier_error_mean": ef_adam,
                  "final_loss_mean": float(loss_hist[-1].mean().item()),
-                 "launch": "phasemask_solve_adam: one graph, 2 fused passes per step, the samples on 2 concurrent chains",
+                 "launch": "phasemask_solve_adam: one graph, 2 fused passes per step",
                  "algorithmic_gbs": ADAM_FUSED_BYTES_PER_PX * batch * n * n / (t_adam / steps) / 1e9,
                  "torch_adam": {"graph_ms_per_step": t_torch_graph * 1e3 / steps,
                                 "eager_ms_per_step": t_torch_eager * 1e3 / steps,

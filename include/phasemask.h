@@ -462,11 +462,14 @@ pm_status phasemask_intensity_loss_bwd(pm_handle h, int batch, const float* phas
  * the captured graphs).  The illumination of phasemask_set_illumination does
  * not apply (the loss is that of exp(i phi)).  Without PM_FLAG_NO_GRAPH the
  * solve is one captured graph per (n_steps, batch, history, lr, beta1,
- * beta2, eps), like phasemask_solve.  The samples run in contiguous groups
- * on 2 concurrent chains of launches (the handle's stream and a side stream
- * forked from it and joined back; PHASEMASK_ADAM_CHAINS=<1..8>, read at the
- * handle's first Adam solve, sets the number); the results do not depend on
- * it.
+ * beta2, eps), like phasemask_solve.  PHASEMASK_ADAM_CHAINS=<1..8> (read at
+ * the handle's first Adam solve; default 1) runs the samples in contiguous
+ * groups on that many concurrent chains of launches: the handle's stream
+ * and side streams forked from it and joined back, each chain its own
+ * captured graph.  The results do not depend on it; the speed does: two
+ * chains gain where each stream has a hardware queue of its own and lose
+ * where streams share them (more streams in the process than the runtime's
+ * hardware queues, GPU_MAX_HW_QUEUES).
  * Errors: PM_EINVAL for a NULL array, batch outside [1, 65535], n_steps < 0,
  * a hyper-parameter out of range, misalignment or overlapping arrays, or an
  * out-of-range PHASEMASK_ADAM_CHAINS; PM_ENOMEM; PM_EDEVICE.
