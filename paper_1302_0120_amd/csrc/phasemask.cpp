@@ -131,9 +131,9 @@ constexpr size_t kBatchGroupBytes = (size_t)48 << 20;
 constexpr int kBatchChains = 4;
 // Concurrent chains of launches in an Adam solve of several samples (one
 // group of samples per chain; PHASEMASK_ADAM_CHAINS).  One by default: two
-// chains took the 16 x 512^2 solve from 9.3 to 8.4 ms where each stream had
-// a hardware queue of its own, but from 9.7 to 10.9 ms in a process with
-// more streams than the runtime's hardware queues, whose streams share them.
+// chains took the 16 x 512^2 solve from 9.3 to 8.4 ms in a process holding
+// only the Adam plan, but from 9.7 to 10.9 ms after other plans had run
+// (streams sharing the runtime's few hardware queues serialise).
 constexpr int kAdamChains = 1;
 constexpr size_t kMaxCachedGraphs = 8;
 
