@@ -1738,9 +1738,12 @@ pm_status enqueue_adam_chain(pm_plan* h, hipStream_t s, const SolveKey& k) {
 // samples on s, the chains (chain 0 on s, the others on side streams forked
 // from s and joined back; each a captured graph of its own unless
 // PM_FLAG_NO_GRAPH, so that every graph stays a single chain of kernels),
-// then the fixed-order loss sums and the phases to the caller.
+// then the fixed-order loss sums and the phases to the caller.  With one
+// chain and graphs, all of it is one captured graph.
 pm_status enqueue_adam(pm_plan* h, hipStream_t s, const SolveKey& k, bool graphs) {
     const int batch = k.batch, n = k.n_iter;
+    // one chain: the whole solve is one graph
+    if (graphs && std::min(h->adam_chains, batch) == 1) return launch_graph(h, k, s);
     PM_TRY(pm::launch_adam_prep(h->io, h->H, h->W, batch, h->a_phase, h->a_inten, h->a_m, h->a_v, s),
            "Adam set-up");
     const int chains = std::min(h->adam_chains, batch);
