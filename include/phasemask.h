@@ -468,8 +468,9 @@ pm_status phasemask_intensity_loss_bwd(pm_handle h, int batch, const float* phas
  * and side streams forked from it and joined back, each chain its own
  * captured graph.  The results do not depend on it; the speed does: two
  * chains gained 10% in a process holding only the Adam plan and lost 12%
- * in one that had created and run other plans first (streams that share
- * one of the runtime's hardware queues serialise).
+ * in one that had created and run other plans first, where the chains'
+ * streams shared one of the runtime's hardware queues (GPU_MAX_HW_QUEUES,
+ * default 4; with 8 the two chains gained 11% there too).
  * Errors: PM_EINVAL for a NULL array, batch outside [1, 65535], n_steps < 0,
  * a hyper-parameter out of range, misalignment or overlapping arrays, or an
  * out-of-range PHASEMASK_ADAM_CHAINS; PM_ENOMEM; PM_EDEVICE.

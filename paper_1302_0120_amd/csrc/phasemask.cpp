@@ -132,8 +132,9 @@ constexpr int kBatchChains = 4;
 // Concurrent chains of launches in an Adam solve of several samples (one
 // group of samples per chain; PHASEMASK_ADAM_CHAINS).  One by default: two
 // chains took the 16 x 512^2 solve from 9.3 to 8.4 ms in a process holding
-// only the Adam plan, but from 9.7 to 10.9 ms after other plans had run
-// (streams sharing the runtime's few hardware queues serialise).
+// only the Adam plan, but from 9.7 to 10.9 ms after other plans had run,
+// where the two chains' streams shared one of the runtime's four hardware
+// queues (with GPU_MAX_HW_QUEUES=8 they gained there too).
 constexpr int kAdamChains = 1;
 constexpr size_t kMaxCachedGraphs = 8;
 
